@@ -1,0 +1,159 @@
+"""Benchmark: JTFS forward + backward metamer iterations per second at N = 2^16.
+
+One step = one jtfs_metamer_step of the config-2 workload (N = 2^16 samples, J = 12,
+Q1 = 12, Q2 = 2, J_fr = 4, Q_fr = 2, T = 2^13, F = 24 bins; Adam, lr 0.1): forward
+transform, loss, exact backward and update, with the signal and target resident on
+the GPU. Prints one JSON line (see the README of this repository for the fields).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "JTFS fwd+bwd iters/s at N=2^16; time to rel loss 1e-2, plain vs learned init"
+CFG2 = dict(n=65536, J=12, Q1=12, Q2=2, J_fr=4, Q_fr=2, log2_T=13, F=24.0)
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def cpu_baseline() -> dict:
+    """The FP64 oracle timed on this host on a bounded sample of the config-2 iteration.
+
+    An oracle forward + backward of config 2 takes minutes, so it is timed in parts:
+    the first layer and order-1 paths (forward and adjoint) exactly, and the second-order
+    groups through one sampled group (n2 with j2 = 3). Every second-order group does
+    the same work per time sample (a frequential DFT of N_fr points and the filters of
+    the frequential list per column), so a group's cost is taken as proportional to its
+    length L2 and the sampled group's cost per sample is applied to all groups.
+    """
+    import numpy as np
+
+    import jtfs_inputs as ji
+    from oracle import fftroute
+    from oracle.plan import make_plan
+
+    op = make_plan(CFG2["n"], CFG2["J"], CFG2["Q1"], CFG2["Q2"], CFG2["J_fr"], CFG2["Q_fr"], CFG2["log2_T"],
+                   CFG2["F"])
+    y = ji.white_noise_like(ji.config2_signal(2), 3)
+    fc = fftroute.FilterCache(op)
+    sample = next(g for g in op.groups if g.j2 == 3)
+    blocks = [b for b in op.blocks if b.order == 2 and b.n2 == sample.n2]
+    dS_group = np.zeros(op.n_coeff)
+    for b in blocks:
+        dS_group[b.offset: b.offset + b.n_lambda * b.n_frames] = 1.0
+    dS_o1 = np.zeros(op.n_coeff)
+    for b in op.blocks:
+        if b.order == 1:
+            dS_o1[b.offset: b.offset + b.n_lambda * b.n_frames] = 1.0
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    fftroute.forward_partial(op, y, [], order1=False, fc=fc)          # fills the filter cache
+    t_fl = timed(lambda: fftroute.forward_partial(op, y, [], order1=False, fc=fc))
+    t_fl_o1 = timed(lambda: fftroute.forward_partial(op, y, [], order1=True, fc=fc))
+    t_fl_g = timed(lambda: fftroute.forward_partial(op, y, [sample.n2], order1=False, fc=fc))
+    t_b_o1 = timed(lambda: fftroute.backward(op, y, dS_o1, fc=fc))
+    t_b_g = timed(lambda: fftroute.backward(op, y, dS_group + dS_o1, fc=fc))
+    t_g = max(t_fl_g - t_fl, 0.0) + max(t_b_g - t_b_o1, 0.0)
+    per_sample = t_g / (op.N_pad >> sample.j2)
+    groups_total = sum(per_sample * (op.N_pad >> g.j2) for g in op.groups)
+    total = t_fl_o1 + t_b_o1 + groups_total
+    spent = t_fl + t_fl_o1 + t_fl_g + t_b_o1 + t_b_g
+    return {"value": 1.0 / total, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": (f"config 2, FP64 NumPy oracle on one thread: first layer + order-1 paths timed in full "
+                       f"(fwd {t_fl_o1:.2f} s, bwd {t_b_o1:.2f} s), second-order group n2={sample.n2} "
+                       f"(j2=3, {sample.K} rows) timed fwd+bwd ({t_g:.2f} s) and extrapolated to all "
+                       f"{len(op.groups)} groups in proportion to their length: {total:.1f} s per iteration; "
+                       f"{spent:.1f} s of CPU work measured")}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import jtfs_inputs as ji
+    import paper_2602_11896_amd as J
+
+    dev = torch.device("cuda:0")
+    plan = J.Plan(J.Params(**CFG2))
+    x = torch.as_tensor(ji.config2_signal(2), dtype=torch.float32, device=dev)
+    y0 = torch.as_tensor(ji.white_noise_like(ji.config2_signal(2), 3), dtype=torch.float32, device=dev)
+    ws = plan.workspace(dev)
+    S_t = plan.forward(x, ws=ws).clone()
+    y = y0.clone()
+    opt = J.Optimizer(plan, "adam", lr=0.1, device=dev)
+    loss = torch.zeros(1, device=dev)
+    for _ in range(args.warmup):
+        plan.metamer_step(y, S_t, opt, loss, ws)
+    torch.cuda.synchronize()
+
+    plan.timing(True)
+    plan.timing_read()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        plan.metamer_step(y, S_t, opt, loss, ws)
+    stop.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    stages = plan.timing_read()
+    plan.timing(False)
+    ms_per_step = total_ms / args.steps
+    value = 1000.0 / ms_per_step
+
+    cost = plan.cost()
+    fwd_ms, fwd_n = stages.get("freq_fwd", (0.0, 0))
+    bwd_ms, bwd_n = stages.get("freq_bwd", (0.0, 0))
+    # Dominant kernel: the one with the larger total time.
+    if bwd_ms >= fwd_ms:
+        name, t_ms, n = "freq_bwd", bwd_ms / max(bwd_n, 1), bwd_n
+        flops = 2 * 8.0 * cost["mac_banded"] + 2.0 * cost["mac_pool"]
+    else:
+        name, t_ms, n = "freq_fwd", fwd_ms / max(fwd_n, 1), fwd_n
+        flops = 8.0 * cost["mac_banded"] + 2.0 * cost["mac_pool"]
+    achieved = flops / (t_ms * 1e-3) / 1e12
+    roofline = {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": round(t_ms, 4), "launches": n}
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "config 2: one metamer step (JTFS forward, loss, exact backward, Adam) of one "
+                               "N=2^16 signal, J=12 Q1=12 Q2=2 J_fr=4 Q_fr=2 T=2^13 F=24",
+                   "global_batch": 1, "seq_len": 65536, "parallelism": "single GPU"},
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

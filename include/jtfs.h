@@ -1,0 +1,216 @@
+/*
+ * jtfs.h - C ABI of the MI355X joint time-frequency scattering (JTFS) library.
+ *
+ * The library computes the JTFS transform S of Lostanlen & Han, "Musical Metamerism
+ * with Time-Frequency Scattering" (Sec. 2.1-2.2, Eqs. 2-4; implementation Sec. 3),
+ * its exact gradient (Sec. 2.3, Eqs. 5-7) and one step of the metamer descent that
+ * drives E(y) = ||S(y) - S(x)||^2 towards zero (Sec. 2.3).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns jtfs_status; nothing throws or aborts across the ABI.
+ *    Argument errors are reported before any device work is enqueued. On an error,
+ *    jtfs_last_error() returns a thread-local description of the last failure.
+ *  - Pointers named x, y, S, dS, dx, S_target, loss, ws and the optimiser state are
+ *    DEVICE pointers (HIP global memory on the current device), owned by the caller.
+ *    Everything else is host memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream). Work is
+ *    enqueued asynchronously on it; outputs are valid once the stream has completed.
+ *  - All floating point data are IEEE binary32 (FP32), packed without strides.
+ *  - A plan is immutable after creation and may be shared by threads and streams as
+ *    long as every concurrent call has its own workspace.
+ */
+#ifndef JTFS_H
+#define JTFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct jtfs_plan_s* jtfs_plan_t;   /* opaque, owned by the library */
+typedef void* jtfs_stream_t;               /* a hipStream_t */
+
+typedef enum {
+  JTFS_OK = 0,
+  JTFS_ERR_ARG = 1,          /* invalid argument (null pointer, bad size, bad parameter) */
+  JTFS_ERR_NOMEM = 2,        /* host or device allocation of plan tables failed */
+  JTFS_ERR_HIP = 3,          /* a HIP runtime call or kernel launch failed */
+  JTFS_ERR_WORKSPACE = 4,    /* ws_bytes smaller than the plan requires */
+  JTFS_ERR_UNSUPPORTED = 5   /* parameters outside what the kernels implement */
+} jtfs_status;
+
+/*
+ * Parameters of one signal (Sec. 3.1 and Sec. 2.2). Sample rate is 1.
+ *  n       number of samples N of x (Sec. 2.1).
+ *  J, Q1   first-order wavelet bank: scale 2^J and Q1 wavelets per octave (Sec. 3.1).
+ *  Q2      second-order temporal bank, same J (Sec. 3.1, last paragraph).
+ *  J_fr, Q_fr  frequential bank along log-frequency (Sec. 3.1, last paragraph).
+ *  log2_T  time averaging scale T = 2^log2_T samples (Sec. 2.2, Eqs. 3-4).
+ *  F       frequential averaging scale in first-order filter bins (Sec. 2.2); the
+ *          frequential subsampling is 2^floor(log2 F).
+ *  periodic 0: zero-pad to 2^(ceil(log2 n)+1) samples, n split evenly on both sides
+ *          (Sec. 3.2 pads both sides); 1: no padding, n must be a power of two.
+ */
+typedef struct {
+  int64_t n;
+  int32_t J, Q1, Q2, J_fr, Q_fr, log2_T;
+  double F;
+  int32_t periodic;
+} jtfs_params;
+
+/*
+ * One block of the output (the paths of Sec. 2.1 after averaging, Eqs. 3-4).
+ * order 1: n2 = j2 = -1, the alpha = 0 paths; order 2: second-order filter n2 with scale j2.
+ * n_fr indexes the frequential list [phi_F, psi_fr(xi > 0)..., psi_fr(xi < 0)...];
+ * spin is 0 for phi_F, +1 / -1 for the two spins (Sec. 3.4). The block holds
+ * n_lambda x n_frames FP32 values, row-major (log-frequency bin, then frame), starting
+ * `offset` floats after the signal's first coefficient.
+ */
+typedef struct {
+  int32_t order, n2, n_fr, spin, j2, j_fr, n_lambda, n_frames;
+  int64_t offset;
+} jtfs_path;
+
+/* Sizes of a plan. Per-signal offsets come from jtfs_plan_offsets. */
+typedef struct {
+  int32_t batch;            /* number of signals */
+  int64_t n_samples_total;  /* sum of n over signals: length of x / y / dx */
+  int64_t n_coeff_total;    /* sum of coefficient counts: length of S / dS / S_target */
+  size_t  ws_forward;       /* workspace bytes for jtfs_forward */
+  size_t  ws_backward;      /* workspace bytes for jtfs_backward and jtfs_metamer_step */
+} jtfs_plan_info;
+
+/* Optimiser of the metamer descent (Sec. 2.3). */
+typedef enum {
+  JTFS_OPT_GD = 0,             /* y <- y - lr * grad */
+  JTFS_OPT_MOMENTUM_BOLD = 1,  /* y <- y + u, u <- momentum*u - mu*grad, bold-driver mu (Sec. 2.3) */
+  JTFS_OPT_ADAM = 2            /* Adam with bias correction */
+} jtfs_opt_kind;
+
+typedef struct {
+  int32_t kind;        /* jtfs_opt_kind */
+  float lr;            /* GD/Adam learning rate; initial mu for MOMENTUM_BOLD */
+  float momentum;      /* MOMENTUM_BOLD momentum m (paper: 0.9) */
+  float beta1, beta2, eps;  /* ADAM */
+  float bold_up, bold_down; /* MOMENTUM_BOLD learning-rate factors on accept / reject */
+  float* state;        /* device buffer of jtfs_opt_state_floats() floats, zeroed by the
+                          caller before the first step and left untouched in between */
+} jtfs_opt;
+
+/*
+ * jtfs_plan - build a plan for `batch` signals (host work only; device tables are
+ * uploaded on the first call that runs on a device). Filterbanks follow Sec. 3.1,
+ * subsampling rules Sec. 3.2-3.5, path order the main algorithm of Sec. 3.6.
+ * Returns JTFS_ERR_ARG for invalid parameters, JTFS_ERR_UNSUPPORTED for valid ones
+ * the kernels do not cover (e.g. a second-order resolution coarser than T).
+ * On success *out owns the plan; release it with jtfs_plan_destroy.
+ */
+jtfs_status jtfs_plan(const jtfs_params* sig, int32_t batch, jtfs_plan_t* out);
+
+/* Fill *info. */
+jtfs_status jtfs_plan_query(jtfs_plan_t plan, jtfs_plan_info* info);
+
+/* Per-signal offsets (in elements) into x and S: arrays of batch + 1 entries, the last
+ * entry being the total. Either pointer may be NULL. */
+jtfs_status jtfs_plan_offsets(jtfs_plan_t plan, int64_t* x_offsets, int64_t* s_offsets);
+
+/* Output layout of signal `signal`: at most `cap` rows written to `rows` (host), the
+ * number of blocks stored in *n_rows. rows may be NULL to query the count. */
+jtfs_status jtfs_plan_meta(jtfs_plan_t plan, int32_t signal, jtfs_path* rows, int64_t cap,
+                           int64_t* n_rows);
+
+/* Filterbank of signal `signal` (host arrays of at least `cap` entries, may be NULL):
+ * bank 0 = first-order wavelets, 1 = second-order wavelets, 2 = frequential list
+ * (phi_F first). xi, sigma in cycles per sample (or per log-frequency bin);
+ * j = subsampling scale; k = subsampling applied (k1 for bank 0, k_fr for bank 2,
+ * 0 for bank 1). The count is stored in *n. */
+jtfs_status jtfs_plan_filters(jtfs_plan_t plan, int32_t signal, int32_t bank, double* xi,
+                              double* sigma, int32_t* j, int32_t* k, int32_t cap, int32_t* n);
+
+/* Scalar sizes of signal `signal`: N_pad, pad_left, N_fr, s_F, nf_pad, f_lo, n_frames,
+ * n_coeff, in this order, into out[0..7]. */
+jtfs_status jtfs_plan_sizes(jtfs_plan_t plan, int32_t signal, int64_t* out8);
+
+/* Intermediate arrays left in the workspace by jtfs_forward, for inspection:
+ * which = 0: Z1 (complex, first-order scalogram before the modulus, row n1 of length
+ * N_pad / 2^k1, rows concatenated); 1: U1hat (complex, DFT of |Z1| per row, same
+ * shape); 2: S1 (real, N1 x nf_pad); 3: Y2 (complex, second-order stacks for every n2
+ * with pairs, K(n2) rows of N_pad / 2^j2 each, groups concatenated in n2 order).
+ * *offset_bytes and *count (elements) locate it inside ws. */
+jtfs_status jtfs_plan_ws_region(jtfs_plan_t plan, int32_t signal, int32_t which,
+                                int64_t* offset_bytes, int64_t* count);
+
+/* Work of the forward frequential stage of signal `signal` (Sec. 3.5, Eq. 4), for
+ * rooflines: out[0] complex multiply-adds of the dense contraction W Y2 over all
+ * second-order groups; out[1] the same counting only taps above 1e-7 of their filter's
+ * peak (the banded contraction); out[2] complex multiply-adds the kernel executes
+ * (16-row tiles, 4-column steps); out[3] real multiply-adds of the time pooling of
+ * the modulus over kept frames. */
+jtfs_status jtfs_plan_cost(jtfs_plan_t plan, int32_t signal, double* out4);
+
+/* Number of floats the optimiser state of `kind` needs for this plan. */
+int64_t jtfs_opt_state_floats(jtfs_plan_t plan, int32_t kind);
+
+/*
+ * jtfs_forward - S = S(x) for every signal of the plan (Eqs. 3-4 with the frequential
+ * scattering of Sec. 3.5). x: n_samples_total floats; S: n_coeff_total floats.
+ * ws: at least ws_forward bytes (ws_backward bytes if a jtfs_backward with
+ * JTFS_REUSE_FORWARD follows). Returns JTFS_ERR_WORKSPACE if ws_bytes is too small.
+ */
+jtfs_status jtfs_forward(jtfs_plan_t plan, const float* x, float* S, void* ws, size_t ws_bytes,
+                         jtfs_stream_t stream);
+
+/* Flags of jtfs_backward. */
+#define JTFS_REUSE_FORWARD 1u   /* ws still holds the intermediates of jtfs_forward(x) */
+
+/*
+ * jtfs_backward - dx = J_S(x)^T dS, the exact adjoint of jtfs_forward at x
+ * (Sec. 2.3, Eqs. 5-7, composed in reverse order; the modulus has subgradient 0 at 0).
+ * With dS = 2 (S(y) - S(x)) this is grad E. dS: n_coeff_total floats; dx:
+ * n_samples_total floats (overwritten). ws: at least ws_backward bytes. Without
+ * JTFS_REUSE_FORWARD the forward intermediates are recomputed from x first.
+ */
+jtfs_status jtfs_backward(jtfs_plan_t plan, const float* x, const float* dS, float* dx, void* ws,
+                          size_t ws_bytes, uint32_t flags, jtfs_stream_t stream);
+
+/*
+ * jtfs_metamer_step - one descent step of Sec. 2.3 for every signal: computes
+ * S(y), loss[s] = ||S(y) - S_target||^2 (per signal, before the update, device
+ * floats), grad E through jtfs_backward, and updates y in place with `opt`.
+ * If a signal's loss is not finite, its y is left unchanged, its momentum is cleared
+ * and the optimiser scalars are not advanced; this is decided on the device, so the
+ * call never waits for the stream and the caller sees the case in `loss`.
+ * Requires ws_backward bytes of workspace.
+ */
+jtfs_status jtfs_metamer_step(jtfs_plan_t plan, float* y, const float* S_target, const jtfs_opt* opt,
+                              float* loss, void* ws, size_t ws_bytes, jtfs_stream_t stream);
+
+/*
+ * Stage timing (for measurement). While enabled, every kernel stage enqueued by
+ * jtfs_forward / jtfs_backward / jtfs_metamer_step on this plan is bracketed by two HIP
+ * events on the same stream. jtfs_timing_read waits for the recorded events, writes
+ * per-stage totals (milliseconds, number of bracketed launches) for stage ids
+ * 0..cap-1 and clears them. Stage ids: 0 signal DFT, 1 first-order wavelets,
+ * 2 DFT of |Z1|, 3 first-order averaging, 4 order-1 frequential paths, 5 second-order
+ * wavelets, 6 frequential contraction + modulus + time pooling (forward), 7 phi_F pooling,
+ * 8 pooled-gradient rows, 9 frequential contraction (backward), 10 order-1 adjoint,
+ * 11 first-order averaging adjoint, 12 DFT of dY2, 13 second-order adjoint gather,
+ * 14 DFT of dZ1, 15 first-order adjoint gather, 16 loss, 17 update. Timing state is
+ * per plan and not thread-safe: use it from one thread.
+ */
+#define JTFS_N_STAGES 18
+jtfs_status jtfs_timing_enable(jtfs_plan_t plan, int32_t on);
+jtfs_status jtfs_timing_read(jtfs_plan_t plan, double* ms, int64_t* counts, int32_t cap);
+
+/* Release a plan and its device tables. NULL is ignored. */
+void jtfs_plan_destroy(jtfs_plan_t plan);
+
+const char* jtfs_status_str(jtfs_status s);
+const char* jtfs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JTFS_H */

@@ -179,6 +179,15 @@ def freq_filter(plan, Xh_fr, g, fc):
     return np.fft.ifft(fold(Xh_fr * fc.fr(g)[:, None], b.k, axis=0), axis=0)
 
 
+def first_layer_cache(plan: OraclePlan, x: np.ndarray, fc: FilterCache = None) -> dict:
+    """The intermediates ``backward`` needs (first layer and the transformed order-1 input)."""
+    fc = fc or FilterCache(plan)
+    Xh, Z1, U1h, S1 = first_layer(plan, x, fc)
+    A = np.zeros((plan.N_fr, plan.nf_pad), dtype=np.float64)
+    A[:plan.N1] = S1
+    return dict(Xh=Xh, Z1=Z1, U1h=U1h, S1=S1, Ah=np.fft.fft(A, axis=0), fc=fc)
+
+
 def forward(plan: OraclePlan, x: np.ndarray, fc: FilterCache = None, return_cache: bool = False):
     """S(x) as a flat FP64 vector in the plan's output layout."""
     fc = fc or FilterCache(plan)
@@ -222,11 +231,11 @@ def forward(plan: OraclePlan, x: np.ndarray, fc: FilterCache = None, return_cach
     return S
 
 
-def backward(plan: OraclePlan, x: np.ndarray, dS: np.ndarray, cache=None) -> np.ndarray:
+def backward(plan: OraclePlan, x: np.ndarray, dS: np.ndarray, cache=None, fc: FilterCache = None) -> np.ndarray:
     """dx = J_S(x)^T dS, the exact adjoint of ``forward``."""
     dS = np.asarray(dS, dtype=np.float64)
     if cache is None:
-        _, cache = forward(plan, x, return_cache=True)
+        cache = first_layer_cache(plan, x, fc)
     fc = cache["fc"]
     Z1, U1h, Ah = cache["Z1"], cache["U1h"], cache["Ah"]
     n_bins_out = plan.N_fr >> plan.s_F
@@ -255,6 +264,8 @@ def backward(plan: OraclePlan, x: np.ndarray, dS: np.ndarray, cache=None) -> np.
         if blk.order == 2:
             by_n2.setdefault(blk.n2, []).append(blk)
     for grp in plan.groups:
+        if not any(np.any(_block_view(plan, blk, dS)) for blk in by_n2[grp.n2]):
+            continue    # every path of this group has zero gradient: it contributes nothing
         Y = second_layer_group(plan, grp, U1h, fc)
         Yh = np.fft.fft(Y, axis=0)
         phT = fc.phi_t(grp.j2)
@@ -285,11 +296,23 @@ def backward(plan: OraclePlan, x: np.ndarray, dS: np.ndarray, cache=None) -> np.
 
 # ----------------------------------------------------------------------------- partial forward
 
-def forward_groups(plan: OraclePlan, x: np.ndarray, n2_list, fc: FilterCache = None):
-    """Only the order-2 blocks of the listed n2 (others left at NaN), for sampled parity at scale."""
+def forward_partial(plan: OraclePlan, x: np.ndarray, n2_list, order1: bool = True, fc: FilterCache = None):
+    """The order-1 blocks (if ``order1``) and the order-2 blocks of the listed n2; every
+    other coefficient is NaN. Used for sampled parity at full size."""
     fc = fc or FilterCache(plan)
-    _, _, U1h, _ = first_layer(plan, x, fc)
+    _, _, U1h, S1 = first_layer(plan, x, fc)
     S = np.full(plan.n_coeff, np.nan)
+    if order1:
+        A = np.zeros((plan.N_fr, plan.nf_pad), dtype=np.float64)
+        A[:plan.N1] = S1
+        Ah = np.fft.fft(A, axis=0)
+        for blk in plan.blocks:
+            if blk.order != 1:
+                continue
+            g, b = blk.n_fr, plan.fr[blk.n_fr]
+            V = freq_filter(plan, Ah, g, fc)
+            out = V.real if b.lowpass else filt_dec(np.abs(V), fc.phi_f(b.k), plan.s_F - b.k, axis=0).real
+            _block_view(plan, blk, S)[:] = _keep(plan, blk, out)
     want = set(n2_list)
     for grp in plan.groups:
         if grp.n2 not in want:

@@ -1,0 +1,105 @@
+"""ctypes declarations of the C ABI in include/jtfs.h (argument marshalling only).
+
+Loading fails with an ImportError when libjtfs.so has not been built: there is no
+fallback implementation of any step.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_uint32, c_void_p
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libjtfs.so")
+
+JTFS_OK = 0
+JTFS_ERR_ARG = 1
+JTFS_ERR_NOMEM = 2
+JTFS_ERR_HIP = 3
+JTFS_ERR_WORKSPACE = 4
+JTFS_ERR_UNSUPPORTED = 5
+
+JTFS_OPT_GD = 0
+JTFS_OPT_MOMENTUM_BOLD = 1
+JTFS_OPT_ADAM = 2
+
+JTFS_REUSE_FORWARD = 1
+JTFS_N_STAGES = 18
+STAGE_NAMES = ["signal_dft", "l1_wavelet", "l1_modulus_dft", "l1_average", "order1_freq", "l2_wavelet",
+               "freq_fwd", "freq_pool", "freq_dP", "freq_bwd", "order1_bwd", "l1_average_adj", "dY2_dft",
+               "l2_adj_gather", "dZ1_dft", "l1_adj_gather", "loss", "update"]
+
+
+class jtfs_params(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("J", c_int32), ("Q1", c_int32), ("Q2", c_int32), ("J_fr", c_int32),
+                ("Q_fr", c_int32), ("log2_T", c_int32), ("F", c_double), ("periodic", c_int32)]
+
+
+class jtfs_path(ctypes.Structure):
+    _fields_ = [("order", c_int32), ("n2", c_int32), ("n_fr", c_int32), ("spin", c_int32), ("j2", c_int32),
+                ("j_fr", c_int32), ("n_lambda", c_int32), ("n_frames", c_int32), ("offset", c_int64)]
+
+
+class jtfs_plan_info(ctypes.Structure):
+    _fields_ = [("batch", c_int32), ("n_samples_total", c_int64), ("n_coeff_total", c_int64),
+                ("ws_forward", c_size_t), ("ws_backward", c_size_t)]
+
+
+class jtfs_opt(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("lr", ctypes.c_float), ("momentum", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("bold_up", ctypes.c_float),
+                ("bold_down", ctypes.c_float), ("state", c_void_p)]
+
+
+# (name, restype, argtypes) for every exported function of include/jtfs.h
+SIGNATURES = [
+    ("jtfs_plan", c_int32, [POINTER(jtfs_params), c_int32, POINTER(c_void_p)]),
+    ("jtfs_plan_query", c_int32, [c_void_p, POINTER(jtfs_plan_info)]),
+    ("jtfs_plan_offsets", c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64)]),
+    ("jtfs_plan_meta", c_int32, [c_void_p, c_int32, POINTER(jtfs_path), c_int64, POINTER(c_int64)]),
+    ("jtfs_plan_filters", c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double), POINTER(c_double),
+                                    POINTER(c_int32), POINTER(c_int32), c_int32, POINTER(c_int32)]),
+    ("jtfs_plan_sizes", c_int32, [c_void_p, c_int32, POINTER(c_int64)]),
+    ("jtfs_plan_ws_region", c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int64), POINTER(c_int64)]),
+    ("jtfs_plan_cost", c_int32, [c_void_p, c_int32, POINTER(c_double)]),
+    ("jtfs_opt_state_floats", c_int64, [c_void_p, c_int32]),
+    ("jtfs_forward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("jtfs_backward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_uint32, c_void_p]),
+    ("jtfs_metamer_step", c_int32, [c_void_p, c_void_p, c_void_p, POINTER(jtfs_opt), c_void_p, c_void_p, c_size_t,
+                                    c_void_p]),
+    ("jtfs_timing_enable", c_int32, [c_void_p, c_int32]),
+    ("jtfs_timing_read", c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64), c_int32]),
+    ("jtfs_plan_destroy", None, [c_void_p]),
+    ("jtfs_status_str", c_char_p, [c_int32]),
+    ("jtfs_last_error", c_char_p, []),
+]
+
+_lib = None
+
+
+def lib():
+    """The loaded library (loaded once)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              "(python -m paper_2602_11896_amd.build)")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+class JTFSError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        L = lib()
+        detail = L.jtfs_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {L.jtfs_status_str(status).decode()} ({status}): {detail}")
+        self.status = status
+
+
+def check(status: int, where: str) -> None:
+    if status != JTFS_OK:
+        raise JTFSError(status, where)

@@ -1,0 +1,52 @@
+// Device view of one signal's plan tables and workspace, passed by value to kernels.
+#pragma once
+#include <cstdint>
+
+#include "fft_core.hpp"
+#include "types.hpp"
+
+namespace jtfs {
+
+struct DevSig {
+  // ---- plan tables (device arena owned by the plan)
+  const c32* tw;            // exp(-2 pi i q / N_pad), q < N_pad
+  const float* bandvals;
+  const Band* bands;
+  const float* tables;      // time-domain phi_T / phi_F
+  const c32* W;             // R_pad x NW frequential rows
+  const int32_t* rt_nrange; // per 16-row tile: n_lo, n_hi
+  const FrFilter* frf;
+  const FreqGroup* fgroups;
+  const FwdItem* fwd_items;
+  const BwdItem* bwd_items;
+  const RowJob* jobs;
+  const GatherTerm* terms;
+  const int64_t* s_off;     // output offset of block (group gi, filter g) at gi*n_g + g;
+                            // order-1 blocks at n_groups*n_g + (index in the real list)
+  // ---- per-call arrays
+  const float* x;           // this signal's samples (n)
+  float* S;                 // this signal's coefficients
+  const float* dS;          // this signal's coefficient gradient
+  float* dx;                // this signal's sample gradient
+  // ---- workspace regions
+  c32* Xh;
+  c32* Z1;
+  c32* U1h;
+  float* S1;
+  c32* Y2;
+  float* part;
+  c32* scr;
+  float* dP;
+  c32* dYpart;
+  c32* dYh;
+  float* dS1p;
+  float* dU1;
+  c32* dZh;
+  // ---- sizes
+  int32_t N, N_pad, pad_left, log2_Npad;
+  int32_t N1, nf_pad, f_lo, nF, Lf, log2T, N_fr, sF;
+  int32_t n_g, n_groups, n_real, R_pad, NW;
+  int64_t y2_total;
+};
+
+}  // namespace jtfs

@@ -1,0 +1,453 @@
+// Frequential scattering and averaging (Sec. 3.4-3.5, Eqs. 2 and 4) and their adjoints.
+//
+// For one second-order stack Y2 (K rows n1, L2 times t) and frequential filter g with
+// subsampling 2^k_g, the frequential convolution is a dense complex contraction
+//   V[r, t] = sum_n W[row0_g + r, n] Y2[n, t],  W[row0_g + r, n] = g[(r 2^k_g - n) mod N_fr]
+// (a circulant Toeplitz on the zero-padded log-frequency axis, decimated by 2^k_g).
+// All filters are stacked into one row space, each padded to a multiple of 16 rows.
+// The modulus U2 = |V| is never stored: the forward kernel pools it over time at once,
+//   P[r, f] = sum_t U2[r, t] phi_T^(j2)[(f 2^(log2T - j2) - t) mod L2],
+// so the chain is MFMA (complex, FP32) -> modulus -> MFMA (pooling), as in a fused
+// back-to-back GEMM. Kept frames only (the time unpadding is applied here).
+// A second kernel sums the per-time-chunk partials and applies phi_F along r.
+//
+// MFMA v_mfma_f32_16x16x4f32 operand layout (lane l, i = l % 16, k = l / 16):
+//   A[i][k] from lane l, B[k][i] from lane l, D[4k + v][i] in element v of lane l.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "launch.hpp"
+#include "plan.hpp"
+
+namespace jtfs {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline f4 mfma(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+// ------------------------------------------------------------------ forward contraction
+// Work item: group, 64-row block (one 16-row tile per wave), a chunk of TC times.
+// Per wave: V^T (16 t x 16 r) = Y2^T (t x n) W^T (n x r) with W^T held in registers,
+// then P^T (f x r) += Phi^T (f x t) |V^T| with the modulus taken in the D layout,
+// which is exactly the B layout the pooling MFMA needs.
+template <int MAXS>
+__global__ __launch_bounds__(256) void k_freq_fwd(DevSig s) {
+  __shared__ c32 ytile[MAXS * 4 * 16];
+  const FwdItem it = s.fwd_items[blockIdx.x];
+  const FreqGroup fg = s.fgroups[it.grp];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int rt = it.rb * 4 + wave;
+  const int r0 = rt * 16;
+  const int K = fg.K;
+  const int Kal = (K + 3) & ~3;
+  const int nlo = s.rt_nrange[2 * rt];
+  const int nhi = min(s.rt_nrange[2 * rt + 1], Kal);
+  const int steps = nhi > nlo ? (nhi - nlo) >> 2 : 0;
+
+  float bre[MAXS], bim[MAXS];
+#pragma unroll
+  for (int q = 0; q < MAXS; ++q) {
+    bre[q] = 0.f;
+    bim[q] = 0.f;
+    const int n = nlo + 4 * q + lk;
+    if (q < steps && n < K) {
+      const c32 w = s.W[static_cast<int64_t>(r0 + li) * s.NW + n];
+      bre[q] = w.x;
+      bim[q] = w.y;
+    }
+  }
+  const int nF = s.nF;
+  const int FT = (nF + 15) >> 4;
+  f4 pacc[8];
+#pragma unroll
+  for (int ft = 0; ft < 8; ++ft) pacc[ft] = f4{0.f, 0.f, 0.f, 0.f};
+  const c32* Y = s.Y2 + fg.y2;
+  const float* phi = s.tables + fg.phiT;
+  const int L2 = fg.L2;
+  const int Lmask = L2 - 1;
+  const int tbeg = it.tc * fg.TC;
+
+  for (int tt = tbeg; tt < tbeg + fg.TC; tt += 16) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < Kal * 16; e += 256) {
+      const int n = e >> 4, t = e & 15;
+      ytile[e] = n < K ? Y[static_cast<int64_t>(n) * L2 + tt + t] : c32{0.f, 0.f};
+    }
+    __syncthreads();
+    f4 ar = {0.f, 0.f, 0.f, 0.f}, ai = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < MAXS; ++q) {
+      if (q < steps) {
+        const c32 a = ytile[(nlo + 4 * q + lk) * 16 + li];
+        ar = mfma(a.x, bre[q], ar);
+        ai = mfma(a.x, bim[q], ai);
+        ar = mfma(a.y, -bim[q], ar);
+        ai = mfma(a.y, bre[q], ai);
+      }
+    }
+    float u[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) u[v] = sqrtf(ar[v] * ar[v] + ai[v] * ai[v]);
+#pragma unroll
+    for (int ft = 0; ft < 8; ++ft) {
+      if (ft < FT) {
+        const int f = ft * 16 + li;
+        const int fc = (s.f_lo + f) << fg.s_t;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int t = tt + 4 * lk + v;
+          const float a = f < nF ? phi[(fc - t) & Lmask] : 0.f;
+          pacc[ft] = mfma(a, u[v], pacc[ft]);
+        }
+      }
+    }
+  }
+  float* out = s.part + fg.part + (static_cast<int64_t>(it.tc) * s.R_pad + r0 + li) * nF;
+#pragma unroll
+  for (int ft = 0; ft < 8; ++ft) {
+    if (ft < FT) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int f = ft * 16 + 4 * lk + v;
+        if (f < nF) out[f] = pacc[ft][v];
+      }
+    }
+  }
+}
+
+// Sum of the time-chunk partials, phi_F averaging along log-frequency (band-pass g) or
+// nothing more (g = phi_F), log-frequency unpadding, store into S.
+__global__ __launch_bounds__(256) void k_freq_pool(DevSig s) {
+  __shared__ float P[8192];
+  const int gi = blockIdx.x / s.n_g, g = blockIdx.x % s.n_g;
+  const FreqGroup fg = s.fgroups[gi];
+  const FrFilter ff = s.frf[g];
+  const int nF = s.nF;
+  const int nb = (fg.K + (1 << s.sF) - 1) >> s.sF;
+  float* out = s.S + s.s_off[gi * s.n_g + g];
+  const int Mrows = ff.lowpass ? nb : ff.M;
+  const int fw = max(1, min(nF, 8192 / Mrows));
+  const int sh = s.sF - ff.k;
+  const float* ph = s.tables + ff.phiF;
+  for (int f0 = 0; f0 < nF; f0 += fw) {
+    const int fc = min(fw, nF - f0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < Mrows * fc; e += 256) {
+      const int r = e / fc, fl = e - r * fc;
+      float acc = 0.f;
+      for (int tc = 0; tc < fg.n_tc; ++tc)
+        acc += s.part[fg.part + (static_cast<int64_t>(tc) * s.R_pad + ff.row0 + r) * nF + f0 + fl];
+      P[r * fc + fl] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nb * fc; e += 256) {
+      const int b = e / fc, fl = e - b * fc;
+      float v;
+      if (ff.lowpass) {
+        v = P[b * fc + fl];
+      } else {
+        float acc = 0.f;
+        for (int r = 0; r < ff.M; ++r) acc += ph[((b << sh) - r) & (ff.M - 1)] * P[r * fc + fl];
+        v = acc;
+      }
+      out[b * nF + f0 + fl] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ order 1 (alpha = 0)
+// Frequential filters on S1 (real): V = W_g S1 over kept frames; band-pass: |V| then
+// phi_F averaging; phi_F itself: V (already averaged along both axes, Eq. 3).
+__global__ __launch_bounds__(256) void k_order1_fwd(DevSig s) {
+  __shared__ float U[8192];
+  const int g = blockIdx.x;
+  const FrFilter ff = s.frf[g];
+  const int nF = s.nF, N1 = s.N1;
+  const int nb = (N1 + (1 << s.sF) - 1) >> s.sF;
+  float* out = s.S + s.s_off[s.n_groups * s.n_g + g];
+  const int Mrows = ff.lowpass ? nb : ff.M;
+  const int fw = max(1, min(nF, 8192 / Mrows));
+  const int sh = s.sF - ff.k;
+  const float* ph = s.tables + ff.phiF;
+  for (int f0 = 0; f0 < nF; f0 += fw) {
+    const int fc = min(fw, nF - f0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < Mrows * fc; e += 256) {
+      const int r = e / fc, fl = e - r * fc;
+      const c32* w = s.W + static_cast<int64_t>(ff.row0 + r) * s.NW;
+      const float* x = s.S1 + s.f_lo + f0 + fl;
+      float vr = 0.f, vi = 0.f;
+      for (int n = 0; n < N1; ++n) {
+        const float a = x[static_cast<int64_t>(n) * s.nf_pad];
+        vr += w[n].x * a;
+        vi += w[n].y * a;
+      }
+      U[r * fc + fl] = ff.lowpass ? vr : sqrtf(vr * vr + vi * vi);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nb * fc; e += 256) {
+      const int b = e / fc, fl = e - b * fc;
+      float v;
+      if (ff.lowpass) {
+        v = U[b * fc + fl];
+      } else {
+        float acc = 0.f;
+        for (int r = 0; r < ff.M; ++r) acc += ph[((b << sh) - r) & (ff.M - 1)] * U[r * fc + fl];
+        v = acc;
+      }
+      out[b * nF + f0 + fl] = v;
+    }
+  }
+}
+
+// Adjoint of the order-1 paths: per filter g, the contribution to dS1 (N1 x nf_pad,
+// zero outside the kept frames), written to its own slice of dS1p (summed later in
+// a fixed order).
+__global__ __launch_bounds__(256) void k_order1_bwd(DevSig s) {
+  __shared__ c32 dV[4096];
+  const int g = blockIdx.x;
+  const FrFilter ff = s.frf[g];
+  const int nF = s.nF, N1 = s.N1;
+  const int nb = (N1 + (1 << s.sF) - 1) >> s.sF;
+  const float* dout = s.dS + s.s_off[s.n_groups * s.n_g + g];
+  float* dst = s.dS1p + static_cast<int64_t>(g) * N1 * s.nf_pad;
+  const int Mrows = ff.lowpass ? nb : ff.M;
+  const int fw = max(1, min(nF, 4096 / Mrows));
+  const int sh = s.sF - ff.k;
+  const float* ph = s.tables + ff.phiF;
+  for (int e = threadIdx.x; e < N1 * s.nf_pad; e += 256) {
+    const int f = e % s.nf_pad;
+    if (f < s.f_lo || f >= s.f_lo + nF) dst[e] = 0.f;
+  }
+  for (int f0 = 0; f0 < nF; f0 += fw) {
+    const int fc = min(fw, nF - f0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < Mrows * fc; e += 256) {
+      const int r = e / fc, fl = e - r * fc;
+      c32 d{0.f, 0.f};
+      if (ff.lowpass) {
+        d.x = dout[r * nF + f0 + fl];
+      } else {
+        float du = 0.f;
+        for (int b = 0; b < nb; ++b) du += ph[((b << sh) - r) & (ff.M - 1)] * dout[b * nF + f0 + fl];
+        const c32* w = s.W + static_cast<int64_t>(ff.row0 + r) * s.NW;
+        const float* x = s.S1 + s.f_lo + f0 + fl;
+        float vr = 0.f, vi = 0.f;
+        for (int n = 0; n < N1; ++n) {
+          const float a = x[static_cast<int64_t>(n) * s.nf_pad];
+          vr += w[n].x * a;
+          vi += w[n].y * a;
+        }
+        const float m = sqrtf(vr * vr + vi * vi);
+        if (m > 0.f) d = c32{du * (vr / m), du * (vi / m)};
+      }
+      dV[r * fc + fl] = d;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < N1 * fc; e += 256) {
+      const int n = e / fc, fl = e - n * fc;
+      float acc = 0.f;
+      for (int r = 0; r < Mrows; ++r) {
+        const c32 w = s.W[static_cast<int64_t>(ff.row0 + r) * s.NW + n];
+        const c32 d = dV[r * fc + fl];
+        acc += w.x * d.x + w.y * d.y;
+      }
+      dst[static_cast<int64_t>(n) * s.nf_pad + s.f_lo + f0 + fl] = acc;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ backward
+// Pooled-gradient rows: dP[row, f] = sum_b phi_F^(k_g)[(b 2^(sF - k_g) - r) mod M] dS[b, f]
+// (band-pass g) or dS[r, f] (g = phi_F); zero on padding rows.
+__global__ __launch_bounds__(256) void k_freq_dP(DevSig s) {
+  const int gi = blockIdx.y;
+  const FreqGroup fg = s.fgroups[gi];
+  const int nF = s.nF;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= s.R_pad * nF) return;
+  const int row = e / nF, f = e - (e / nF) * nF;
+  int g = -1;
+  for (int q = 0; q < s.n_g; ++q) {
+    const FrFilter c = s.frf[q];
+    if (row >= c.row0 && row < c.row0 + ((c.M + 15) & ~15)) g = q;
+  }
+  float v = 0.f;
+  if (g >= 0) {
+    const FrFilter ff = s.frf[g];
+    const int r = row - ff.row0;
+    const int nb = (fg.K + (1 << s.sF) - 1) >> s.sF;
+    const float* in = s.dS + s.s_off[gi * s.n_g + g];
+    if (r < ff.M) {
+      if (ff.lowpass) {
+        v = r < nb ? in[r * nF + f] : 0.f;
+      } else {
+        const int sh = s.sF - ff.k;
+        const float* ph = s.tables + ff.phiF;
+        for (int b = 0; b < nb; ++b) v += ph[((b << sh) - r) & (ff.M - 1)] * in[b * nF + f];
+      }
+    }
+  }
+  s.dP[fg.dP + e] = v;
+}
+
+// Work item: group, 64 times (one 16-time tile per wave), a split of the row tiles.
+// Per wave and row tile: recompute V (16 r x 16 t) = W Y2, dU = dP Phi (time-pooling
+// adjoint), dV = dU V / |V|, then dY2 (n x t) += W^H dV; Y2 operands and dY2
+// accumulators stay in registers over the row loop.
+template <int MAXS, int MAXNT>
+__global__ __launch_bounds__(256) void k_freq_bwd(DevSig s) {
+  __shared__ c32 wt[16 * 256];
+  const BwdItem it = s.bwd_items[blockIdx.x];
+  const FreqGroup fg = s.fgroups[it.grp];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int t0 = it.tb * 64 + wave * 16;
+  const int L2 = fg.L2;
+  const bool active = t0 < L2;
+  const int K = fg.K;
+  const int Kal = (K + 3) & ~3;
+  const int NT = (K + 15) >> 4;
+  const c32* Y = s.Y2 + fg.y2;
+
+  float yre[MAXS], yim[MAXS];
+#pragma unroll
+  for (int q = 0; q < MAXS; ++q) {
+    yre[q] = 0.f;
+    yim[q] = 0.f;
+    const int n = 4 * q + lk;
+    if (active && n < K) {
+      const c32 y = Y[static_cast<int64_t>(n) * L2 + t0 + li];
+      yre[q] = y.x;
+      yim[q] = y.y;
+    }
+  }
+  f4 dyr[MAXNT], dyi[MAXNT];
+#pragma unroll
+  for (int q = 0; q < MAXNT; ++q) {
+    dyr[q] = f4{0.f, 0.f, 0.f, 0.f};
+    dyi[q] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  const int nrt = s.R_pad >> 4;
+  const int rt_lo = it.rs * fg.rt_per_split;
+  const int rt_hi = min(nrt, rt_lo + fg.rt_per_split);
+  const float* phi = s.tables + fg.phiT;
+  const int nF = s.nF;
+  const int nFq = (nF + 3) >> 2;
+  const int ncols = NT * 16;
+
+  for (int rt = rt_lo; rt < rt_hi; ++rt) {
+    const int nlo = s.rt_nrange[2 * rt];
+    const int nhi = min(s.rt_nrange[2 * rt + 1], Kal);
+    if (nhi <= nlo) continue;   // uniform over the workgroup
+    const int r0 = rt * 16;
+    __syncthreads();
+    for (int e = threadIdx.x; e < 16 * ncols; e += 256) {
+      const int rr = e / ncols, n = e - rr * ncols;
+      wt[rr * 256 + n] = s.W[static_cast<int64_t>(r0 + rr) * s.NW + n];
+    }
+    __syncthreads();
+    if (!active) continue;
+    f4 vr = {0.f, 0.f, 0.f, 0.f}, vi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < MAXS; ++q) {
+      if (4 * q >= nlo && 4 * q < nhi) {
+        const c32 a = wt[li * 256 + 4 * q + lk];
+        vr = mfma(a.x, yre[q], vr);
+        vr = mfma(-a.y, yim[q], vr);
+        vi = mfma(a.x, yim[q], vi);
+        vi = mfma(a.y, yre[q], vi);
+      }
+    }
+    f4 du = {0.f, 0.f, 0.f, 0.f};
+    const float* dPr = s.dP + fg.dP + static_cast<int64_t>(r0 + li) * nF;
+    for (int q = 0; q < nFq; ++q) {
+      const int f = 4 * q + lk;
+      float a = 0.f, b = 0.f;
+      if (f < nF) {
+        a = dPr[f];
+        b = phi[(((s.f_lo + f) << fg.s_t) - (t0 + li)) & (L2 - 1)];
+      }
+      du = mfma(a, b, du);
+    }
+    float dvr[4], dvi[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float m = sqrtf(vr[v] * vr[v] + vi[v] * vi[v]);
+      dvr[v] = m > 0.f ? du[v] * (vr[v] / m) : 0.f;
+      dvi[v] = m > 0.f ? du[v] * (vi[v] / m) : 0.f;
+    }
+#pragma unroll
+    for (int nt = 0; nt < MAXNT; ++nt) {
+      if (nt < NT && nt * 16 < nhi && nt * 16 + 16 > nlo) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const c32 a = wt[(4 * lk + v) * 256 + nt * 16 + li];
+          dyr[nt] = mfma(a.x, dvr[v], dyr[nt]);
+          dyr[nt] = mfma(a.y, dvi[v], dyr[nt]);
+          dyi[nt] = mfma(a.x, dvi[v], dyi[nt]);
+          dyi[nt] = mfma(-a.y, dvr[v], dyi[nt]);
+        }
+      }
+    }
+  }
+  if (!active) return;
+  c32* dst = s.dYpart + fg.dYpart + static_cast<int64_t>(it.rs) * K * L2;
+#pragma unroll
+  for (int nt = 0; nt < MAXNT; ++nt) {
+    if (nt < NT) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int n = nt * 16 + 4 * lk + v;
+        if (n < K) dst[static_cast<int64_t>(n) * L2 + t0 + li] = c32{dyr[nt][v], dyi[nt][v]};
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t run_order1_fwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  hipLaunchKernelGGL(k_order1_fwd, dim3(p.fr_real.size()), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t run_order1_bwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  hipLaunchKernelGGL(k_order1_bwd, dim3(p.fr_real.size()), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t run_freq_fwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  if (p.fwd_items.empty()) return hipSuccess;
+  if (p.NW <= 128)
+    hipLaunchKernelGGL(k_freq_fwd<32>, dim3(p.fwd_items.size()), dim3(256), 0, st, s);
+  else
+    hipLaunchKernelGGL(k_freq_fwd<64>, dim3(p.fwd_items.size()), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t run_freq_pool(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  if (p.groups.empty()) return hipSuccess;
+  hipLaunchKernelGGL(k_freq_pool, dim3(p.groups.size() * p.fr.size()), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t run_freq_dP(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  if (p.groups.empty()) return hipSuccess;
+  const int blocks = (p.R_pad * p.n_frames + 255) / 256;
+  hipLaunchKernelGGL(k_freq_dP, dim3(blocks, p.groups.size()), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t run_freq_bwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  if (p.bwd_items.empty()) return hipSuccess;
+  if (p.NW <= 128)
+    hipLaunchKernelGGL((k_freq_bwd<32, 8>), dim3(p.bwd_items.size()), dim3(256), 0, st, s);
+  else
+    hipLaunchKernelGGL((k_freq_bwd<64, 16>), dim3(p.bwd_items.size()), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+}  // namespace jtfs

@@ -1,0 +1,348 @@
+// Time-axis stages of JTFS and their adjoints: batched FFTs with fused Fourier-domain
+// filtering, Fourier subsampling, modulus and phase (Sec. 3.2-3.3, Eqs. 5-7).
+//
+// Every stage is a batch of independent rows (RowJob); a row's transform has length n.
+// Rows with n <= 4096 run in one kernel (the whole row in a 4096-element LDS tile);
+// longer rows run as two kernels (fft_core.hpp's split) through a scratch buffer.
+// A stage supplies load(idx) producing transform input idx, and store(idx, v)
+// consuming transform output idx (already scaled by 1/n for inverse transforms).
+//
+// Stage meanings (RowJob fields in brackets):
+//  XHAT  X = DFT(x zero-padded to N_pad)                               [dst: Xh]
+//  L1Z   Z1 = IDFT_L1(fold_k1(X . psi1))        (Sec. 3.2)           [band psi1, shift k1, dst: Z1 row]
+//  L1UH  U1hat = DFT(|Z1|)                       (Sec. 3.2)           [src/dst: row offset]
+//  L2Y   Y2 = IDFT_L2(fold_k2(U1hat . psi2^(k1)))  (Sec. 3.3)         [src: U1hat row, band, shift k2]
+//  BYH   dY2hat = DFT(sum of the row-split partials of dY2)           [src, aux: split stride, t0: splits]
+//  BU    dU1 = Re IDFT_L1(sum_terms band . tile(term source))        [terms t0..t1]
+//  BZH   dZ1hat = DFT(dU1 . Z1 / |Z1|)  (0 where Z1 = 0)              [src: dU1, aux: Z1]
+//  BX    dx = unpad Re IDFT_Npad(sum_n1 psi1 . tile(dZ1hat))          [terms t0..t1]
+// fold_k averages the 2^k aliased blocks of a spectrum; tile is its transpose up to
+// 2^-k; with both, a filter-and-subsample step and its adjoint are exact.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "launch.hpp"
+#include "plan.hpp"
+
+namespace jtfs {
+namespace {
+
+__device__ inline float cabs(c32 z) { return sqrtf(z.x * z.x + z.y * z.y); }
+
+// Fourier subsampling by 2^shift of (src . band) onto an n-point grid, output bin q.
+__device__ inline c32 fold_gather(const c32* src, const Band& b, const float* vals, int n, int shift, int q) {
+  const int nmask = n - 1;
+  int d = (q - (b.lo & nmask)) & nmask;
+  c32 acc{0.f, 0.f};
+  for (; d < b.len; d += n) {
+    int m = b.lo + d;
+    if (m >= b.L) m -= b.L;
+    const float h = vals[b.off + d];
+    const c32 v = src[m];
+    acc.x += v.x * h;
+    acc.y += v.y * h;
+  }
+  const float sc = ldexpf(1.0f, -shift);
+  return c32{acc.x * sc, acc.y * sc};
+}
+
+// Adjoint gather: sum over terms of band[m] * src_t[m mod len_t], output bin m.
+__device__ inline c32 term_gather(const DevSig& s, const c32* base, int t0, int t1, int m) {
+  c32 acc{0.f, 0.f};
+  for (int t = t0; t < t1; ++t) {
+    const GatherTerm g = s.terms[t];
+    const Band b = s.bands[g.band];
+    int d = m - b.lo;
+    if (d < 0) d += b.L;
+    if (d < b.len) {
+      const float h = s.bandvals[b.off + d];
+      const c32 v = base[g.src + (m & (g.src_len - 1))];
+      acc.x += v.x * h;
+      acc.y += v.y * h;
+    }
+  }
+  return acc;
+}
+
+template <int ST>
+struct Ops;
+
+template <>
+struct Ops<ST_XHAT> {
+  static constexpr int DIR = -1;
+  __device__ static c32 load(const DevSig& s, const RowJob&, int idx) {
+    const int j = idx - s.pad_left;
+    return c32{(j >= 0 && j < s.N) ? s.x[j] : 0.f, 0.f};
+  }
+  __device__ static void store(const DevSig& s, const RowJob&, int idx, c32 v) { s.Xh[idx] = v; }
+};
+
+template <>
+struct Ops<ST_L1Z> {
+  static constexpr int DIR = +1;
+  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
+    return fold_gather(s.Xh, s.bands[j.band], s.bandvals, j.n, j.shift, idx);
+  }
+  __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.Z1[j.dst + idx] = v; }
+};
+
+template <>
+struct Ops<ST_L1UH> {
+  static constexpr int DIR = -1;
+  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
+    return c32{cabs(s.Z1[j.src + idx]), 0.f};
+  }
+  __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.U1h[j.dst + idx] = v; }
+};
+
+template <>
+struct Ops<ST_L2Y> {
+  static constexpr int DIR = +1;
+  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
+    return fold_gather(s.U1h + j.src, s.bands[j.band], s.bandvals, j.n, j.shift, idx);
+  }
+  __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.Y2[j.dst + idx] = v; }
+};
+
+template <>
+struct Ops<ST_BYH> {
+  static constexpr int DIR = -1;
+  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
+    c32 acc{0.f, 0.f};
+    for (int r = 0; r < j.t0; ++r) {
+      const c32 v = s.dYpart[j.src + r * j.aux + idx];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    return acc;
+  }
+  __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.dYh[j.dst + idx] = v; }
+};
+
+template <>
+struct Ops<ST_BU> {
+  static constexpr int DIR = +1;
+  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
+    return term_gather(s, s.dYh, j.t0, j.t1, idx);
+  }
+  __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.dU1[j.dst + idx] = v.x; }
+};
+
+template <>
+struct Ops<ST_BZH> {
+  static constexpr int DIR = -1;
+  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
+    const float u = s.dU1[j.src + idx];
+    const c32 z = s.Z1[j.aux + idx];
+    const float a = cabs(z);
+    return a > 0.f ? c32{u * (z.x / a), u * (z.y / a)} : c32{0.f, 0.f};
+  }
+  __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.dZh[j.dst + idx] = v; }
+};
+
+template <>
+struct Ops<ST_BX> {
+  static constexpr int DIR = +1;
+  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
+    return term_gather(s, s.dZh, j.t0, j.t1, idx);
+  }
+  __device__ static void store(const DevSig& s, const RowJob&, int idx, c32 v) {
+    const int k = idx - s.pad_left;
+    if (k >= 0 && k < s.N) s.dx[k] = v.x;
+  }
+};
+
+// One radix-2^LR pass over the tile (two barriers: all reads before any write).
+template <int DIR, int LR>
+__device__ inline void tile_pass(c32* col, int log2n, int log2p, int t, int tpf, const c32* tw, int log2tw) {
+  c32 v[16];
+  stockham_compute<DIR, LR>(col, log2n, log2p, t, tpf, tw, log2tw, v);
+  __syncthreads();
+  stockham_store<LR>(col, log2p, t, tpf, v);
+  __syncthreads();
+}
+
+// In-place FFT of the 4096 / n columns of the tile (natural order in and out).
+template <int DIR>
+__device__ void fft_tile(c32* lds, int log2n, const c32* tw, int log2tw) {
+  const int tpf = 1 << (log2n - 4);
+  const int t = threadIdx.x & (tpf - 1);
+  c32* col = lds + (threadIdx.x >> (log2n - 4)) * (1 << log2n);
+  int lr[8];
+  const int np = fft_radices(log2n, lr);
+  int log2p = 0;
+  for (int p = 0; p < np; ++p) {
+    switch (lr[p]) {
+      case 1: tile_pass<DIR, 1>(col, log2n, log2p, t, tpf, tw, log2tw); break;
+      case 2: tile_pass<DIR, 2>(col, log2n, log2p, t, tpf, tw, log2tw); break;
+      case 3: tile_pass<DIR, 3>(col, log2n, log2p, t, tpf, tw, log2tw); break;
+      default: tile_pass<DIR, 4>(col, log2n, log2p, t, tpf, tw, log2tw); break;
+    }
+    log2p += lr[p];
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_fft_rows(DevSig s, int job0, int njobs, int log2n) {
+  __shared__ c32 lds[4096];
+  using O = Ops<ST>;
+  const int n = 1 << log2n;
+  const int row0 = blockIdx.x << (12 - log2n);
+  for (int i = 0; i < 16; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    const int row = row0 + (e >> log2n);
+    lds[e] = row < njobs ? O::load(s, s.jobs[job0 + row], e & (n - 1)) : c32{0.f, 0.f};
+  }
+  __syncthreads();
+  fft_tile<O::DIR>(lds, log2n, s.tw, s.log2_Npad);
+  const float sc = O::DIR > 0 ? 1.0f / n : 1.0f;
+  for (int i = 0; i < 16; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    const int row = row0 + (e >> log2n);
+    if (row < njobs) O::store(s, s.jobs[job0 + row], e & (n - 1), cscale(lds[e], sc));
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_fft_split1(DevSig s, int job0, int log2n) {
+  __shared__ c32 lds[4096];
+  using O = Ops<ST>;
+  const SplitGeom g = split_geom(log2n);
+  const int row = blockIdx.y;
+  const RowJob job = s.jobs[job0 + row];
+  const int n1_0 = blockIdx.x << g.log2C1;
+  for (int i = 0; i < 16; ++i) {
+    int idx, slot;
+    split_p1_load(g, n1_0, threadIdx.x + 256 * i, idx, slot);
+    lds[slot] = O::load(s, job, idx);
+  }
+  __syncthreads();
+  fft_tile<O::DIR>(lds, g.log2B, s.tw, s.log2_Npad);
+  c32* scr = s.scr + (static_cast<int64_t>(row) << log2n);
+  const int tshift = s.log2_Npad - log2n;
+  for (int i = 0; i < 16; ++i) {
+    int slot, sidx, te;
+    split_p1_store(g, n1_0, threadIdx.x + 256 * i, slot, sidx, te);
+    c32 w = s.tw[te << tshift];
+    if (O::DIR > 0) w.y = -w.y;
+    scr[sidx] = cmul(lds[slot], w);
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_fft_split2(DevSig s, int job0, int log2n) {
+  __shared__ c32 lds[4096];
+  using O = Ops<ST>;
+  const SplitGeom g = split_geom(log2n);
+  const int row = blockIdx.y;
+  const RowJob job = s.jobs[job0 + row];
+  const int k2_0 = blockIdx.x << g.log2C2;
+  const c32* scr = s.scr + (static_cast<int64_t>(row) << log2n);
+  for (int i = 0; i < 16; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    lds[e] = scr[split_p2_load(g, k2_0, e)];
+  }
+  __syncthreads();
+  fft_tile<O::DIR>(lds, g.log2A, s.tw, s.log2_Npad);
+  const float sc = O::DIR > 0 ? 1.0f / static_cast<float>(1 << log2n) : 1.0f;
+  for (int i = 0; i < 16; ++i) {
+    int slot, oidx;
+    split_p2_store(g, k2_0, threadIdx.x + 256 * i, slot, oidx);
+    O::store(s, job, oidx, cscale(lds[slot], sc));
+  }
+}
+
+// First-order averaging (Eq. 3 before phi_F): S1 = Re IDFT_Lf(fold(U1hat . phi_T^(k1))),
+// one workgroup per first-order row; the Lf-point inverse DFT is computed directly.
+__global__ __launch_bounds__(256) void k_s1(DevSig s, int job0) {
+  __shared__ c32 F[1024];
+  const RowJob j = s.jobs[job0 + blockIdx.x];
+  const int Lf = j.n;
+  const int log2Lf = 31 - __clz(Lf);
+  const Band b = s.bands[j.band];
+  for (int q = threadIdx.x; q < Lf; q += 256) F[q] = fold_gather(s.U1h + j.src, b, s.bandvals, Lf, j.shift, q);
+  __syncthreads();
+  const int tshift = s.log2_Npad - log2Lf;
+  for (int f = threadIdx.x; f < Lf; f += 256) {
+    float acc = 0.f;
+    for (int q = 0; q < Lf; ++q) {
+      const c32 w = s.tw[((q * f) & (Lf - 1)) << tshift];   // exp(-2 pi i q f / Lf)
+      acc += F[q].x * w.x + F[q].y * w.y;                    // Re(F exp(+2 pi i q f / Lf))
+    }
+    s.S1[j.dst + f] = acc / Lf;
+  }
+}
+
+// Adjoint of the first-order averaging onto the spectrum: for each first-order row,
+// dS1hat = DFT_Lf(sum over the real frequential filters of their dS1 contributions).
+__global__ __launch_bounds__(256) void k_ds1h(DevSig s) {
+  __shared__ float d[1024];
+  const int n1 = blockIdx.x;
+  const int Lf = s.nf_pad;
+  const int log2Lf = 31 - __clz(Lf);
+  for (int f = threadIdx.x; f < Lf; f += 256) {
+    float acc = 0.f;
+    for (int g = 0; g < s.n_real; ++g) acc += s.dS1p[(static_cast<int64_t>(g) * s.N1 + n1) * Lf + f];
+    d[f] = acc;
+  }
+  __syncthreads();
+  const int tshift = s.log2_Npad - log2Lf;
+  for (int m = threadIdx.x; m < Lf; m += 256) {
+    c32 acc{0.f, 0.f};
+    for (int f = 0; f < Lf; ++f) {
+      const c32 w = s.tw[((m * f) & (Lf - 1)) << tshift];
+      acc.x += d[f] * w.x;
+      acc.y += d[f] * w.y;
+    }
+    s.dYh[s.y2_total + static_cast<int64_t>(n1) * Lf + m] = acc;
+  }
+}
+
+template <int ST>
+hipError_t run_stage_t(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  for (const Launch& l : p.launches[ST]) {
+    const int log2n = 31 - __builtin_clz(static_cast<unsigned>(l.n));
+    if (l.n <= 4096) {
+      const int per = 4096 / l.n;
+      const int blocks = (l.njobs + per - 1) / per;
+      hipLaunchKernelGGL(k_fft_rows<ST>, dim3(blocks), dim3(256), 0, st, s, l.job0, l.njobs, log2n);
+    } else {
+      const SplitGeom g = split_geom(log2n);
+      hipLaunchKernelGGL(k_fft_split1<ST>, dim3((1 << g.log2A) >> g.log2C1, l.njobs), dim3(256), 0, st, s, l.job0,
+                         log2n);
+      hipLaunchKernelGGL(k_fft_split2<ST>, dim3((1 << g.log2B) >> g.log2C2, l.njobs), dim3(256), 0, st, s, l.job0,
+                         log2n);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t run_time_stage(int stage, const DevSig& s, const SigPlan& p, hipStream_t st) {
+  switch (stage) {
+    case ST_XHAT: return run_stage_t<ST_XHAT>(s, p, st);
+    case ST_L1Z: return run_stage_t<ST_L1Z>(s, p, st);
+    case ST_L1UH: return run_stage_t<ST_L1UH>(s, p, st);
+    case ST_L2Y: return run_stage_t<ST_L2Y>(s, p, st);
+    case ST_BYH: return run_stage_t<ST_BYH>(s, p, st);
+    case ST_BU: return run_stage_t<ST_BU>(s, p, st);
+    case ST_BZH: return run_stage_t<ST_BZH>(s, p, st);
+    case ST_BX: return run_stage_t<ST_BX>(s, p, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t run_s1(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  hipLaunchKernelGGL(k_s1, dim3(p.psi1.size()), dim3(256), 0, st, s, p.s1_job0);
+  return hipGetLastError();
+}
+
+hipError_t run_ds1h(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  hipLaunchKernelGGL(k_ds1h, dim3(p.psi1.size()), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+}  // namespace jtfs

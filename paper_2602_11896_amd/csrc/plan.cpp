@@ -1,0 +1,607 @@
+// Host-side JTFS plan (see plan.hpp). All tables are computed in FP64 and rounded
+// once to FP32 when stored.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace jtfs {
+namespace {
+
+constexpr double kSigma0 = 0.1;      // sigma0 of the Sec. 3.1 generator
+constexpr double kBandThresh = 1e-10; // Fourier bins below this fraction of the peak are dropped
+constexpr double kTapThresh = 1e-9;   // frequential taps below this fraction of the peak are skipped
+constexpr int kPeriods = 4;           // period-1 images of a Fourier Gaussian on each side
+constexpr double kPi = 3.14159265358979323846;
+
+int ceil_log2(int64_t n) {
+  int p = 0;
+  while ((int64_t(1) << p) < n) ++p;
+  return p;
+}
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+double gauss(double u, double s) { return std::exp(-(u * u) / (2.0 * s * s)); }
+
+// Fourier closed form of a Morlet at a given level: periodised Gaussian bump minus kappa
+// times the periodised Gaussian envelope, kappa making the value at w = 0 vanish.
+struct Morlet {
+  double xs, ss, kappa;
+  Morlet(double xi, double sigma, int level) {
+    xs = std::ldexp(xi, level);
+    ss = std::ldexp(sigma, level);
+    double num = 0.0, den = 0.0;
+    for (int p = -kPeriods; p <= kPeriods; ++p) {
+      num += gauss(p - xs, ss);
+      den += gauss(static_cast<double>(p), ss);
+    }
+    kappa = num / den;
+  }
+  double operator()(double w) const {
+    double bump = 0.0, env = 0.0;
+    for (int p = -kPeriods; p <= kPeriods; ++p) {
+      bump += gauss(w + p - xs, ss);
+      env += gauss(w + p, ss);
+    }
+    return bump - kappa * env;
+  }
+};
+
+// Fourier closed form of a Gaussian low-pass at a given level, unit gain at w = 0.
+struct Lowpass {
+  double ss, norm;
+  Lowpass(double sigma, int level) {
+    ss = std::ldexp(sigma, level);
+    norm = 0.0;
+    for (int p = -kPeriods; p <= kPeriods; ++p) norm += gauss(static_cast<double>(p), ss);
+  }
+  double operator()(double w) const {
+    double env = 0.0;
+    for (int p = -kPeriods; p <= kPeriods; ++p) env += gauss(w + p, ss);
+    return env / norm;
+  }
+};
+
+// Appends the band-limited image of a real Fourier filter on an L-point grid.
+// [wlo, whi] is a frequency window (cycles per sample, may leave [0, 1)) outside
+// which the filter is known to be negligible.
+template <class Fn>
+int32_t add_band(SigPlan& p, int64_t L, const Fn& value, double wlo, double whi) {
+  int64_t mlo = static_cast<int64_t>(std::floor(wlo * L));
+  int64_t mhi = static_cast<int64_t>(std::ceil(whi * L));
+  if (mhi - mlo + 1 >= L) {
+    mlo = 0;
+    mhi = L - 1;
+  }
+  std::vector<double> v(static_cast<size_t>(mhi - mlo + 1));
+  double peak = 0.0;
+  for (int64_t m = mlo; m <= mhi; ++m) {
+    double w = static_cast<double>(m) / static_cast<double>(L);
+    v[m - mlo] = value(w);
+    peak = std::max(peak, std::fabs(v[m - mlo]));
+  }
+  int64_t first = 0, last = static_cast<int64_t>(v.size()) - 1;
+  const double thr = kBandThresh * peak;
+  while (first < last && std::fabs(v[first]) <= thr) ++first;
+  while (last > first && std::fabs(v[last]) <= thr) --last;
+  Band b{};
+  b.L = static_cast<int32_t>(L);
+  b.lo = static_cast<int32_t>(((mlo + first) % L + L) % L);
+  b.len = static_cast<int32_t>(last - first + 1);
+  b.off = static_cast<int64_t>(p.bandvals.size());
+  for (int64_t i = first; i <= last; ++i) p.bandvals.push_back(static_cast<float>(v[i]));
+  p.bands.push_back(b);
+  return static_cast<int32_t>(p.bands.size() - 1);
+}
+
+int32_t add_morlet_band(SigPlan& p, int64_t L, double xi, double sigma, int level) {
+  Morlet h(xi, sigma, level);
+  double lo = std::min(h.xs, 0.0) - 8.0 * h.ss, hi = std::max(h.xs, 0.0) + 8.0 * h.ss;
+  return add_band(p, L, h, lo, hi);
+}
+
+int32_t add_lowpass_band(SigPlan& p, int64_t L, double sigma, int level) {
+  Lowpass h(sigma, level);
+  return add_band(p, L, h, -8.0 * h.ss, 8.0 * h.ss);
+}
+
+// Time-domain Gaussian low-pass at a level on an L-point grid: the continuous Gaussian
+// sampled at integers and periodised, normalised to unit sum (the inverse DFT of the
+// Fourier closed form, by Poisson summation).
+int64_t add_lowpass_time(SigPlan& p, int64_t L, double sigma, int level) {
+  const double ss = std::ldexp(sigma, level);
+  const double a = 2.0 * kPi * kPi * ss * ss;
+  const double width = 40.0 / (2.0 * kPi * ss);
+  const int64_t q = static_cast<int64_t>(std::ceil(width / static_cast<double>(L))) + 1;
+  std::vector<double> h(static_cast<size_t>(L), 0.0);
+  double total = 0.0;
+  for (int64_t d = 0; d < L; ++d) {
+    double s = 0.0;
+    for (int64_t img = -q; img <= q; ++img) {
+      double t = static_cast<double>(d + img * L);
+      s += std::exp(-a * t * t);
+    }
+    h[d] = s;
+    total += s;
+  }
+  int64_t off = static_cast<int64_t>(p.tables.size());
+  for (int64_t d = 0; d < L; ++d) p.tables.push_back(static_cast<float>(h[d] / total));
+  return off;
+}
+
+}  // namespace
+
+std::vector<std::pair<double, double>> wavelet_bank(int J, int Q) {
+  std::vector<std::pair<double, double>> bank;
+  const double step = std::pow(2.0, 1.0 / Q);
+  const double shrink = 1.0 / step;
+  double xi = std::max(1.0 / (1.0 + std::pow(2.0, 3.0 / Q)), 0.35);
+  double sigma = (1.0 - shrink) / (1.0 + shrink) * xi / std::sqrt(2.0 * std::log(1.0 / std::sqrt(0.5)));
+  const double sigma_min = kSigma0 / std::pow(2.0, J);
+  if (sigma <= sigma_min) {
+    xi = sigma;
+  } else {
+    bank.emplace_back(xi, sigma);
+    while (sigma > sigma_min * step) {
+      xi = xi / step;
+      sigma = sigma / step;
+      bank.emplace_back(xi, sigma);
+    }
+  }
+  const double elbow = xi;
+  for (int q = 0; q < Q - 1; ++q) {
+    xi = xi - elbow / Q;
+    bank.emplace_back(xi, sigma_min);
+  }
+  return bank;
+}
+
+int32_t subsampling_scale(double xi, double sigma) {
+  const double edge = std::fabs(xi) + 5.0 * sigma;
+  int32_t j = 0;
+  while (edge <= std::ldexp(1.0, -(j + 2))) ++j;
+  return j;
+}
+
+jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& err) {
+  p = SigPlan{};
+  p.prm = prm;
+  if (prm.n < 2 || prm.J < 0 || prm.Q1 < 1 || prm.Q2 < 1 || prm.J_fr < 0 || prm.Q_fr < 1 || prm.log2_T < 0 ||
+      !(prm.F >= 1.0) || prm.J > 24 || prm.J_fr > 24 || prm.Q1 > 64 || prm.Q2 > 64 || prm.Q_fr > 64) {
+    err = "invalid JTFS parameters";
+    return JTFS_ERR_ARG;
+  }
+  p.N = prm.n;
+  if (prm.periodic) {
+    if (prm.n & (prm.n - 1)) {
+      err = "periodic mode needs n a power of two";
+      return JTFS_ERR_ARG;
+    }
+    p.N_pad = prm.n;
+    p.pad_left = 0;
+  } else {
+    p.N_pad = int64_t(1) << (ceil_log2(prm.n) + 1);
+    p.pad_left = (p.N_pad - p.N) / 2;
+  }
+  p.log2_Npad = ceil_log2(p.N_pad);
+  if (p.N_pad > (int64_t(1) << 24)) {
+    err = "padded length above 2^24 is not supported";
+    return JTFS_ERR_UNSUPPORTED;
+  }
+  p.log2T = prm.log2_T;
+  if (prm.log2_T > p.log2_Npad) {
+    err = "T exceeds the padded length";
+    return JTFS_ERR_ARG;
+  }
+  p.T = 1 << prm.log2_T;
+  p.sF = 0;
+  while (std::ldexp(1.0, p.sF + 1) <= prm.F) ++p.sF;
+  p.sigmaT = kSigma0 / p.T;
+  p.sigmaF = kSigma0 / prm.F;
+
+  for (auto& xs : wavelet_bank(prm.J, prm.Q1)) {
+    Filt f{xs.first, xs.second, subsampling_scale(xs.first, xs.second), 0, 0, false};
+    f.k = std::min(f.j, p.log2T);
+    p.psi1.push_back(f);
+  }
+  for (auto& xs : wavelet_bank(prm.J, prm.Q2)) {
+    p.psi2.push_back(Filt{xs.first, xs.second, subsampling_scale(xs.first, xs.second), 0, 0, false});
+  }
+  const int32_t N1 = static_cast<int32_t>(p.psi1.size());
+  if (N1 == 0) {
+    err = "empty first-order filterbank";
+    return JTFS_ERR_ARG;
+  }
+  p.N_fr = 2 * (1 << ceil_log2(N1));
+  if ((1 << p.sF) > p.N_fr) {
+    err = "F exceeds the padded frequential axis";
+    return JTFS_ERR_ARG;
+  }
+  p.fr.push_back(Filt{0.0, p.sigmaF, p.sF, p.sF, 0, true});
+  auto bank_fr = wavelet_bank(prm.J_fr, prm.Q_fr);
+  for (int sign : {+1, -1}) {
+    for (auto& xs : bank_fr) {
+      Filt f{sign * xs.first, xs.second, subsampling_scale(xs.first, xs.second), 0, sign, false};
+      f.k = std::min(f.j, p.sF);
+      p.fr.push_back(f);
+    }
+  }
+  for (int32_t g = 0; g < static_cast<int32_t>(p.fr.size()); ++g)
+    if (p.fr[g].spin >= 0) p.fr_real.push_back(g);
+
+  // Second-order groups: rows n1 with j1 < j2 are a prefix (j1 never decreases).
+  for (int32_t n2 = 0; n2 < static_cast<int32_t>(p.psi2.size()); ++n2) {
+    const Filt& b2 = p.psi2[n2];
+    int32_t K = 0;
+    while (K < N1 && p.psi1[K].j < b2.j) ++K;
+    for (int32_t i = K; i < N1; ++i) {
+      if (p.psi1[i].j < b2.j) {
+        err = "first-order scales are not monotone";
+        return JTFS_ERR_UNSUPPORTED;
+      }
+    }
+    if (K == 0) continue;
+    for (int32_t n1 = 0; n1 < K; ++n1) {
+      int32_t k1 = p.psi1[n1].k;
+      int32_t k2 = std::min(b2.j - k1, p.log2T);
+      if (k1 + k2 > p.log2T || k1 + k2 != b2.j) {
+        err = "second-order resolution coarser than T is not supported";
+        return JTFS_ERR_UNSUPPORTED;
+      }
+    }
+    p.groups.push_back(Grp{n2, b2.j, K, p.N_pad >> b2.j});
+  }
+
+  p.nf_pad = static_cast<int32_t>(p.N_pad >> p.log2T);
+  p.Lf = p.nf_pad;
+  int64_t f_hi;
+  if (prm.periodic) {
+    p.f_lo = 0;
+    f_hi = p.nf_pad;
+  } else {
+    p.f_lo = static_cast<int32_t>((p.pad_left + p.T - 1) / p.T);
+    f_hi = (p.pad_left + p.N + p.T - 1) / p.T;
+  }
+  p.n_frames = static_cast<int32_t>(f_hi - p.f_lo);
+  // Kernel limits: transforms of at least 16 points, at most 128 kept frames.
+  for (const Grp& g : p.groups) {
+    if (g.L2 < 16) {
+      err = "second-order signals shorter than 16 samples are not supported";
+      return JTFS_ERR_UNSUPPORTED;
+    }
+  }
+  for (const Filt& f : p.psi1) {
+    if ((p.N_pad >> f.k) < 16) {
+      err = "first-order signals shorter than 16 samples are not supported";
+      return JTFS_ERR_UNSUPPORTED;
+    }
+  }
+  if (p.nf_pad > 1024) {
+    err = "more than 1024 padded frames (N_pad / T) are not supported";
+    return JTFS_ERR_UNSUPPORTED;
+  }
+  if (p.n_frames > 128 || p.n_frames < 1) {
+    err = "between 1 and 128 output frames are supported";
+    return JTFS_ERR_UNSUPPORTED;
+  }
+  if (N1 > 256) {
+    err = "at most 256 first-order filters are supported";
+    return JTFS_ERR_UNSUPPORTED;
+  }
+
+  // ---- output layout: order 1, then order 2 by ascending n2
+  auto bins = [&](int32_t K) { return (K + (1 << p.sF) - 1) >> p.sF; };
+  int64_t off = 0;
+  for (int32_t g : p.fr_real) {
+    jtfs_path r{1, -1, g, p.fr[g].spin, -1, p.fr[g].j, bins(N1), p.n_frames, off};
+    p.paths.push_back(r);
+    off += int64_t(r.n_lambda) * r.n_frames;
+  }
+  for (const Grp& grp : p.groups) {
+    for (int32_t g = 0; g < static_cast<int32_t>(p.fr.size()); ++g) {
+      jtfs_path r{2, grp.n2, g, p.fr[g].spin, grp.j2, p.fr[g].j, bins(grp.K), p.n_frames, off};
+      p.paths.push_back(r);
+      off += int64_t(r.n_lambda) * r.n_frames;
+    }
+  }
+  p.n_coeff = off;
+
+  // ---- twiddles exp(-2 pi i k / N_pad)
+  p.tw.resize(static_cast<size_t>(p.N_pad));
+  for (int64_t k = 0; k < p.N_pad; ++k) {
+    double a = -2.0 * kPi * static_cast<double>(k) / static_cast<double>(p.N_pad);
+    p.tw[k] = cfloat{static_cast<float>(std::cos(a)), static_cast<float>(std::sin(a))};
+  }
+
+  // ---- band tables
+  for (const Filt& f : p.psi1) p.band_psi1.push_back(add_morlet_band(p, p.N_pad, f.xi, f.sigma, 0));
+  p.band_phiT.assign(static_cast<size_t>(p.log2T + 1), -1);
+  for (const Filt& f : p.psi1) {
+    if (p.band_phiT[f.k] < 0) p.band_phiT[f.k] = add_lowpass_band(p, p.N_pad >> f.k, p.sigmaT, f.k);
+  }
+  for (const Grp& grp : p.groups) {
+    const Filt& b2 = p.psi2[grp.n2];
+    for (int32_t n1 = 0; n1 < grp.K; ++n1) {
+      int32_t k1 = p.psi1[n1].k;
+      auto key = std::make_pair(grp.n2, k1);
+      if (!p.band_psi2.count(key)) p.band_psi2[key] = add_morlet_band(p, p.N_pad >> k1, b2.xi, b2.sigma, k1);
+    }
+  }
+
+  // ---- frequential rows W: row r of filter g holds g[(r 2^k_g - n) mod N_fr], n < N1
+  p.NW = static_cast<int32_t>(round_up(N1, 16));
+  int32_t rows = 0;
+  for (const Filt& f : p.fr) {
+    FrFilter ff{};
+    ff.row0 = rows;
+    ff.M = p.N_fr >> f.k;
+    ff.k = f.k;
+    ff.lowpass = f.lowpass ? 1 : 0;
+    ff.spin = f.spin;
+    p.frf.push_back(ff);
+    rows += static_cast<int32_t>(round_up(ff.M, 16));
+  }
+  p.R_total = rows;
+  p.R_pad = static_cast<int32_t>(round_up(rows, 64));
+  p.W.assign(static_cast<size_t>(p.R_pad) * p.NW, cfloat{0.f, 0.f});
+  {
+    const int32_t L = p.N_fr;
+    std::vector<double> cs(L), sn(L);
+    for (int32_t j = 0; j < L; ++j) {
+      cs[j] = std::cos(2.0 * kPi * j / L);
+      sn[j] = std::sin(2.0 * kPi * j / L);
+    }
+    std::vector<double> tap_mag(static_cast<size_t>(p.R_pad) * p.NW, 0.0);
+    for (size_t g = 0; g < p.fr.size(); ++g) {
+      const Filt& f = p.fr[g];
+      std::vector<double> hat(L);
+      if (f.lowpass) {
+        Lowpass h(f.sigma, 0);
+        for (int32_t m = 0; m < L; ++m) hat[m] = h(static_cast<double>(m) / L);
+      } else {
+        Morlet h(f.xi, f.sigma, 0);
+        for (int32_t m = 0; m < L; ++m) hat[m] = h(static_cast<double>(m) / L);
+      }
+      // time (log-frequency) taps by a direct inverse DFT of the closed form
+      std::vector<double> re(L), im(L);
+      double peak = 0.0;
+      for (int32_t d = 0; d < L; ++d) {
+        double sr = 0.0, si = 0.0;
+        for (int32_t m = 0; m < L; ++m) {
+          int32_t e = static_cast<int32_t>((static_cast<int64_t>(m) * d) % L);
+          sr += hat[m] * cs[e];
+          si += hat[m] * sn[e];
+        }
+        re[d] = sr / L;
+        im[d] = si / L;
+        peak = std::max(peak, std::hypot(re[d], im[d]));
+      }
+      const FrFilter& ff = p.frf[g];
+      for (int32_t r = 0; r < ff.M; ++r) {
+        for (int32_t n = 0; n < N1; ++n) {
+          int32_t d = static_cast<int32_t>(((static_cast<int64_t>(r) << f.k) - n) % L);
+          if (d < 0) d += L;
+          size_t idx = static_cast<size_t>(ff.row0 + r) * p.NW + n;
+          p.W[idx] = cfloat{static_cast<float>(re[d]), static_cast<float>(im[d])};
+          tap_mag[idx] = std::hypot(re[d], im[d]) / peak;
+        }
+      }
+    }
+    // algorithmic work: taps above 1e-7 of the filter's peak (the "banded" contraction)
+    p.tap_count.assign(static_cast<size_t>(p.R_pad) * (N1 + 1), 0);
+    for (int32_t r = 0; r < p.R_pad; ++r) {
+      int32_t c = 0;
+      for (int32_t n = 0; n < N1; ++n) {
+        if (tap_mag[static_cast<size_t>(r) * p.NW + n] > 1e-7) ++c;
+        p.tap_count[static_cast<size_t>(r) * (N1 + 1) + n + 1] = c;
+      }
+    }
+    // per 16-row tile, the convex hull of columns with non-negligible taps, in steps of 4
+    const int32_t n_tiles = p.R_pad / 16;
+    p.rt_nrange.assign(static_cast<size_t>(2 * n_tiles), 0);
+    for (int32_t t = 0; t < n_tiles; ++t) {
+      int32_t lo = p.NW, hi = 0;
+      for (int32_t r = t * 16; r < t * 16 + 16; ++r) {
+        for (int32_t n = 0; n < N1; ++n) {
+          if (tap_mag[static_cast<size_t>(r) * p.NW + n] > kTapThresh) {
+            lo = std::min(lo, n);
+            hi = std::max(hi, n + 1);
+          }
+        }
+      }
+      if (hi <= lo) {
+        lo = hi = 0;
+      } else {
+        lo = lo / 4 * 4;
+        hi = static_cast<int32_t>(round_up(hi, 4));
+      }
+      p.rt_nrange[2 * t] = lo;
+      p.rt_nrange[2 * t + 1] = hi;
+    }
+  }
+  for (size_t g = 0; g < p.fr.size(); ++g)
+    p.frf[g].phiF = add_lowpass_time(p, p.frf[g].M, p.sigmaF, p.frf[g].k);
+
+  // ---- workspace arrays (element counts) and row offsets
+  p.z1_off.resize(N1);
+  for (int32_t n1 = 0; n1 < N1; ++n1) {
+    p.z1_off[n1] = p.z1_total;
+    p.z1_total += p.N_pad >> p.psi1[n1].k;
+  }
+  const int32_t nF = p.n_frames;
+  const int32_t n_rt = p.R_pad / 16;
+  for (const Grp& grp : p.groups) {
+    FreqGroup fg{};
+    fg.y2 = p.y2_total;
+    fg.K = grp.K;
+    fg.L2 = static_cast<int32_t>(grp.L2);
+    fg.j2 = grp.j2;
+    fg.s_t = p.log2T - grp.j2;
+    fg.phiT = add_lowpass_time(p, grp.L2, p.sigmaT, grp.j2);
+    fg.TC = static_cast<int32_t>(std::min<int64_t>(grp.L2, 512));
+    fg.n_tc = static_cast<int32_t>(grp.L2 / fg.TC);
+    fg.part = p.part_total;
+    p.part_total += static_cast<int64_t>(fg.n_tc) * p.R_pad * nF;
+    fg.dP = p.dP_total;
+    p.dP_total += static_cast<int64_t>(p.R_pad) * nF;
+    fg.n_tb = static_cast<int32_t>((grp.L2 + 63) / 64);
+    int32_t want = (256 + fg.n_tb - 1) / fg.n_tb;
+    fg.RS = std::max(1, std::min(want, n_rt / 4));
+    fg.rt_per_split = (n_rt + fg.RS - 1) / fg.RS;
+    fg.RS = (n_rt + fg.rt_per_split - 1) / fg.rt_per_split;
+    fg.dYpart = p.dYpart_total;
+    p.dYpart_total += static_cast<int64_t>(fg.RS) * grp.K * grp.L2;
+    p.y2_total += static_cast<int64_t>(grp.K) * grp.L2;
+    p.fgroups.push_back(fg);
+  }
+  for (const FreqGroup& fg : p.fgroups) {
+    for (size_t g = 0; g < p.frf.size(); ++g) {
+      const FrFilter& ff = p.frf[g];
+      p.mac_dense += double(ff.M) * fg.K * fg.L2;
+      p.mac_pool += double(ff.M) * fg.L2 * nF;
+      for (int32_t r = 0; r < ff.M; ++r)
+        p.mac_banded += double(p.tap_count[static_cast<size_t>(ff.row0 + r) * (N1 + 1) + fg.K]) * fg.L2;
+    }
+    for (int32_t t = 0; t < p.R_pad / 16; ++t) {
+      const int32_t lo = p.rt_nrange[2 * t];
+      const int32_t hi = std::min<int32_t>(p.rt_nrange[2 * t + 1], (fg.K + 3) & ~3);
+      if (hi > lo) p.mac_exec += 16.0 * (hi - lo) * fg.L2;
+    }
+  }
+  for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
+    const FreqGroup& fg = p.fgroups[gi];
+    for (int32_t tc = 0; tc < fg.n_tc; ++tc)
+      for (int32_t rb = 0; rb < p.R_pad / 64; ++rb) p.fwd_items.push_back(FwdItem{gi, rb, tc, 0});
+    for (int32_t tb = 0; tb < fg.n_tb; ++tb)
+      for (int32_t rs = 0; rs < fg.RS; ++rs) p.bwd_items.push_back(BwdItem{gi, tb, rs, 0});
+  }
+
+  // ---- row jobs of the time-axis stages, grouped by transform length
+  auto emit = [&](int stage, std::vector<RowJob> js) {
+    std::stable_sort(js.begin(), js.end(), [](const RowJob& a, const RowJob& b) { return a.n > b.n; });
+    size_t i = 0;
+    while (i < js.size()) {
+      size_t j = i;
+      while (j < js.size() && js[j].n == js[i].n) ++j;
+      Launch l{stage, js[i].n, static_cast<int32_t>(p.jobs.size()), static_cast<int32_t>(j - i)};
+      for (size_t q = i; q < j; ++q) p.jobs.push_back(js[q]);
+      if (l.n > 4096) p.scr_elems = std::max<int64_t>(p.scr_elems, int64_t(l.n) * l.njobs);
+      p.launches[stage].push_back(l);
+      i = j;
+    }
+  };
+  auto job = [](int64_t src, int64_t dst, int64_t aux, int32_t band, int32_t src_len, int32_t n, int32_t shift) {
+    RowJob r{};
+    r.src = src;
+    r.dst = dst;
+    r.aux = aux;
+    r.band = band;
+    r.src_len = src_len;
+    r.n = n;
+    r.shift = shift;
+    r.t0 = r.t1 = 0;
+    return r;
+  };
+  const int32_t Np = static_cast<int32_t>(p.N_pad);
+  emit(ST_XHAT, {job(0, 0, 0, -1, Np, Np, 0)});
+  {
+    std::vector<RowJob> a, b;
+    for (int32_t n1 = 0; n1 < N1; ++n1) {
+      int32_t L1 = Np >> p.psi1[n1].k;
+      a.push_back(job(0, p.z1_off[n1], 0, p.band_psi1[n1], Np, L1, p.psi1[n1].k));
+      b.push_back(job(p.z1_off[n1], p.z1_off[n1], 0, -1, L1, L1, 0));
+    }
+    emit(ST_L1Z, a);
+    emit(ST_L1UH, b);
+  }
+  {
+    std::vector<RowJob> a, b;
+    for (size_t gi = 0; gi < p.groups.size(); ++gi) {
+      const Grp& grp = p.groups[gi];
+      const FreqGroup& fg = p.fgroups[gi];
+      for (int32_t n1 = 0; n1 < grp.K; ++n1) {
+        int32_t k1 = p.psi1[n1].k;
+        int32_t L1 = Np >> k1;
+        a.push_back(job(p.z1_off[n1], fg.y2 + int64_t(n1) * fg.L2, 0, p.band_psi2.at({grp.n2, k1}), L1, fg.L2,
+                        grp.j2 - k1));
+        RowJob r = job(fg.dYpart + int64_t(n1) * fg.L2, fg.y2 + int64_t(n1) * fg.L2, int64_t(grp.K) * fg.L2, -1,
+                       fg.L2, fg.L2, 0);
+        r.t0 = fg.RS;
+        b.push_back(r);
+      }
+    }
+    emit(ST_L2Y, a);
+    emit(ST_BYH, b);
+  }
+  {
+    // adjoint gather per n1: second-order terms (dY2hat rows), then the phi_T term (dS1hat)
+    std::vector<RowJob> a, b;
+    const int64_t dS1h_base = p.y2_total;   // dS1hat rows follow the dY2hat stacks
+    for (int32_t n1 = 0; n1 < N1; ++n1) {
+      int32_t k1 = p.psi1[n1].k;
+      int32_t L1 = Np >> k1;
+      RowJob r = job(0, p.z1_off[n1], 0, -1, L1, L1, 0);
+      r.t0 = static_cast<int32_t>(p.terms.size());
+      for (size_t gi = 0; gi < p.groups.size(); ++gi) {
+        const Grp& grp = p.groups[gi];
+        if (n1 >= grp.K) continue;
+        GatherTerm t{p.fgroups[gi].y2 + int64_t(n1) * p.fgroups[gi].L2, p.band_psi2.at({grp.n2, k1}),
+                     p.fgroups[gi].L2};
+        p.terms.push_back(t);
+      }
+      p.terms.push_back(GatherTerm{dS1h_base + int64_t(n1) * p.Lf, p.band_phiT[k1], p.Lf});
+      r.t1 = static_cast<int32_t>(p.terms.size());
+      a.push_back(r);
+      b.push_back(job(p.z1_off[n1], p.z1_off[n1], p.z1_off[n1], -1, L1, L1, 0));
+    }
+    emit(ST_BU, a);
+    emit(ST_BZH, b);
+  }
+  {
+    RowJob r = job(0, 0, 0, -1, Np, Np, 0);
+    r.t0 = static_cast<int32_t>(p.terms.size());
+    for (int32_t n1 = 0; n1 < N1; ++n1)
+      p.terms.push_back(GatherTerm{p.z1_off[n1], p.band_psi1[n1], Np >> p.psi1[n1].k});
+    r.t1 = static_cast<int32_t>(p.terms.size());
+    emit(ST_BX, {r});
+  }
+  p.s1_job0 = static_cast<int32_t>(p.jobs.size());
+  for (int32_t n1 = 0; n1 < N1; ++n1) {
+    int32_t k1 = p.psi1[n1].k;
+    p.jobs.push_back(job(p.z1_off[n1], int64_t(n1) * p.nf_pad, 0, p.band_phiT[k1], Np >> k1, p.Lf, p.log2T - k1));
+  }
+
+  // ---- workspace layout (bytes, 256-aligned regions)
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += (bytes + 255) / 256 * 256;
+    return at;
+  };
+  WsLayout& w = p.ws;
+  w.Xh = take(sizeof(cfloat) * p.N_pad);
+  w.Z1 = take(sizeof(cfloat) * p.z1_total);
+  w.U1h = take(sizeof(cfloat) * p.z1_total);
+  w.S1 = take(sizeof(float) * N1 * p.nf_pad);
+  w.Y2 = take(sizeof(cfloat) * std::max<int64_t>(p.y2_total, 1));
+  w.part = take(sizeof(float) * std::max<int64_t>(p.part_total, 1));
+  w.scr = take(sizeof(cfloat) * std::max<int64_t>(p.scr_elems, 1));
+  w.S = take(sizeof(float) * p.n_coeff);
+  w.dS = take(sizeof(float) * p.n_coeff);
+  w.fwd_end = o;
+  w.dP = take(sizeof(float) * std::max<int64_t>(p.dP_total, 1));
+  w.dYpart = take(sizeof(cfloat) * std::max<int64_t>(p.dYpart_total, 1));
+  w.dYh = take(sizeof(cfloat) * (p.y2_total + int64_t(N1) * p.Lf));
+  w.dS1p = take(sizeof(float) * p.fr_real.size() * N1 * p.nf_pad);
+  w.dU1 = take(sizeof(float) * p.z1_total);
+  w.dZh = take(sizeof(cfloat) * p.z1_total);
+  w.dXh = take(sizeof(cfloat) * p.N_pad);
+  w.grad = take(sizeof(float) * p.N);
+  w.bwd_end = o;
+  return JTFS_OK;
+}
+
+}  // namespace jtfs

@@ -1,0 +1,105 @@
+// Host-side JTFS plan: filterbanks, subsampling rules, path list, output layout,
+// device table images, work lists and workspace layout for one signal.
+// Pure C++17 (no HIP): it runs at jtfs_plan() time on the host.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/jtfs.h"
+#include "types.hpp"
+
+namespace jtfs {
+
+struct cfloat { float x, y; };   // host image of a device float2
+
+struct Filt {
+  double xi, sigma;
+  int32_t j, k, spin;
+  bool lowpass;
+};
+
+struct Grp {
+  int32_t n2, j2, K;
+  int64_t L2;
+};
+
+// Stages of the time-axis pipeline (see kernels_time.hip for what each computes).
+enum Stage : int32_t {
+  ST_XHAT = 0,   // DFT of the zero-padded signal
+  ST_L1Z = 1,    // first-order wavelet: fold-gather of Xhat * psi1, inverse DFT -> Z1
+  ST_L1UH = 2,   // DFT of |Z1| -> U1hat
+  ST_L2Y = 3,    // second-order wavelet: fold-gather of U1hat * psi2^(k1), inverse DFT -> Y2
+  ST_BYH = 4,    // DFT of dY2 (sum of row-split partials) -> dY2hat
+  ST_BU = 5,     // adjoint gather onto U1hat, inverse DFT, real part -> dU1
+  ST_BZH = 6,    // DFT of dU1 * Z1/|Z1| -> dZ1hat
+  ST_BX = 7,     // adjoint gather onto Xhat, inverse DFT, real part, unpad -> dx
+  ST_COUNT = 8
+};
+
+struct Launch {
+  int32_t stage, n, job0, njobs;
+};
+
+// Byte offsets of workspace regions for one signal (relative to the signal's segment).
+struct WsLayout {
+  size_t Xh, Z1, U1h, S1, Y2, part, scr, S, dS;   // forward (+ loss scratch)
+  size_t fwd_end;
+  size_t dP, dYpart, dYh, dS1p, dU1, dZh, dXh, grad;
+  size_t bwd_end;
+};
+
+struct SigPlan {
+  jtfs_params prm{};
+  int64_t N = 0, N_pad = 0, pad_left = 0;
+  int32_t log2T = 0, T = 0, sF = 0, N_fr = 0, nf_pad = 0, f_lo = 0, n_frames = 0, Lf = 0;
+  int32_t log2_Npad = 0;
+  double sigmaT = 0, sigmaF = 0;
+  std::vector<Filt> psi1, psi2, fr;
+  std::vector<int32_t> fr_real;          // frequential filters applied to real inputs
+  std::vector<Grp> groups;
+  std::vector<jtfs_path> paths;
+  int64_t n_coeff = 0;
+
+  // ---- device table images
+  std::vector<cfloat> tw;                // exp(-2 pi i k / N_pad), k < N_pad
+  std::vector<float> bandvals;
+  std::vector<Band> bands;
+  std::vector<int32_t> band_psi1;        // per n1, level 0 on the N_pad grid
+  std::map<std::pair<int, int>, int32_t> band_psi2;   // (n2, level) -> band
+  std::vector<int32_t> band_phiT;        // per level (0..log2T), -1 if unused
+  std::vector<float> tables;             // time-domain phi_T (per group) and phi_F (per g)
+  std::vector<cfloat> W;                 // R_pad x NW frequential Toeplitz rows
+  int32_t NW = 0, R_total = 0, R_pad = 0;
+  std::vector<int32_t> rt_nrange;        // per 16-row tile: n_lo, n_hi (pairs)
+  std::vector<int32_t> tap_count;        // per row: taps above 1e-7 of peak among the first n columns
+  std::vector<FrFilter> frf;
+  std::vector<FreqGroup> fgroups;
+  std::vector<FwdItem> fwd_items;
+  std::vector<BwdItem> bwd_items;
+  std::vector<RowJob> jobs;              // all stages; S1 jobs after the launches
+  std::vector<GatherTerm> terms;
+  std::vector<Launch> launches[ST_COUNT];
+  int32_t s1_job0 = 0;                   // N1 jobs for the S1 stage
+  // forward frequential work, in complex multiply-adds (contraction) and real ones (pooling)
+  double mac_dense = 0, mac_banded = 0, mac_exec = 0, mac_pool = 0;
+  int32_t max_fwd_tiles = 0;
+
+  // ---- workspace
+  std::vector<int64_t> z1_off;           // complex offset of row n1 in Z1 / U1h / dZh (float offset in dU1)
+  int64_t z1_total = 0, y2_total = 0, part_total = 0, dP_total = 0, dYpart_total = 0;
+  int64_t scr_elems = 0;
+  WsLayout ws{};
+};
+
+// Builds the plan of one signal; on failure returns a status and sets `err`.
+jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& out, std::string& err);
+
+// Filterbank generator of Sec. 3.1 and the subsampling-scale rule, exposed for tests.
+std::vector<std::pair<double, double>> wavelet_bank(int J, int Q);
+int32_t subsampling_scale(double xi, double sigma);
+
+}  // namespace jtfs

@@ -1,0 +1,76 @@
+// Plain-old-data records shared by the host plan and the HIP kernels.
+// Every record is built on the host, copied once into the plan's device arena,
+// and read by the kernels; none holds a pointer (only element offsets).
+#pragma once
+#include <cstdint>
+
+namespace jtfs {
+
+// A band-limited Fourier filter on an L-point grid: bins lo, lo+1, ..., lo+len-1
+// (modulo L) hold the non-negligible values, stored contiguously at `off` floats into
+// the plan's band-value array. Filters are real in the Fourier domain (Gaussian
+// spectra), so one float per bin.
+struct Band {
+  int32_t L;
+  int32_t lo;
+  int32_t len;
+  int32_t pad_;
+  int64_t off;
+};
+
+// One row of a batched 1-D transform stage. Field meaning depends on the stage
+// (documented next to each stage in kernels_time.hip).
+struct RowJob {
+  int64_t src;     // element offset of the input
+  int64_t dst;     // element offset of the output
+  int64_t aux;     // stage-specific second input offset
+  int32_t band;    // band index (gather stages) or -1
+  int32_t src_len; // length of the input grid
+  int32_t n;       // transform length (power of two)
+  int32_t shift;   // Fourier subsampling exponent: the fold averages 2^shift blocks
+  int32_t t0, t1;  // term range [t0, t1) for multi-term gathers
+};
+
+// One term of a multi-term adjoint gather: out[m] += band[m] * src[m mod src_len]
+// for bins m of the output grid inside the band.
+struct GatherTerm {
+  int64_t src;
+  int32_t band;
+  int32_t src_len;
+};
+
+// A second-order group (one n2 with K >= 1 rows), frequential stage bookkeeping.
+struct FreqGroup {
+  int64_t y2;       // complex offset of the K x L2 stack in the Y2 region
+  int64_t phiT;     // float offset of phi_T at level j2 (time domain, L2 values)
+  int64_t part;     // float offset of this group's pooled partial sums
+  int64_t dP;       // float offset of this group's pooled-gradient rows
+  int64_t dYpart;   // complex offset of this group's dY2 partials (RS x K x L2)
+  int32_t K, L2, j2, s_t;   // s_t = log2 T - j2 (time pooling stride exponent)
+  int32_t TC, n_tc;         // t-chunk length of the forward and number of chunks
+  int32_t RS, rt_per_split; // backward row splits and row tiles per split
+  int32_t n_tb;             // backward 64-column t-blocks
+  int32_t pad_;
+};
+
+// Forward frequential work item: rows [rb*64, rb*64+64) x columns [tc*TC, (tc+1)*TC).
+struct FwdItem {
+  int32_t grp, rb, tc, pad_;
+};
+
+// Backward frequential work item: columns [tb*64, tb*64+64), row tiles of split rs.
+struct BwdItem {
+  int32_t grp, tb, rs, pad_;
+};
+
+// A frequential filter g as laid out in the row space of the W matrix.
+struct FrFilter {
+  int32_t row0;     // first row of g in W (multiple of 16)
+  int32_t M;        // N_fr / 2^k_g rows carrying data
+  int32_t k;        // k_g
+  int32_t lowpass;  // 1 for phi_F
+  int64_t phiF;     // float offset of phi_F at level k_g (time domain, M values)
+  int32_t spin, pad_;
+};
+
+}  // namespace jtfs

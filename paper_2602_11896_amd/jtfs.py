@@ -1,0 +1,210 @@
+"""Python face of the JTFS library: plans, forward, backward and metamer steps.
+
+Every computation runs in the HIP kernels behind the C ABI (include/jtfs.h); this
+module only marshals arguments. PyTorch supplies device memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Iterable, List, Sequence, Union
+
+import torch
+
+from . import _lib as L
+
+
+@dataclass(frozen=True)
+class Params:
+    """Parameters of one signal (jtfs_params): sample count and filterbank settings."""
+    n: int
+    J: int
+    Q1: int
+    Q2: int
+    J_fr: int
+    Q_fr: int
+    log2_T: int
+    F: float
+    periodic: bool = False
+
+    def c(self) -> L.jtfs_params:
+        return L.jtfs_params(self.n, self.J, self.Q1, self.Q2, self.J_fr, self.Q_fr, self.log2_T, float(self.F),
+                             1 if self.periodic else 0)
+
+
+def _stream(device: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _require(t: torch.Tensor, numel: int, name: str, dtype=torch.float32) -> None:
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} CUDA/HIP tensor")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+class Plan:
+    """A JTFS plan for one or more signals (jtfs_plan)."""
+
+    def __init__(self, params: Union[Params, Sequence[Params]]):
+        plist = [params] if isinstance(params, Params) else list(params)
+        arr = (L.jtfs_params * len(plist))(*[p.c() for p in plist])
+        handle = ctypes.c_void_p()
+        L.check(L.lib().jtfs_plan(arr, len(plist), ctypes.byref(handle)), "jtfs_plan")
+        self._h = handle
+        self._destroy = L.lib().jtfs_plan_destroy
+        self.params = plist
+        info = L.jtfs_plan_info()
+        L.check(L.lib().jtfs_plan_query(self._h, ctypes.byref(info)), "jtfs_plan_query")
+        self.batch = info.batch
+        self.n_samples = info.n_samples_total
+        self.n_coeff = info.n_coeff_total
+        self.ws_forward = info.ws_forward
+        self.ws_backward = info.ws_backward
+        xo = (ctypes.c_int64 * (self.batch + 1))()
+        so = (ctypes.c_int64 * (self.batch + 1))()
+        L.check(L.lib().jtfs_plan_offsets(self._h, xo, so), "jtfs_plan_offsets")
+        self.x_offsets = list(xo)
+        self.s_offsets = list(so)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._destroy(h)
+            self._h = None
+
+    # ---------------------------------------------------------------- introspection
+    def meta(self, signal: int = 0) -> List[dict]:
+        n = ctypes.c_int64()
+        L.check(L.lib().jtfs_plan_meta(self._h, signal, None, 0, ctypes.byref(n)), "jtfs_plan_meta")
+        rows = (L.jtfs_path * n.value)()
+        L.check(L.lib().jtfs_plan_meta(self._h, signal, rows, n.value, ctypes.byref(n)), "jtfs_plan_meta")
+        keys = [f[0] for f in L.jtfs_path._fields_]
+        return [{k: getattr(r, k) for k in keys} for r in rows]
+
+    def filters(self, signal: int, bank: int):
+        n = ctypes.c_int32()
+        L.check(L.lib().jtfs_plan_filters(self._h, signal, bank, None, None, None, None, 0, ctypes.byref(n)),
+                "jtfs_plan_filters")
+        m = n.value
+        xi, sg = (ctypes.c_double * m)(), (ctypes.c_double * m)()
+        j, k = (ctypes.c_int32 * m)(), (ctypes.c_int32 * m)()
+        L.check(L.lib().jtfs_plan_filters(self._h, signal, bank, xi, sg, j, k, m, ctypes.byref(n)),
+                "jtfs_plan_filters")
+        return list(xi), list(sg), list(j), list(k)
+
+    def sizes(self, signal: int = 0) -> dict:
+        out = (ctypes.c_int64 * 8)()
+        L.check(L.lib().jtfs_plan_sizes(self._h, signal, out), "jtfs_plan_sizes")
+        keys = ["N_pad", "pad_left", "N_fr", "s_F", "nf_pad", "f_lo", "n_frames", "n_coeff"]
+        return dict(zip(keys, list(out)))
+
+    def ws_region(self, ws: torch.Tensor, signal: int, which: int, dtype=torch.complex64) -> torch.Tensor:
+        """View of an intermediate left in the workspace by forward (see jtfs_plan_ws_region)."""
+        off, cnt = ctypes.c_int64(), ctypes.c_int64()
+        L.check(L.lib().jtfs_plan_ws_region(self._h, signal, which, ctypes.byref(off), ctypes.byref(cnt)),
+                "jtfs_plan_ws_region")
+        item = torch.empty((), dtype=dtype).element_size()
+        return ws[off.value: off.value + cnt.value * item].view(dtype)
+
+    def cost(self, signal: int = 0) -> dict:
+        """Forward frequential work (see jtfs_plan_cost), in multiply-adds."""
+        out = (ctypes.c_double * 4)()
+        L.check(L.lib().jtfs_plan_cost(self._h, signal, out), "jtfs_plan_cost")
+        return dict(zip(["mac_dense", "mac_banded", "mac_exec", "mac_pool"], list(out)))
+
+    def timing(self, on: bool) -> None:
+        """Bracket every kernel stage with HIP events on the caller's stream (see jtfs.h)."""
+        L.check(L.lib().jtfs_timing_enable(self._h, 1 if on else 0), "jtfs_timing_enable")
+
+    def timing_read(self) -> dict:
+        """{stage name: (total ms, launches)} since the previous read (waits for the events)."""
+        ms = (ctypes.c_double * L.JTFS_N_STAGES)()
+        cnt = (ctypes.c_int64 * L.JTFS_N_STAGES)()
+        L.check(L.lib().jtfs_timing_read(self._h, ms, cnt, L.JTFS_N_STAGES), "jtfs_timing_read")
+        return {L.STAGE_NAMES[i]: (ms[i], cnt[i]) for i in range(L.JTFS_N_STAGES) if cnt[i]}
+
+    def opt_state_floats(self, kind: int) -> int:
+        return int(L.lib().jtfs_opt_state_floats(self._h, kind))
+
+    # ---------------------------------------------------------------- buffers
+    def workspace(self, device="cuda", backward: bool = True) -> torch.Tensor:
+        n = self.ws_backward if backward else self.ws_forward
+        return torch.empty(max(n, 1), dtype=torch.uint8, device=device)
+
+    # ---------------------------------------------------------------- compute
+    def forward(self, x: torch.Tensor, S: torch.Tensor = None, ws: torch.Tensor = None) -> torch.Tensor:
+        _require(x, self.n_samples, "x")
+        if S is None:
+            S = torch.empty(self.n_coeff, dtype=torch.float32, device=x.device)
+        _require(S, self.n_coeff, "S")
+        if ws is None:
+            ws = self.workspace(x.device, backward=False)
+        L.check(L.lib().jtfs_forward(self._h, _ptr(x), _ptr(S), _ptr(ws), ws.numel(), _stream(x.device)),
+                "jtfs_forward")
+        return S
+
+    def backward(self, x: torch.Tensor, dS: torch.Tensor, dx: torch.Tensor = None, ws: torch.Tensor = None,
+                 reuse_forward: bool = False) -> torch.Tensor:
+        _require(x, self.n_samples, "x")
+        _require(dS, self.n_coeff, "dS")
+        if dx is None:
+            dx = torch.empty(self.n_samples, dtype=torch.float32, device=x.device)
+        _require(dx, self.n_samples, "dx")
+        if ws is None:
+            if reuse_forward:
+                raise ValueError("reuse_forward needs the workspace of the preceding forward")
+            ws = self.workspace(x.device)
+        flags = L.JTFS_REUSE_FORWARD if reuse_forward else 0
+        L.check(L.lib().jtfs_backward(self._h, _ptr(x), _ptr(dS), _ptr(dx), _ptr(ws), ws.numel(), flags,
+                                      _stream(x.device)), "jtfs_backward")
+        return dx
+
+    def metamer_step(self, y: torch.Tensor, S_target: torch.Tensor, opt: "Optimizer", loss: torch.Tensor,
+                     ws: torch.Tensor) -> None:
+        _require(y, self.n_samples, "y")
+        _require(S_target, self.n_coeff, "S_target")
+        _require(loss, self.batch, "loss")
+        c = opt.c()
+        L.check(L.lib().jtfs_metamer_step(self._h, _ptr(y), _ptr(S_target), ctypes.byref(c), _ptr(loss), _ptr(ws),
+                                          ws.numel(), _stream(y.device)), "jtfs_metamer_step")
+
+
+class Optimizer:
+    """Descent settings plus the device state buffer of jtfs_opt."""
+
+    def __init__(self, plan: Plan, kind: str = "gd", lr: float = 0.1, momentum: float = 0.9, beta1: float = 0.9,
+                 beta2: float = 0.999, eps: float = 1e-8, bold_up: float = 1.1, bold_down: float = 0.5,
+                 device="cuda"):
+        self.kind = {"gd": L.JTFS_OPT_GD, "momentum": L.JTFS_OPT_MOMENTUM_BOLD, "adam": L.JTFS_OPT_ADAM}[kind]
+        self.lr, self.momentum = lr, momentum
+        self.beta1, self.beta2, self.eps = beta1, beta2, eps
+        self.bold_up, self.bold_down = bold_up, bold_down
+        self.state = torch.zeros(max(plan.opt_state_floats(self.kind), 1), dtype=torch.float32, device=device)
+
+    def c(self) -> L.jtfs_opt:
+        return L.jtfs_opt(self.kind, self.lr, self.momentum, self.beta1, self.beta2, self.eps, self.bold_up,
+                          self.bold_down, ctypes.c_void_p(self.state.data_ptr()))
+
+    def reset(self) -> None:
+        self.state.zero_()
+
+
+# Names of the C ABI, for callers that prefer them.
+jtfs_plan = Plan
+
+
+def jtfs_forward(plan: Plan, x, S=None, ws=None):
+    return plan.forward(x, S, ws)
+
+
+def jtfs_backward(plan: Plan, x, dS, dx=None, ws=None, reuse_forward=False):
+    return plan.backward(x, dS, dx, ws, reuse_forward)
+
+
+def jtfs_metamer_step(plan: Plan, y, S_target, opt: Optimizer, loss, ws):
+    return plan.metamer_step(y, S_target, opt, loss, ws)

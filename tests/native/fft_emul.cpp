@@ -1,0 +1,154 @@
+// Host emulation of the LDS Stockham FFT tile (fft_core.hpp): the 256 threads of a
+// workgroup run sequentially, phase by phase, exactly as the barriers separate them on
+// the GPU. Checks every length 16..4096 in both directions against a direct DFT in FP64,
+// and the two-pass split used for longer transforms.
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "../../paper_2602_11896_amd/csrc/fft_core.hpp"
+
+using namespace jtfs;
+
+static std::vector<c32> twiddles(int log2N) {
+  int N = 1 << log2N;
+  std::vector<c32> tw(N);
+  for (int k = 0; k < N; ++k) {
+    double a = -2.0 * M_PI * k / N;
+    tw[k] = c32{(float)std::cos(a), (float)std::sin(a)};
+  }
+  return tw;
+}
+
+template <int DIR, int LR>
+static void one_pass(std::vector<c32>& lds, int log2n, int log2p, const std::vector<c32>& tw, int log2tw) {
+  const int n = 1 << log2n, tpf = n / 16;
+  std::vector<c32> regs(256 * 16);
+  for (int tid = 0; tid < 256; ++tid)
+    stockham_compute<DIR, LR>(lds.data() + (tid / tpf) * n, log2n, log2p, tid % tpf, tpf, tw.data(), log2tw,
+                              &regs[tid * 16]);
+  for (int tid = 0; tid < 256; ++tid)
+    stockham_store<LR>(lds.data() + (tid / tpf) * n, log2p, tid % tpf, tpf, &regs[tid * 16]);
+}
+
+template <int DIR>
+static void tile_fft(std::vector<c32>& lds, int log2n, const std::vector<c32>& tw, int log2tw) {
+  int lr[8];
+  int np = fft_radices(log2n, lr);
+  int log2p = 0;
+  for (int s = 0; s < np; ++s) {
+    switch (lr[s]) {
+      case 1: one_pass<DIR, 1>(lds, log2n, log2p, tw, log2tw); break;
+      case 2: one_pass<DIR, 2>(lds, log2n, log2p, tw, log2tw); break;
+      case 3: one_pass<DIR, 3>(lds, log2n, log2p, tw, log2tw); break;
+      default: one_pass<DIR, 4>(lds, log2n, log2p, tw, log2tw); break;
+    }
+    log2p += lr[s];
+  }
+}
+
+static double check(int log2n, int dir, const std::vector<c32>& tw, int log2tw) {
+  const int n = 1 << log2n, C = 4096 / n;
+  std::vector<c32> lds(4096);
+  std::vector<double> xr(4096), xi(4096);
+  unsigned s = 12345u + log2n * 7 + dir;
+  for (int e = 0; e < 4096; ++e) {
+    s = s * 1664525u + 1013904223u;
+    xr[e] = ((s >> 8) & 0xffff) / 65536.0 - 0.5;
+    s = s * 1664525u + 1013904223u;
+    xi[e] = ((s >> 8) & 0xffff) / 65536.0 - 0.5;
+    lds[e] = c32{(float)xr[e], (float)xi[e]};
+  }
+  if (dir < 0) tile_fft<-1>(lds, log2n, tw, log2tw);
+  else tile_fft<+1>(lds, log2n, tw, log2tw);
+  double err = 0, ref = 0;
+  for (int c = 0; c < C; ++c)
+    for (int k = 0; k < n; ++k) {
+      double sr = 0, si = 0;
+      for (int j = 0; j < n; ++j) {
+        double a = dir * 2.0 * M_PI * (double)((long long)j * k % n) / n;
+        sr += xr[c * n + j] * std::cos(a) - xi[c * n + j] * std::sin(a);
+        si += xr[c * n + j] * std::sin(a) + xi[c * n + j] * std::cos(a);
+      }
+      double dr = lds[c * n + k].x - sr, di = lds[c * n + k].y - si;
+      err += dr * dr + di * di;
+      ref += sr * sr + si * si;
+    }
+  return std::sqrt(err / ref);
+}
+
+// Reference FFT in FP64 (recursive radix 2).
+static void ref_fft(std::vector<double>& re, std::vector<double>& im, int dir) {
+  const size_t n = re.size();
+  if (n == 1) return;
+  std::vector<double> er(n / 2), ei(n / 2), odr(n / 2), odi(n / 2);
+  for (size_t i = 0; i < n / 2; ++i) {
+    er[i] = re[2 * i]; ei[i] = im[2 * i]; odr[i] = re[2 * i + 1]; odi[i] = im[2 * i + 1];
+  }
+  ref_fft(er, ei, dir);
+  ref_fft(odr, odi, dir);
+  for (size_t k = 0; k < n / 2; ++k) {
+    double a = dir * 2.0 * M_PI * k / n, c = std::cos(a), s = std::sin(a);
+    double tr = odr[k] * c - odi[k] * s, ti = odr[k] * s + odi[k] * c;
+    re[k] = er[k] + tr; im[k] = ei[k] + ti;
+    re[k + n / 2] = er[k] - tr; im[k + n / 2] = ei[k] - ti;
+  }
+}
+
+// Emulates pass 1 and pass 2 workgroups of the two-pass split for one n-point row.
+static double check_split(int log2n, int dir, const std::vector<c32>& tw, int log2tw) {
+  const int n = 1 << log2n;
+  SplitGeom g = split_geom(log2n);
+  std::vector<double> xr(n), xi(n);
+  std::vector<c32> x(n), scr(n), out(n);
+  unsigned s = 777u + log2n;
+  for (int i = 0; i < n; ++i) {
+    s = s * 1664525u + 1013904223u; xr[i] = ((s >> 8) & 0xffff) / 65536.0 - 0.5;
+    s = s * 1664525u + 1013904223u; xi[i] = ((s >> 8) & 0xffff) / 65536.0 - 0.5;
+    x[i] = c32{(float)xr[i], (float)xi[i]};
+  }
+  std::vector<c32> lds(4096);
+  const int A = 1 << g.log2A, B = 1 << g.log2B;
+  for (int n1_0 = 0; n1_0 < A; n1_0 += 1 << g.log2C1) {
+    for (int e = 0; e < 4096; ++e) { int idx, slot; split_p1_load(g, n1_0, e, idx, slot); lds[slot] = x[idx]; }
+    if (dir < 0) tile_fft<-1>(lds, g.log2B, tw, log2tw); else tile_fft<+1>(lds, g.log2B, tw, log2tw);
+    for (int e = 0; e < 4096; ++e) {
+      int slot, sidx, te; split_p1_store(g, n1_0, e, slot, sidx, te);
+      c32 w = tw[(size_t)te << (log2tw - log2n)];
+      if (dir > 0) w.y = -w.y;
+      scr[sidx] = cmul(lds[slot], w);
+    }
+  }
+  for (int k2_0 = 0; k2_0 < B; k2_0 += 1 << g.log2C2) {
+    for (int e = 0; e < 4096; ++e) lds[e] = scr[split_p2_load(g, k2_0, e)];
+    if (dir < 0) tile_fft<-1>(lds, g.log2A, tw, log2tw); else tile_fft<+1>(lds, g.log2A, tw, log2tw);
+    for (int e = 0; e < 4096; ++e) { int slot, oidx; split_p2_store(g, k2_0, e, slot, oidx); out[oidx] = lds[slot]; }
+  }
+  ref_fft(xr, xi, dir);
+  double err = 0, ref = 0;
+  for (int k = 0; k < n; ++k) {
+    double dr = out[k].x - xr[k], di = out[k].y - xi[k];
+    err += dr * dr + di * di; ref += xr[k] * xr[k] + xi[k] * xi[k];
+  }
+  return std::sqrt(err / ref);
+}
+
+int main() {
+  const int log2tw = 17;
+  auto tw = twiddles(log2tw);
+  int bad = 0;
+  for (int log2n = 4; log2n <= 12; ++log2n)
+    for (int dir : {-1, 1}) {
+      double e = check(log2n, dir, tw, log2tw);
+      std::printf("n=%6d dir=%+d rel_l2=%.3e\n", 1 << log2n, dir, e);
+      if (!(e < 2e-6)) bad = 1;
+    }
+  for (int log2n = 13; log2n <= 17; ++log2n)
+    for (int dir : {-1, 1}) {
+      double e = check_split(log2n, dir, tw, log2tw);
+      std::printf("split n=%6d dir=%+d rel_l2=%.3e\n", 1 << log2n, dir, e);
+      if (!(e < 3e-6)) bad = 1;
+    }
+  std::printf(bad ? "FAIL\n" : "OK\n");
+  return bad;
+}

@@ -1,0 +1,265 @@
+"""GPU parity of the HIP path against the FP64 oracle (run on an MI355X).
+
+Tolerances (FP32 path vs FP64 oracle): relative L2 error <= 1e-5 on S(x) and on the
+first-layer / second-layer intermediates, <= 1e-4 on the gradient dx.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import jtfs_inputs as ji
+from oracle import descent, fftroute
+from oracle.plan import make_plan
+
+pytestmark = pytest.mark.gpu
+
+J = pytest.importorskip("paper_2602_11896_amd.jtfs")
+
+TOL_S = 1e-5
+TOL_GRAD = 1e-4
+
+TINY = (512, 4, 4, 1, 2, 1, 5, 2)
+TINY_B = (384, 4, 3, 2, 2, 2, 4, 3)
+CFG1 = (8192, 6, 8, 1, 3, 1, 9, 4)
+CFG2 = (65536, 12, 12, 2, 4, 2, 13, 24)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    """Relative L2 error of a against b (complex arrays compared in both parts)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    dt = np.complex128 if (np.iscomplexobj(a) or np.iscomplexobj(b)) else np.float64
+    a, b = a.astype(dt), b.astype(dt)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float32), device="cuda").contiguous()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    a = t.detach().cpu().numpy()
+    return a.astype(np.complex128 if np.iscomplexobj(a) else np.float64)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def run_forward(args, x, periodic=False):
+    plan = J.Plan(J.Params(*args, periodic=periodic))
+    ws = plan.workspace()
+    S = plan.forward(dev(x), ws=ws)
+    return plan, ws, S
+
+
+@pytest.mark.parametrize("name,args,periodic", [("tiny", TINY, False), ("tiny_b", TINY_B, False),
+                                                ("periodic", (1024, 4, 4, 2, 2, 2, 5, 2), True),
+                                                ("cfg1", CFG1, False)])
+def test_forward_and_intermediates(name, args, periodic):
+    say(f"[parity] forward {name} {args}")
+    op = make_plan(*args, periodic=periodic)
+    x = ji.config1_signal(0, n=op.N) if not periodic else np.random.default_rng(9).standard_normal(op.N)
+    plan, ws, S = run_forward(args, x, periodic)
+    S_ref, cache = fftroute.forward(op, x, return_cache=True)
+    Z1 = host(plan.ws_region(ws, 0, 0))
+    U1h = host(plan.ws_region(ws, 0, 1))
+    S1 = host(plan.ws_region(ws, 0, 2, torch.float32)).reshape(op.N1, op.nf_pad)
+    Y2 = host(plan.ws_region(ws, 0, 3))
+    off = 0
+    for n1 in range(op.N1):
+        L = cache["Z1"][n1].shape[0]
+        assert rel(Z1[off:off + L], cache["Z1"][n1]) <= TOL_S, f"Z1 row {n1}"
+        assert rel(U1h[off:off + L], cache["U1h"][n1]) <= TOL_S, f"U1hat row {n1}"
+        off += L
+    assert rel(S1, cache["S1"]) <= TOL_S
+    off = 0
+    for grp in op.groups:
+        Yr = fftroute.second_layer_group(op, grp, cache["U1h"], cache["fc"])[:grp.K]
+        n = Yr.size
+        assert rel(Y2[off:off + n].reshape(Yr.shape), Yr) <= TOL_S, f"Y2 group n2={grp.n2}"
+        off += n
+    Sg = host(S)
+    for blk in op.blocks:
+        a = Sg[blk.offset: blk.offset + blk.n_lambda * blk.n_frames]
+        b = S_ref[blk.offset: blk.offset + blk.n_lambda * blk.n_frames]
+        assert rel(a, b) <= 10 * TOL_S, f"block order={blk.order} n2={blk.n2} n_fr={blk.n_fr}: {rel(a, b)}"
+    err = rel(Sg, S_ref)
+    say(f"[parity] forward {name}: rel L2 {err:.3e}")
+    assert err <= TOL_S
+
+
+@pytest.mark.parametrize("name,args", [("tiny", TINY), ("tiny_b", TINY_B), ("cfg1", CFG1)])
+def test_backward(name, args):
+    say(f"[parity] backward {name} {args}")
+    op = make_plan(*args)
+    x = ji.config1_signal(0, n=op.N)
+    y = ji.white_noise_like(x, 1)
+    S_x = fftroute.forward(op, x)
+    S_y, cache = fftroute.forward(op, y, return_cache=True)
+    dS = 2.0 * (S_y - S_x)
+    g_ref = fftroute.backward(op, y, dS, cache=cache)
+    plan = J.Plan(J.Params(*args))
+    ws = plan.workspace()
+    dx = plan.backward(dev(y), dev(dS), ws=ws)
+    err = rel(host(dx), g_ref)
+    say(f"[parity] backward {name}: rel L2 {err:.3e}")
+    assert err <= TOL_GRAD
+    # reuse of the forward intermediates gives the same gradient bit for bit
+    yd = dev(y)
+    plan.forward(yd, ws=ws)
+    dx2 = plan.backward(yd, dev(dS), ws=ws, reuse_forward=True)
+    assert torch.equal(dx, dx2)
+
+
+def test_config2_sampled_forward_and_backward():
+    # Full config-2 size; the oracle computes the order-1 blocks and a few second-order
+    # groups (short and long ones), and the gradient of a loss restricted to them.
+    say("[parity] config 2 sampled")
+    op = make_plan(*CFG2)
+    x = ji.config2_signal(2)
+    n2s = [op.groups[0].n2, op.groups[-3].n2, op.groups[-1].n2]
+    S_ref = fftroute.forward_partial(op, x, n2s)
+    plan, ws, S = run_forward(CFG2, x)
+    Sg = host(S)
+    mask = ~np.isnan(S_ref)
+    err = rel(Sg[mask], S_ref[mask])
+    say(f"[parity] config 2 forward sampled ({mask.sum()} coefficients): rel L2 {err:.3e}")
+    assert err <= TOL_S
+    rng = np.random.default_rng(4)
+    dS = np.where(mask, rng.standard_normal(op.n_coeff), 0.0)
+    g_ref = fftroute.backward(op, x, dS)
+    dx = plan.backward(dev(x), dev(dS), ws=ws, reuse_forward=True)
+    err = rel(host(dx), g_ref)
+    say(f"[parity] config 2 backward sampled: rel L2 {err:.3e}")
+    assert err <= TOL_GRAD
+
+
+def test_forward_is_deterministic():
+    say("[parity] determinism cfg1")
+    x = dev(ji.config1_signal(0))
+    plan = J.Plan(J.Params(*CFG1))
+    ws = plan.workspace()
+    a = plan.forward(x, ws=ws).clone()
+    b = plan.forward(x, ws=ws).clone()
+    dS = torch.ones_like(a)
+    g1 = plan.backward(x, dS, ws=ws).clone()
+    g2 = plan.backward(x, dS, ws=ws).clone()
+    assert torch.equal(a, b) and torch.equal(g1, g2)
+
+
+def test_homogeneity_and_zero_input():
+    say("[parity] homogeneity cfg1")
+    x = ji.config1_signal(0)
+    plan = J.Plan(J.Params(*CFG1))
+    ws = plan.workspace()
+    S = host(plan.forward(dev(x), ws=ws))
+    S3 = host(plan.forward(dev(-3.0 * x), ws=ws))
+    assert rel(S3, 3.0 * S) <= 1e-6
+    S0 = host(plan.forward(dev(np.zeros_like(x)), ws=ws))
+    assert np.all(S0 == 0.0)
+    g0 = host(plan.backward(dev(np.zeros_like(x)), dev(np.ones(plan.n_coeff)), ws=ws))
+    assert np.all(g0 == 0.0)
+
+
+def test_euler_identity_config2():
+    # <y, J^T dS> = <S(y), dS> for the degree-1 homogeneous transform, at full size.
+    say("[parity] Euler identity cfg2")
+    y = ji.config2_signal(3)
+    plan = J.Plan(J.Params(*CFG2))
+    ws = plan.workspace()
+    yd = dev(y)
+    S = host(plan.forward(yd, ws=ws))
+    dS = np.random.default_rng(1).standard_normal(plan.n_coeff)
+    g = host(plan.backward(yd, dev(dS), ws=ws, reuse_forward=True))
+    lhs, rhs = float(np.dot(y, g)), float(np.dot(S, dS))
+    say(f"[parity] Euler cfg2: {lhs:.8e} vs {rhs:.8e}")
+    assert abs(lhs - rhs) <= 1e-5 * abs(rhs) + 1e-6 * np.linalg.norm(y) * np.linalg.norm(g)
+
+
+def test_metamer_gd_trajectory_config1():
+    # Config 1: 20 gradient-descent steps (step 0.1) from white noise, per-step losses.
+    say("[parity] metamer GD trajectory cfg1")
+    op = make_plan(*CFG1)
+    x = ji.config1_signal(0)
+    y0 = ji.white_noise_like(x, 1)
+    S_x = fftroute.forward(op, x)
+    _, losses_ref = descent.metamer(op, S_x, y0, descent.OptState("gd", lr=0.1), 20)
+    plan = J.Plan(J.Params(*CFG1))
+    ws = plan.workspace()
+    opt = J.Optimizer(plan, "gd", lr=0.1)
+    y = dev(y0)
+    St = dev(S_x)
+    loss = torch.zeros(1, device="cuda")
+    got = []
+    for _ in range(20):
+        plan.metamer_step(y, St, opt, loss, ws)
+        got.append(float(host(loss)[0]))
+    err = max(abs(a - b) / abs(b) for a, b in zip(got, losses_ref))
+    say(f"[parity] GD losses max rel err {err:.3e} (first {got[0]:.6e}, last {got[-1]:.6e})")
+    assert err <= 1e-3
+
+
+@pytest.mark.parametrize("kind", ["adam", "momentum"])
+def test_metamer_optimisers_tiny(kind):
+    say(f"[parity] metamer {kind} tiny")
+    op = make_plan(*TINY)
+    x = ji.config1_signal(0, n=op.N)
+    y0 = ji.white_noise_like(x, 1)
+    S_x = fftroute.forward(op, x)
+    st = descent.OptState(kind, lr=0.1 if kind == "adam" else 2000.0)
+    y_ref, losses_ref = descent.metamer(op, S_x, y0, st, 8)
+    plan = J.Plan(J.Params(*TINY))
+    ws = plan.workspace()
+    opt = J.Optimizer(plan, kind, lr=0.1 if kind == "adam" else 2000.0)
+    y = dev(y0)
+    St = dev(S_x)
+    loss = torch.zeros(1, device="cuda")
+    got = []
+    for _ in range(8):
+        plan.metamer_step(y, St, opt, loss, ws)
+        got.append(float(host(loss)[0]))
+    err = max(abs(a - b) / abs(b) for a, b in zip(got, losses_ref))
+    say(f"[parity] {kind} losses max rel err {err:.3e}; ref {losses_ref[0]:.4e} -> {losses_ref[-1]:.4e}")
+    assert err <= 1e-3
+    assert rel(host(y), y_ref) <= 1e-3
+
+
+def test_nonfinite_loss_leaves_signal():
+    say("[parity] non-finite step")
+    plan = J.Plan(J.Params(*TINY))
+    ws = plan.workspace()
+    opt = J.Optimizer(plan, "momentum", lr=0.1)
+    y = dev(np.random.default_rng(2).standard_normal(TINY[0]))
+    y[7] = float("nan")
+    before = y.clone()
+    loss = torch.zeros(1, device="cuda")
+    plan.metamer_step(y, torch.zeros(plan.n_coeff, device="cuda"), opt, loss, ws)
+    torch.cuda.synchronize()
+    assert not math.isfinite(float(loss[0]))
+    assert torch.equal(torch.isnan(y), torch.isnan(before))
+    assert torch.equal(y[~torch.isnan(y)], before[~torch.isnan(before)])
+
+
+def test_batched_plan_matches_single():
+    say("[parity] batch of two signals")
+    a, b = TINY, TINY_B
+    xa = ji.config1_signal(0, n=a[0])
+    xb = ji.config1_signal(5, n=b[0])
+    plan = J.Plan([J.Params(*a), J.Params(*b)])
+    S = host(plan.forward(dev(np.concatenate([xa, xb])), ws=plan.workspace()))
+    Sa = fftroute.forward(make_plan(*a), xa)
+    Sb = fftroute.forward(make_plan(*b), xb)
+    assert rel(S[: Sa.size], Sa) <= TOL_S
+    assert rel(S[Sa.size:], Sb) <= TOL_S

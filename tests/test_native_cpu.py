@@ -1,0 +1,109 @@
+"""CPU tests of the native library: exports, plan parity with the oracle, error paths,
+and a host emulation of the FFT kernels' index logic. No device work is launched."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle.plan import make_plan
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "jtfs.h")
+
+J = pytest.importorskip("paper_2602_11896_amd.jtfs")
+from paper_2602_11896_amd import _lib as L  # noqa: E402
+
+CONFIGS = {
+    "tiny": (512, 4, 4, 1, 2, 1, 5, 2, False),
+    "tiny_b": (384, 4, 3, 2, 2, 2, 4, 3, False),
+    "periodic": (1024, 4, 4, 2, 2, 2, 5, 2, True),
+    "cfg1": (8192, 6, 8, 1, 3, 1, 9, 4, False),
+    "cfg2": (65536, 12, 12, 2, 4, 2, 13, 24, False),
+    "cfg4": (65536, 6, 8, 1, 3, 1, 9, 4, False),
+    "cfg5": (1 << 20, 14, 16, 2, 5, 2, 14, 32, False),
+}
+
+
+def test_library_exports_every_declared_function():
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\*?\s+\**(jtfs_[a-z_]+)\s*\(", text, re.M))
+    assert {"jtfs_plan", "jtfs_forward", "jtfs_backward", "jtfs_metamer_step"} <= declared
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert {s[0] for s in L.SIGNATURES} == declared
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_plan_matches_oracle_plan(name):
+    args = CONFIGS[name]
+    op = make_plan(*args[:8], periodic=args[8])
+    p = J.Plan(J.Params(*args))
+    for bank, ref in ((0, op.psi1), (1, op.psi2), (2, op.fr)):
+        xi, sg, j, k = p.filters(0, bank)
+        assert len(xi) == len(ref)
+        assert np.allclose(xi, [b.xi for b in ref], rtol=1e-15, atol=0)
+        assert np.allclose(sg, [b.sigma for b in ref], rtol=1e-15, atol=0)
+        assert j == [b.j for b in ref]
+        if bank != 1:
+            assert k == [b.k for b in ref]
+    sz = p.sizes()
+    assert (sz["N_pad"], sz["pad_left"], sz["N_fr"], sz["s_F"]) == (op.N_pad, op.pad_left, op.N_fr, op.s_F)
+    assert (sz["nf_pad"], sz["f_lo"], sz["n_frames"], sz["n_coeff"]) == (op.nf_pad, op.f_lo, op.n_frames, op.n_coeff)
+    rows = p.meta()
+    assert len(rows) == len(op.blocks)
+    for r, b in zip(rows, op.blocks):
+        assert (r["order"], r["n2"], r["n_fr"], r["spin"], r["j2"], r["j_fr"], r["n_lambda"], r["n_frames"],
+                r["offset"]) == (b.order, b.n2, b.n_fr, b.spin, b.j2, b.j_fr, b.n_lambda, b.n_frames, b.offset)
+
+
+def test_batch_offsets():
+    a, b = CONFIGS["tiny"], CONFIGS["cfg1"]
+    p = J.Plan([J.Params(*a), J.Params(*b), J.Params(*a)])
+    na, nb = a[0], b[0]
+    ca, cb = make_plan(*a[:8]).n_coeff, make_plan(*b[:8]).n_coeff
+    assert p.x_offsets == [0, na, na + nb, 2 * na + nb]
+    assert p.s_offsets == [0, ca, ca + cb, 2 * ca + cb]
+    assert p.ws_forward < p.ws_backward
+
+
+@pytest.mark.parametrize("bad,status", [
+    ((1, 4, 4, 1, 2, 1, 5, 2, False), L.JTFS_ERR_ARG),            # n < 2
+    ((512, 4, 0, 1, 2, 1, 5, 2, False), L.JTFS_ERR_ARG),          # Q1 = 0
+    ((512, 4, 4, 1, 2, 1, 5, 0.5, False), L.JTFS_ERR_ARG),        # F < 1
+    ((500, 4, 4, 1, 2, 1, 5, 2, True), L.JTFS_ERR_ARG),           # periodic, not a power of two
+    ((512, 4, 4, 1, 2, 1, 12, 2, False), L.JTFS_ERR_ARG),         # T beyond the padded length
+    ((512, 8, 4, 1, 2, 1, 2, 2, False), L.JTFS_ERR_UNSUPPORTED),  # second order coarser than T
+])
+def test_plan_rejects(bad, status):
+    with pytest.raises(L.JTFSError) as e:
+        J.Plan(J.Params(*bad))
+    assert e.value.status == status
+
+
+def test_host_side_argument_errors():
+    lib = L.lib()
+    p = J.Plan(J.Params(*CONFIGS["tiny"]))
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.jtfs_forward(p._h, fake, fake, fake, 16, None) == L.JTFS_ERR_WORKSPACE
+    assert lib.jtfs_forward(p._h, None, fake, fake, p.ws_forward, None) == L.JTFS_ERR_ARG
+    assert lib.jtfs_backward(p._h, fake, fake, fake, fake, p.ws_forward, 0, None) == L.JTFS_ERR_WORKSPACE
+    assert lib.jtfs_backward(p._h, fake, fake, fake, fake, p.ws_backward, 8, None) == L.JTFS_ERR_ARG
+    opt = L.jtfs_opt(7, 0.1, 0.9, 0.9, 0.999, 1e-8, 1.1, 0.5, fake)
+    assert lib.jtfs_metamer_step(p._h, fake, fake, ctypes.byref(opt), fake, fake, p.ws_backward, None) == L.JTFS_ERR_ARG
+    assert lib.jtfs_opt_state_floats(p._h, 2) == 2 * 512 + 4
+    assert b"workspace" in lib.jtfs_status_str(L.JTFS_ERR_WORKSPACE)
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_fft_tile_index_logic_host_emulation(tmp_path):
+    exe = tmp_path / "fft_emul"
+    subprocess.run(["g++", "-std=c++17", "-O2", "-o", str(exe), os.path.join(ROOT, "tests", "native", "fft_emul.cpp")],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.strip().endswith("OK")
