@@ -37,6 +37,7 @@ struct SigTables {
   const jtfs::FwdItem* fwd_items;
   const jtfs::BwdItem* bwd_items;
   const jtfs::RowJob* jobs;
+  const jtfs::RowTask* tasks;
   const jtfs::GatherTerm* terms;
   const int64_t* s_off;
 };
@@ -117,6 +118,7 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     append_bytes(buf, o, sp.jobs);
     append_bytes(buf, o, sp.terms);
     append_bytes(buf, o, p->block_off[s]);
+    append_bytes(buf, o, sp.tasks);
   }
   DeviceArena a;
   if (hipMalloc(&a.base, buf.size() + 256) != hipSuccess) return fail(JTFS_ERR_NOMEM, "hipMalloc of plan tables failed");
@@ -141,6 +143,7 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     t.jobs = reinterpret_cast<const jtfs::RowJob*>(b + o[10]);
     t.terms = reinterpret_cast<const jtfs::GatherTerm*>(b + o[11]);
     t.s_off = reinterpret_cast<const int64_t*>(b + o[12]);
+    t.tasks = reinterpret_cast<const jtfs::RowTask*>(b + o[13]);
     a.sig.push_back(t);
   }
   auto ins = p->dev.emplace(dev, std::move(a));
@@ -164,6 +167,7 @@ jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void
   d.fwd_items = t.fwd_items;
   d.bwd_items = t.bwd_items;
   d.jobs = t.jobs;
+  d.tasks = t.tasks;
   d.terms = t.terms;
   d.s_off = t.s_off;
   d.Xh = reinterpret_cast<jtfs::c32*>(base + w.Xh);
@@ -179,6 +183,7 @@ jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void
   d.dS1p = reinterpret_cast<float*>(base + w.dS1p);
   d.dU1 = reinterpret_cast<float*>(base + w.dU1);
   d.dZh = reinterpret_cast<jtfs::c32*>(base + w.dZh);
+  d.o1 = reinterpret_cast<jtfs::c32*>(base + w.o1);
   d.N = static_cast<int32_t>(sp.N);
   d.N_pad = static_cast<int32_t>(sp.N_pad);
   d.pad_left = static_cast<int32_t>(sp.pad_left);
@@ -253,6 +258,7 @@ jtfs_status backward_signal(jtfs_plan_t p, const jtfs::DevSig& d, const jtfs::Si
   }
   STAGE(8, jtfs::run_freq_dP(d, sp, st));
   STAGE(9, jtfs::run_freq_bwd(d, sp, st));
+  STAGE(9, jtfs::run_dy_reduce(d, sp, st));
   STAGE(10, jtfs::run_order1_bwd(d, sp, st));
   STAGE(11, jtfs::run_ds1h(d, sp, st));
   STAGE(12, jtfs::run_time_stage(jtfs::ST_BYH, d, sp, st));

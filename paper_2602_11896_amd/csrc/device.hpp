@@ -20,6 +20,7 @@ struct DevSig {
   const FwdItem* fwd_items;
   const BwdItem* bwd_items;
   const RowJob* jobs;
+  const RowTask* tasks;
   const GatherTerm* terms;
   const int64_t* s_off;     // output offset of block (group gi, filter g) at gi*n_g + g;
                             // order-1 blocks at n_groups*n_g + (index in the real list)
@@ -42,6 +43,7 @@ struct DevSig {
   float* dS1p;
   float* dU1;
   c32* dZh;
+  c32* o1;                  // order-1 modulus / gradient rows (R_pad x nF)
   // ---- sizes
   int32_t N, N_pad, pad_left, log2_Npad;
   int32_t N1, nf_pad, f_lo, nF, Lf, log2T, N_fr, sF;

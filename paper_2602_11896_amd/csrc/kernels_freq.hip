@@ -15,6 +15,8 @@
 //   A[i][k] from lane l, B[k][i] from lane l, D[4k + v][i] in element v of lane l.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
@@ -158,104 +160,129 @@ __global__ __launch_bounds__(256) void k_freq_pool(DevSig s) {
 }
 
 // ------------------------------------------------------------------ order 1 (alpha = 0)
-// Frequential filters on S1 (real): V = W_g S1 over kept frames; band-pass: |V| then
-// phi_F averaging; phi_F itself: V (already averaged along both axes, Eq. 3).
-__global__ __launch_bounds__(256) void k_order1_fwd(DevSig s) {
-  __shared__ float U[8192];
-  const int g = blockIdx.x;
-  const FrFilter ff = s.frf[g];
-  const int nF = s.nF, N1 = s.N1;
-  const int nb = (N1 + (1 << s.sF) - 1) >> s.sF;
-  float* out = s.S + s.s_off[s.n_groups * s.n_g + g];
-  const int Mrows = ff.lowpass ? nb : ff.M;
-  const int fw = max(1, min(nF, 8192 / Mrows));
-  const int sh = s.sF - ff.k;
-  const float* ph = s.tables + ff.phiF;
-  for (int f0 = 0; f0 < nF; f0 += fw) {
-    const int fc = min(fw, nF - f0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < Mrows * fc; e += 256) {
-      const int r = e / fc, fl = e - r * fc;
-      const c32* w = s.W + static_cast<int64_t>(ff.row0 + r) * s.NW;
-      const float* x = s.S1 + s.f_lo + f0 + fl;
-      float vr = 0.f, vi = 0.f;
-      for (int n = 0; n < N1; ++n) {
-        const float a = x[static_cast<int64_t>(n) * s.nf_pad];
-        vr += w[n].x * a;
-        vi += w[n].y * a;
-      }
-      U[r * fc + fl] = ff.lowpass ? vr : sqrtf(vr * vr + vi * vi);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nb * fc; e += 256) {
-      const int b = e / fc, fl = e - b * fc;
-      float v;
-      if (ff.lowpass) {
-        v = U[b * fc + fl];
-      } else {
-        float acc = 0.f;
-        for (int r = 0; r < ff.M; ++r) acc += ph[((b << sh) - r) & (ff.M - 1)] * U[r * fc + fl];
-        v = acc;
-      }
-      out[b * nF + f0 + fl] = v;
-    }
+// Frequential filters of the real list on S1 (kept frames only): V = W_g S1; the
+// band-pass paths keep |V| for phi_F averaging, phi_F itself keeps V (Eq. 3 has no
+// modulus). One thread per (row of the real list, frame); rows of other filters and
+// padding rows are written as zero.
+__device__ inline int real_filter_of_row(const DevSig& s, int row) {
+  for (int q = 0; q < s.n_real; ++q) {
+    const FrFilter c = s.frf[q];
+    if (row >= c.row0 && row < c.row0 + c.M) return q;
   }
+  return -1;
 }
 
-// Adjoint of the order-1 paths: per filter g, the contribution to dS1 (N1 x nf_pad,
-// zero outside the kept frames), written to its own slice of dS1p (summed later in
-// a fixed order).
-__global__ __launch_bounds__(256) void k_order1_bwd(DevSig s) {
-  __shared__ c32 dV[4096];
-  const int g = blockIdx.x;
-  const FrFilter ff = s.frf[g];
-  const int nF = s.nF, N1 = s.N1;
-  const int nb = (N1 + (1 << s.sF) - 1) >> s.sF;
-  const float* dout = s.dS + s.s_off[s.n_groups * s.n_g + g];
-  float* dst = s.dS1p + static_cast<int64_t>(g) * N1 * s.nf_pad;
-  const int Mrows = ff.lowpass ? nb : ff.M;
-  const int fw = max(1, min(nF, 4096 / Mrows));
-  const int sh = s.sF - ff.k;
-  const float* ph = s.tables + ff.phiF;
-  for (int e = threadIdx.x; e < N1 * s.nf_pad; e += 256) {
-    const int f = e % s.nf_pad;
-    if (f < s.f_lo || f >= s.f_lo + nF) dst[e] = 0.f;
+__device__ inline c32 order1_v(const DevSig& s, int row, int f) {
+  const c32* w = s.W + static_cast<int64_t>(row) * s.NW;
+  const float* x = s.S1 + s.f_lo + f;
+  float vr = 0.f, vi = 0.f;
+  for (int n = 0; n < s.N1; ++n) {
+    const float a = x[static_cast<int64_t>(n) * s.nf_pad];
+    vr += w[n].x * a;
+    vi += w[n].y * a;
   }
-  for (int f0 = 0; f0 < nF; f0 += fw) {
-    const int fc = min(fw, nF - f0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < Mrows * fc; e += 256) {
-      const int r = e / fc, fl = e - r * fc;
-      c32 d{0.f, 0.f};
-      if (ff.lowpass) {
-        d.x = dout[r * nF + f0 + fl];
-      } else {
-        float du = 0.f;
-        for (int b = 0; b < nb; ++b) du += ph[((b << sh) - r) & (ff.M - 1)] * dout[b * nF + f0 + fl];
-        const c32* w = s.W + static_cast<int64_t>(ff.row0 + r) * s.NW;
-        const float* x = s.S1 + s.f_lo + f0 + fl;
-        float vr = 0.f, vi = 0.f;
-        for (int n = 0; n < N1; ++n) {
-          const float a = x[static_cast<int64_t>(n) * s.nf_pad];
-          vr += w[n].x * a;
-          vi += w[n].y * a;
-        }
-        const float m = sqrtf(vr * vr + vi * vi);
-        if (m > 0.f) d = c32{du * (vr / m), du * (vi / m)};
-      }
-      dV[r * fc + fl] = d;
+  return c32{vr, vi};
+}
+
+__global__ __launch_bounds__(256) void k_o1_v(DevSig s) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= s.R_pad * s.nF) return;
+  const int row = e / s.nF, f = e - row * s.nF;
+  const int g = real_filter_of_row(s, row);
+  float u = 0.f;
+  if (g >= 0) {
+    const c32 v = order1_v(s, row, f);
+    u = s.frf[g].lowpass ? v.x : sqrtf(v.x * v.x + v.y * v.y);
+  }
+  s.o1[e] = c32{u, 0.f};
+}
+
+// phi_F averaging along log-frequency and unpadding of the order-1 paths.
+__global__ __launch_bounds__(256) void k_o1_pool(DevSig s) {
+  const int g = blockIdx.y;
+  const FrFilter ff = s.frf[g];
+  const int nF = s.nF;
+  const int nb = (s.N1 + (1 << s.sF) - 1) >> s.sF;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nb * nF) return;
+  const int b = e / nF, f = e - b * nF;
+  float v;
+  if (ff.lowpass) {
+    v = s.o1[(ff.row0 + b) * nF + f].x;
+  } else {
+    const int sh = s.sF - ff.k;
+    const float* ph = s.tables + ff.phiF;
+    v = 0.f;
+    for (int r = 0; r < ff.M; ++r) v += ph[((b << sh) - r) & (ff.M - 1)] * s.o1[(ff.row0 + r) * nF + f].x;
+  }
+  s.S[s.s_off[s.n_groups * s.n_g + g] + e] = v;
+}
+
+// Adjoint of the order-1 paths, step 1: per (row, frame) the gradient of V.
+__global__ __launch_bounds__(256) void k_o1_dv(DevSig s) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= s.R_pad * s.nF) return;
+  const int nF = s.nF;
+  const int row = e / nF, f = e - row * nF;
+  const int g = real_filter_of_row(s, row);
+  c32 d{0.f, 0.f};
+  if (g >= 0) {
+    const FrFilter ff = s.frf[g];
+    const int r = row - ff.row0;
+    const int nb = (s.N1 + (1 << s.sF) - 1) >> s.sF;
+    const float* dout = s.dS + s.s_off[s.n_groups * s.n_g + g];
+    if (ff.lowpass) {
+      d.x = r < nb ? dout[r * nF + f] : 0.f;
+    } else {
+      const int sh = s.sF - ff.k;
+      const float* ph = s.tables + ff.phiF;
+      float du = 0.f;
+      for (int b = 0; b < nb; ++b) du += ph[((b << sh) - r) & (ff.M - 1)] * dout[b * nF + f];
+      const c32 v = order1_v(s, row, f);
+      const float m = sqrtf(v.x * v.x + v.y * v.y);
+      if (m > 0.f) d = c32{du * (v.x / m), du * (v.y / m)};
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < N1 * fc; e += 256) {
-      const int n = e / fc, fl = e - n * fc;
-      float acc = 0.f;
-      for (int r = 0; r < Mrows; ++r) {
-        const c32 w = s.W[static_cast<int64_t>(ff.row0 + r) * s.NW + n];
-        const c32 d = dV[r * fc + fl];
-        acc += w.x * d.x + w.y * d.y;
-      }
-      dst[static_cast<int64_t>(n) * s.nf_pad + s.f_lo + f0 + fl] = acc;
+  }
+  s.o1[e] = d;
+}
+
+// Step 2: dS1 contribution of filter g, Re(W_g^H dV), on every padded frame (zero
+// outside the kept ones); summed over g in a fixed order later.
+__global__ __launch_bounds__(256) void k_o1_ds1(DevSig s) {
+  const int g = blockIdx.y;
+  const FrFilter ff = s.frf[g];
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= s.N1 * s.nf_pad) return;
+  const int n = e / s.nf_pad, f = e - n * s.nf_pad;
+  float acc = 0.f;
+  const int fl = f - s.f_lo;
+  if (fl >= 0 && fl < s.nF) {
+    const int nb = (s.N1 + (1 << s.sF) - 1) >> s.sF;
+    const int rows = ff.lowpass ? nb : ff.M;
+    for (int r = 0; r < rows; ++r) {
+      const c32 w = s.W[static_cast<int64_t>(ff.row0 + r) * s.NW + n];
+      const c32 d = s.o1[(ff.row0 + r) * s.nF + fl];
+      acc += w.x * d.x + w.y * d.y;
     }
+  }
+  s.dS1p[static_cast<int64_t>(g) * s.N1 * s.nf_pad + e] = acc;
+}
+
+// Sum of the row-split partials of dY2 into split 0 (fixed order), groups with RS > 1.
+__global__ __launch_bounds__(256) void k_dy_reduce(DevSig s) {
+  const FreqGroup fg = s.fgroups[blockIdx.y];
+  if (fg.RS <= 1) return;
+  const int64_t n = static_cast<int64_t>(fg.K) * fg.L2;
+  c32* base = s.dYpart + fg.dYpart;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < n;
+       e += static_cast<int64_t>(gridDim.x) * 256) {
+    c32 acc = base[e];
+    for (int r = 1; r < fg.RS; ++r) {
+      const c32 v = base[r * n + e];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    base[e] = acc;
   }
 }
 
@@ -410,12 +437,29 @@ __global__ __launch_bounds__(256) void k_freq_bwd(DevSig s) {
 }  // namespace
 
 hipError_t run_order1_fwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
-  hipLaunchKernelGGL(k_order1_fwd, dim3(p.fr_real.size()), dim3(256), 0, st, s);
+  const int rows = (p.R_pad * p.n_frames + 255) / 256;
+  hipLaunchKernelGGL(k_o1_v, dim3(rows), dim3(256), 0, st, s);
+  const int nb = (static_cast<int>(p.psi1.size()) + (1 << p.sF) - 1) >> p.sF;
+  hipLaunchKernelGGL(k_o1_pool, dim3((nb * p.n_frames + 255) / 256, p.fr_real.size()), dim3(256), 0, st, s);
   return hipGetLastError();
 }
 
 hipError_t run_order1_bwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
-  hipLaunchKernelGGL(k_order1_bwd, dim3(p.fr_real.size()), dim3(256), 0, st, s);
+  const int rows = (p.R_pad * p.n_frames + 255) / 256;
+  hipLaunchKernelGGL(k_o1_dv, dim3(rows), dim3(256), 0, st, s);
+  const int cells = (static_cast<int>(p.psi1.size()) * p.nf_pad + 255) / 256;
+  hipLaunchKernelGGL(k_o1_ds1, dim3(cells, p.fr_real.size()), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t run_dy_reduce(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  if (p.groups.empty()) return hipSuccess;
+  int64_t most = 0;
+  for (const FreqGroup& fg : p.fgroups)
+    if (fg.RS > 1) most = std::max<int64_t>(most, static_cast<int64_t>(fg.K) * fg.L2);
+  if (most == 0) return hipSuccess;
+  const int blocks = static_cast<int>(std::min<int64_t>((most + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_dy_reduce, dim3(blocks, p.groups.size()), dim3(256), 0, st, s);
   return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@
 //  L1Z   Z1 = IDFT_L1(fold_k1(X . psi1))        (Sec. 3.2)           [band psi1, shift k1, dst: Z1 row]
 //  L1UH  U1hat = DFT(|Z1|)                       (Sec. 3.2)           [src/dst: row offset]
 //  L2Y   Y2 = IDFT_L2(fold_k2(U1hat . psi2^(k1)))  (Sec. 3.3)         [src: U1hat row, band, shift k2]
-//  BYH   dY2hat = DFT(sum of the row-split partials of dY2)           [src, aux: split stride, t0: splits]
+//  BYH   dY2hat = DFT(dY2) (row-split partials already summed in split 0)  [src: dY2 row]
 //  BU    dU1 = Re IDFT_L1(sum_terms band . tile(term source))        [terms t0..t1]
 //  BZH   dZ1hat = DFT(dU1 . Z1 / |Z1|)  (0 where Z1 = 0)              [src: dU1, aux: Z1]
 //  BX    dx = unpad Re IDFT_Npad(sum_n1 psi1 . tile(dZ1hat))          [terms t0..t1]
@@ -107,15 +107,7 @@ struct Ops<ST_L2Y> {
 template <>
 struct Ops<ST_BYH> {
   static constexpr int DIR = -1;
-  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
-    c32 acc{0.f, 0.f};
-    for (int r = 0; r < j.t0; ++r) {
-      const c32 v = s.dYpart[j.src + r * j.aux + idx];
-      acc.x += v.x;
-      acc.y += v.y;
-    }
-    return acc;
-  }
+  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) { return s.dYpart[j.src + idx]; }
   __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.dYh[j.dst + idx] = v; }
 };
 
@@ -182,24 +174,28 @@ __device__ void fft_tile(c32* lds, int log2n, const c32* tw, int log2tw) {
   }
 }
 
+// One workgroup per task: `count` rows of one length, all in one 4096-element tile.
 template <int ST>
-__global__ __launch_bounds__(256) void k_fft_rows(DevSig s, int job0, int njobs, int log2n) {
+__global__ __launch_bounds__(256) void k_fft_rows(DevSig s, int task0) {
   __shared__ c32 lds[4096];
   using O = Ops<ST>;
+  const RowTask tk = s.tasks[task0 + blockIdx.x];
+  const int log2n = tk.log2n;
   const int n = 1 << log2n;
-  const int row0 = blockIdx.x << (12 - log2n);
+#pragma unroll 1
   for (int i = 0; i < 16; ++i) {
     const int e = threadIdx.x + 256 * i;
-    const int row = row0 + (e >> log2n);
-    lds[e] = row < njobs ? O::load(s, s.jobs[job0 + row], e & (n - 1)) : c32{0.f, 0.f};
+    const int row = e >> log2n;
+    lds[e] = row < tk.count ? O::load(s, s.jobs[tk.job0 + row], e & (n - 1)) : c32{0.f, 0.f};
   }
   __syncthreads();
   fft_tile<O::DIR>(lds, log2n, s.tw, s.log2_Npad);
   const float sc = O::DIR > 0 ? 1.0f / n : 1.0f;
+#pragma unroll 1
   for (int i = 0; i < 16; ++i) {
     const int e = threadIdx.x + 256 * i;
-    const int row = row0 + (e >> log2n);
-    if (row < njobs) O::store(s, s.jobs[job0 + row], e & (n - 1), cscale(lds[e], sc));
+    const int row = e >> log2n;
+    if (row < tk.count) O::store(s, s.jobs[tk.job0 + row], e & (n - 1), cscale(lds[e], sc));
   }
 }
 
@@ -300,13 +296,14 @@ __global__ __launch_bounds__(256) void k_ds1h(DevSig s) {
 
 template <int ST>
 hipError_t run_stage_t(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  if (p.ntask[ST] > 0) {
+    hipLaunchKernelGGL(k_fft_rows<ST>, dim3(p.ntask[ST]), dim3(256), 0, st, s, p.task0[ST]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   for (const Launch& l : p.launches[ST]) {
     const int log2n = 31 - __builtin_clz(static_cast<unsigned>(l.n));
-    if (l.n <= 4096) {
-      const int per = 4096 / l.n;
-      const int blocks = (l.njobs + per - 1) / per;
-      hipLaunchKernelGGL(k_fft_rows<ST>, dim3(blocks), dim3(256), 0, st, s, l.job0, l.njobs, log2n);
-    } else {
+    {
       const SplitGeom g = split_geom(log2n);
       hipLaunchKernelGGL(k_fft_split1<ST>, dim3((1 << g.log2A) >> g.log2C1, l.njobs), dim3(256), 0, st, s, l.job0,
                          log2n);

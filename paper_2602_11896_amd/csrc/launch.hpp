@@ -19,6 +19,7 @@ hipError_t run_freq_pool(const DevSig& s, const SigPlan& p, hipStream_t st);
 hipError_t run_freq_dP(const DevSig& s, const SigPlan& p, hipStream_t st);
 hipError_t run_freq_bwd(const DevSig& s, const SigPlan& p, hipStream_t st);
 hipError_t run_order1_bwd(const DevSig& s, const SigPlan& p, hipStream_t st);
+hipError_t run_dy_reduce(const DevSig& s, const SigPlan& p, hipStream_t st);
 
 // kernels_opt.hip
 // loss[0] = ||S - S_target||^2 and dS = 2 (S - S_target) over n coefficients.

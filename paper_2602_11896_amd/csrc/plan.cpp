@@ -441,7 +441,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     fg.j2 = grp.j2;
     fg.s_t = p.log2T - grp.j2;
     fg.phiT = add_lowpass_time(p, grp.L2, p.sigmaT, grp.j2);
-    fg.TC = static_cast<int32_t>(std::min<int64_t>(grp.L2, 512));
+    fg.TC = static_cast<int32_t>(std::min<int64_t>(grp.L2, 2048));
     fg.n_tc = static_cast<int32_t>(grp.L2 / fg.TC);
     fg.part = p.part_total;
     p.part_total += static_cast<int64_t>(fg.n_tc) * p.R_pad * nF;
@@ -480,18 +480,30 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   }
 
   // ---- row jobs of the time-axis stages, grouped by transform length
+  // Rows of a stage are sorted by length; lengths above 4096 become two-pass launches,
+  // the others workgroup tasks of one launch per stage (4096 / n rows per workgroup).
   auto emit = [&](int stage, std::vector<RowJob> js) {
     std::stable_sort(js.begin(), js.end(), [](const RowJob& a, const RowJob& b) { return a.n > b.n; });
+    p.task0[stage] = static_cast<int32_t>(p.tasks.size());
     size_t i = 0;
     while (i < js.size()) {
       size_t j = i;
       while (j < js.size() && js[j].n == js[i].n) ++j;
       Launch l{stage, js[i].n, static_cast<int32_t>(p.jobs.size()), static_cast<int32_t>(j - i)};
       for (size_t q = i; q < j; ++q) p.jobs.push_back(js[q]);
-      if (l.n > 4096) p.scr_elems = std::max<int64_t>(p.scr_elems, int64_t(l.n) * l.njobs);
-      p.launches[stage].push_back(l);
+      if (l.n > 4096) {
+        p.scr_elems = std::max<int64_t>(p.scr_elems, int64_t(l.n) * l.njobs);
+        p.launches[stage].push_back(l);
+      } else {
+        const int32_t per = 4096 / l.n;
+        int32_t log2n = 0;
+        while ((1 << log2n) < l.n) ++log2n;
+        for (int32_t r = 0; r < l.njobs; r += per)
+          p.tasks.push_back(RowTask{l.job0 + r, std::min(per, l.njobs - r), log2n, 0});
+      }
       i = j;
     }
+    p.ntask[stage] = static_cast<int32_t>(p.tasks.size()) - p.task0[stage];
   };
   auto job = [](int64_t src, int64_t dst, int64_t aux, int32_t band, int32_t src_len, int32_t n, int32_t shift) {
     RowJob r{};
@@ -527,10 +539,8 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
         int32_t L1 = Np >> k1;
         a.push_back(job(p.z1_off[n1], fg.y2 + int64_t(n1) * fg.L2, 0, p.band_psi2.at({grp.n2, k1}), L1, fg.L2,
                         grp.j2 - k1));
-        RowJob r = job(fg.dYpart + int64_t(n1) * fg.L2, fg.y2 + int64_t(n1) * fg.L2, int64_t(grp.K) * fg.L2, -1,
-                       fg.L2, fg.L2, 0);
-        r.t0 = fg.RS;
-        b.push_back(r);
+        // the row-split partials are summed into split 0 before this stage
+        b.push_back(job(fg.dYpart + int64_t(n1) * fg.L2, fg.y2 + int64_t(n1) * fg.L2, 0, -1, fg.L2, fg.L2, 0));
       }
     }
     emit(ST_L2Y, a);
@@ -591,6 +601,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   w.scr = take(sizeof(cfloat) * std::max<int64_t>(p.scr_elems, 1));
   w.S = take(sizeof(float) * p.n_coeff);
   w.dS = take(sizeof(float) * p.n_coeff);
+  w.o1 = take(sizeof(cfloat) * p.R_pad * p.n_frames);
   w.fwd_end = o;
   w.dP = take(sizeof(float) * std::max<int64_t>(p.dP_total, 1));
   w.dYpart = take(sizeof(cfloat) * std::max<int64_t>(p.dYpart_total, 1));

@@ -46,7 +46,7 @@ struct Launch {
 
 // Byte offsets of workspace regions for one signal (relative to the signal's segment).
 struct WsLayout {
-  size_t Xh, Z1, U1h, S1, Y2, part, scr, S, dS;   // forward (+ loss scratch)
+  size_t Xh, Z1, U1h, S1, Y2, part, scr, S, dS, o1;   // forward (+ loss scratch)
   size_t fwd_end;
   size_t dP, dYpart, dYh, dS1p, dU1, dZh, dXh, grad;
   size_t bwd_end;
@@ -82,7 +82,9 @@ struct SigPlan {
   std::vector<BwdItem> bwd_items;
   std::vector<RowJob> jobs;              // all stages; S1 jobs after the launches
   std::vector<GatherTerm> terms;
-  std::vector<Launch> launches[ST_COUNT];
+  std::vector<Launch> launches[ST_COUNT];     // two-pass (n > 4096) launches
+  std::vector<RowTask> tasks;                  // single-pass workgroup tasks of every stage
+  int32_t task0[ST_COUNT] = {0}, ntask[ST_COUNT] = {0};
   int32_t s1_job0 = 0;                   // N1 jobs for the S1 stage
   // forward frequential work, in complex multiply-adds (contraction) and real ones (pooling)
   double mac_dense = 0, mac_banded = 0, mac_exec = 0, mac_pool = 0;

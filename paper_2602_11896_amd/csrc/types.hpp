@@ -31,6 +31,12 @@ struct RowJob {
   int32_t t0, t1;  // term range [t0, t1) for multi-term gathers
 };
 
+// A workgroup's share of a single-pass transform stage: `count` consecutive rows of
+// length 2^log2n starting at job `job0` (count * 2^log2n <= 4096).
+struct RowTask {
+  int32_t job0, count, log2n, pad_;
+};
+
 // One term of a multi-term adjoint gather: out[m] += band[m] * src[m mod src_len]
 // for bins m of the output grid inside the band.
 struct GatherTerm {
