@@ -197,10 +197,11 @@ jtfs_status jtfs_metamer_step(jtfs_plan_t plan, float* y, const float* S_target,
  * wavelets, 6 frequential contraction + modulus + time pooling (forward), 7 phi_F pooling,
  * 8 pooled-gradient rows, 9 frequential contraction (backward), 10 order-1 adjoint,
  * 11 first-order averaging adjoint, 12 DFT of dY2, 13 second-order adjoint gather,
- * 14 DFT of dZ1, 15 first-order adjoint gather, 16 loss, 17 update. Timing state is
+ * 14 DFT of dZ1, 15 first-order adjoint gather, 16 loss, 17 update, 18 sum of the
+ * row-split partials of dY2. Timing state is
  * per plan and not thread-safe: use it from one thread.
  */
-#define JTFS_N_STAGES 18
+#define JTFS_N_STAGES 19
 jtfs_status jtfs_timing_enable(jtfs_plan_t plan, int32_t on);
 jtfs_status jtfs_timing_read(jtfs_plan_t plan, double* ms, int64_t* counts, int32_t cap);
 

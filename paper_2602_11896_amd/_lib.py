@@ -23,10 +23,10 @@ JTFS_OPT_MOMENTUM_BOLD = 1
 JTFS_OPT_ADAM = 2
 
 JTFS_REUSE_FORWARD = 1
-JTFS_N_STAGES = 18
+JTFS_N_STAGES = 19
 STAGE_NAMES = ["signal_dft", "l1_wavelet", "l1_modulus_dft", "l1_average", "order1_freq", "l2_wavelet",
                "freq_fwd", "freq_pool", "freq_dP", "freq_bwd", "order1_bwd", "l1_average_adj", "dY2_dft",
-               "l2_adj_gather", "dZ1_dft", "l1_adj_gather", "loss", "update"]
+               "l2_adj_gather", "dZ1_dft", "l1_adj_gather", "loss", "update", "dY2_reduce"]
 
 
 class jtfs_params(ctypes.Structure):

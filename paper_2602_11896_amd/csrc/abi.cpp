@@ -258,7 +258,7 @@ jtfs_status backward_signal(jtfs_plan_t p, const jtfs::DevSig& d, const jtfs::Si
   }
   STAGE(8, jtfs::run_freq_dP(d, sp, st));
   STAGE(9, jtfs::run_freq_bwd(d, sp, st));
-  STAGE(9, jtfs::run_dy_reduce(d, sp, st));
+  STAGE(18, jtfs::run_dy_reduce(d, sp, st));
   STAGE(10, jtfs::run_order1_bwd(d, sp, st));
   STAGE(11, jtfs::run_ds1h(d, sp, st));
   STAGE(12, jtfs::run_time_stage(jtfs::ST_BYH, d, sp, st));

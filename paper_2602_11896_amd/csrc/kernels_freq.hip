@@ -28,92 +28,178 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ inline f4 mfma(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
-// ------------------------------------------------------------------ forward contraction
-// Work item: group, 64-row block (one 16-row tile per wave), a chunk of TC times.
-// Per wave: V^T (16 t x 16 r) = Y2^T (t x n) W^T (n x r) with W^T held in registers,
-// then P^T (f x r) += Phi^T (f x t) |V^T| with the modulus taken in the D layout,
-// which is exactly the B layout the pooling MFMA needs.
-template <int MAXS>
-__global__ __launch_bounds__(256) void k_freq_fwd(DevSig s) {
-  __shared__ c32 ytile[MAXS * 4 * 16];
-  const FwdItem it = s.fwd_items[blockIdx.x];
-  const FreqGroup fg = s.fgroups[it.grp];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int li = lane & 15, lk = lane >> 4;
-  const int rt = it.rb * 4 + wave;
-  const int r0 = rt * 16;
-  const int K = fg.K;
-  const int Kal = (K + 3) & ~3;
-  const int nlo = s.rt_nrange[2 * rt];
-  const int nhi = min(s.rt_nrange[2 * rt + 1], Kal);
-  const int steps = nhi > nlo ? (nhi - nlo) >> 2 : 0;
+// Hardware square root (v_sqrt_f32, within 1 ulp) for moduli and phases.
+__device__ inline float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-  float bre[MAXS], bim[MAXS];
+// Index of the calling thread's wave, as a wave-uniform (scalar) value.
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// ------------------------------------------------------------------ forward contraction
+// Work item: group, a block of 4 * RW row tiles (RW 16-row tiles per wave), a chunk of
+// TC times. Per wave and 16-time tile: V^T (16 t x 16 r) = Y2^T (t x n) W^T (n x r) for
+// each of its row tiles, with W^T in registers and the Y2^T fragments streamed from
+// memory one tile ahead (no LDS, no barriers); then P^T (f x r) += Phi^T (f x t) |V^T|,
+// the modulus taken in the D layout, which is the B layout of the pooling MFMA.
+// Complex products: with a = Y2 and b = W, up to 8 k-steps use three real products
+//   P1 = (a_r + a_i) b_r,  P2 = a_r (b_i - b_r),  P3 = a_i (b_r + b_i),
+//   Re(ab) = P1 - P3,  Im(ab) = P1 + P2,
+// longer ones four (a_r b_r, a_i b_i, a_r b_i + a_i b_r), which needs fewer registers.
+constexpr int fwd_rw(int S, int FT) {
+  return 4 * (2 * S + 4 * FT) <= 100 ? 4 : (2 * (2 * S + 4 * FT) <= 100 ? 2 : 1);
+}
+
+// Loads the Y2^T fragments and the Phi^T fragments of the 16-time tile starting at tt.
+template <int S, int FT>
+__device__ inline void fwd_load(const c32* Y, const float* phi, int L2, int K, int ulo, int nst, int lk, int li, int tt,
+                                bool ok, int f_lo, int s_t, int nF, float (&ar)[S], float (&ai)[S], float (&ph)[FT][4]) {
 #pragma unroll
-  for (int q = 0; q < MAXS; ++q) {
-    bre[q] = 0.f;
-    bim[q] = 0.f;
-    const int n = nlo + 4 * q + lk;
-    if (q < steps && n < K) {
-      const c32 w = s.W[static_cast<int64_t>(r0 + li) * s.NW + n];
-      bre[q] = w.x;
-      bim[q] = w.y;
+  for (int q = 0; q < S; ++q) {
+    const int n = ulo + 4 * q + lk;
+    c32 y{0.f, 0.f};
+    if (ok && q < nst && n < K) y = Y[static_cast<int64_t>(n) * L2 + tt + li];
+    ar[q] = y.x;
+    ai[q] = y.y;
+  }
+#pragma unroll
+  for (int ft = 0; ft < FT; ++ft) {
+    const int f = ft * 16 + li;
+    const int fc = (f_lo + f) << s_t;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ph[ft][v] = (ok && f < nF) ? phi[(fc - (tt + 4 * lk + v)) & (L2 - 1)] : 0.f;
+  }
+}
+
+// Contraction, modulus and pooling of one 16-time tile for the wave's RW row tiles.
+template <int S, int FT, int RW>
+__device__ inline void fwd_tile(const float (&ar)[S], const float (&ai)[S], const float (&ph)[FT][4],
+                                const float (&br)[RW][S], const float (&bi)[RW][S], const int (&qa)[RW],
+                                const int (&qb)[RW], f4 (&pacc)[RW][FT]) {
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    if (qb[i] > qa[i]) {
+      f4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = {0.f, 0.f, 0.f, 0.f}, p3 = {0.f, 0.f, 0.f, 0.f};
+      float u[4];
+      if constexpr (S <= 8) {
+        // three products: Re = P1 - P3, Im = P1 + P2
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+          if (q >= qa[i] && q < qb[i]) {
+            p1 = mfma(ar[q] + ai[q], br[i][q], p1);
+            p2 = mfma(ar[q], bi[i][q] - br[i][q], p2);
+            p3 = mfma(ai[q], br[i][q] + bi[i][q], p3);
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float re = p1[v] - p3[v], im = p1[v] + p2[v];
+          u[v] = hw_sqrt(re * re + im * im);
+        }
+      } else {
+        // four products on the raw parts: Re = a_r b_r - a_i b_i, Im = a_r b_i + a_i b_r
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+          if (q >= qa[i] && q < qb[i]) {
+            p1 = mfma(ar[q], br[i][q], p1);
+            p2 = mfma(ai[q], bi[i][q], p2);
+            p3 = mfma(ar[q], bi[i][q], p3);
+            p3 = mfma(ai[q], br[i][q], p3);
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float re = p1[v] - p2[v], im = p3[v];
+          u[v] = hw_sqrt(re * re + im * im);
+        }
+      }
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pacc[i][ft] = mfma(ph[ft][v], u[v], pacc[i][ft]);
     }
   }
-  const int nF = s.nF;
-  const int FT = (nF + 15) >> 4;
-  f4 pacc[8];
+}
+
+template <int S, int FT>
+__global__ __launch_bounds__(256, (S >= 32 ? 1 : 2)) void k_freq_fwd(DevSig s, int item0) {
+  constexpr int RW = fwd_rw(S, FT);
+  const FwdItem it = s.fwd_items[item0 + blockIdx.x];
+  const FreqGroup fg = s.fgroups[it.grp];
+  const int wave = wave_id();
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int K = fg.K;
+  const int Kal = (K + 3) & ~3;
+  const int rt0 = (it.rb * 4 + wave) * RW;
+
+  int qa[RW], qb[RW];
+  int ulo = Kal, uhi = 0;
 #pragma unroll
-  for (int ft = 0; ft < 8; ++ft) pacc[ft] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < RW; ++i) {
+    const int lo = s.rt_nrange[2 * (rt0 + i)];
+    const int hi = min(s.rt_nrange[2 * (rt0 + i) + 1], Kal);
+    qa[i] = lo;
+    qb[i] = hi;
+    if (hi > lo) {
+      ulo = min(ulo, lo);
+      uhi = max(uhi, hi);
+    }
+  }
+  const int nst = uhi > ulo ? (uhi - ulo) >> 2 : 0;
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    const bool live = qb[i] > qa[i];
+    qa[i] = live ? (qa[i] - ulo) >> 2 : 0;
+    qb[i] = live ? (qb[i] - ulo) >> 2 : 0;
+  }
+
+  float br[RW][S], bi[RW][S];
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      br[i][q] = 0.f;
+      bi[i][q] = 0.f;
+      if (q >= qa[i] && q < qb[i]) {
+        const c32 w = s.W[static_cast<int64_t>((rt0 + i) * 16 + li) * s.NW + ulo + 4 * q + lk];
+        br[i][q] = w.x;
+        bi[i][q] = w.y;
+      }
+    }
+  }
+
   const c32* Y = s.Y2 + fg.y2;
   const float* phi = s.tables + fg.phiT;
   const int L2 = fg.L2;
-  const int Lmask = L2 - 1;
-  const int tbeg = it.tc * fg.TC;
+  const int nF = s.nF;
+  f4 pacc[RW][FT];
+#pragma unroll
+  for (int i = 0; i < RW; ++i)
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) pacc[i][ft] = f4{0.f, 0.f, 0.f, 0.f};
 
-  for (int tt = tbeg; tt < tbeg + fg.TC; tt += 16) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < Kal * 16; e += 256) {
-      const int n = e >> 4, t = e & 15;
-      ytile[e] = n < K ? Y[static_cast<int64_t>(n) * L2 + tt + t] : c32{0.f, 0.f};
-    }
-    __syncthreads();
-    f4 ar = {0.f, 0.f, 0.f, 0.f}, ai = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int q = 0; q < MAXS; ++q) {
-      if (q < steps) {
-        const c32 a = ytile[(nlo + 4 * q + lk) * 16 + li];
-        ar = mfma(a.x, bre[q], ar);
-        ai = mfma(a.x, bim[q], ai);
-        ar = mfma(a.y, -bim[q], ar);
-        ai = mfma(a.y, bre[q], ai);
-      }
-    }
-    float u[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) u[v] = sqrtf(ar[v] * ar[v] + ai[v] * ai[v]);
-#pragma unroll
-    for (int ft = 0; ft < 8; ++ft) {
-      if (ft < FT) {
-        const int f = ft * 16 + li;
-        const int fc = (s.f_lo + f) << fg.s_t;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int t = tt + 4 * lk + v;
-          const float a = f < nF ? phi[(fc - t) & Lmask] : 0.f;
-          pacc[ft] = mfma(a, u[v], pacc[ft]);
-        }
-      }
+  if (nst > 0) {
+    // Two register sets used alternately: the next tile's operands are requested
+    // before the current tile is computed (TC is a power of two, at least 16).
+    const int tbeg = it.tc * fg.TC, tend = tbeg + fg.TC;
+    float ar0[S], ai0[S], ph0[FT][4], ar1[S], ai1[S], ph1[FT][4];
+    fwd_load<S, FT>(Y, phi, L2, K, ulo, nst, lk, li, tbeg, true, s.f_lo, fg.s_t, nF, ar0, ai0, ph0);
+    for (int tt = tbeg; tt < tend; tt += 32) {
+      const bool second = tt + 16 < tend;
+      fwd_load<S, FT>(Y, phi, L2, K, ulo, nst, lk, li, tt + 16, second, s.f_lo, fg.s_t, nF, ar1, ai1, ph1);
+      fwd_tile<S, FT, RW>(ar0, ai0, ph0, br, bi, qa, qb, pacc);
+      fwd_load<S, FT>(Y, phi, L2, K, ulo, nst, lk, li, tt + 32, tt + 32 < tend, s.f_lo, fg.s_t, nF, ar0, ai0, ph0);
+      if (second) fwd_tile<S, FT, RW>(ar1, ai1, ph1, br, bi, qa, qb, pacc);
     }
   }
-  float* out = s.part + fg.part + (static_cast<int64_t>(it.tc) * s.R_pad + r0 + li) * nF;
 #pragma unroll
-  for (int ft = 0; ft < 8; ++ft) {
-    if (ft < FT) {
+  for (int i = 0; i < RW; ++i) {
+    float* out = s.part + fg.part + (static_cast<int64_t>(it.tc) * s.R_pad + (rt0 + i) * 16 + li) * nF;
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int f = ft * 16 + 4 * lk + v;
-        if (f < nF) out[f] = pacc[ft][v];
+        if (f < nF) out[f] = pacc[i][ft][v];
       }
     }
   }
@@ -323,13 +409,23 @@ __global__ __launch_bounds__(256) void k_freq_dP(DevSig s) {
 // Work item: group, 64 times (one 16-time tile per wave), a split of the row tiles.
 // Per wave and row tile: recompute V (16 r x 16 t) = W Y2, dU = dP Phi (time-pooling
 // adjoint), dV = dU V / |V|, then dY2 (n x t) += W^H dV; Y2 operands and dY2
-// accumulators stay in registers over the row loop.
+// accumulators stay in registers over the row loop. W tiles are staged in LDS, double
+// buffered: the next live tile's global loads are in flight while the current one is
+// used, and one barrier per tile separates the buffers.
+__device__ inline int next_live_tile(const DevSig& s, int rt, int rt_hi, int Kal) {
+  while (rt < rt_hi && min(s.rt_nrange[2 * rt + 1], Kal) <= s.rt_nrange[2 * rt]) ++rt;
+  return rt;
+}
+
 template <int MAXS, int MAXNT>
-__global__ __launch_bounds__(256) void k_freq_bwd(DevSig s) {
-  __shared__ c32 wt[16 * 256];
+__global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s) {
+  constexpr int WS = 4 * MAXS;               // LDS row stride (columns)
+  constexpr int PER = (16 * WS) / 256;       // W elements staged per thread
+  __shared__ c32 wt[2][16 * WS];
   const BwdItem it = s.bwd_items[blockIdx.x];
   const FreqGroup fg = s.fgroups[it.grp];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_id();
+  const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int t0 = it.tb * 64 + wave * 16;
   const int L2 = fg.L2;
@@ -337,6 +433,7 @@ __global__ __launch_bounds__(256) void k_freq_bwd(DevSig s) {
   const int K = fg.K;
   const int Kal = (K + 3) & ~3;
   const int NT = (K + 15) >> 4;
+  const int ncols = NT * 16;
   const c32* Y = s.Y2 + fg.y2;
 
   float yre[MAXS], yim[MAXS];
@@ -363,62 +460,86 @@ __global__ __launch_bounds__(256) void k_freq_bwd(DevSig s) {
   const float* phi = s.tables + fg.phiT;
   const int nF = s.nF;
   const int nFq = (nF + 3) >> 2;
-  const int ncols = NT * 16;
 
-  for (int rt = rt_lo; rt < rt_hi; ++rt) {
+  // stage the first live tile
+  int rt = next_live_tile(s, rt_lo, rt_hi, Kal);
+  c32 wreg[PER];
+  if (rt < rt_hi) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int rr = e / WS, n = e - rr * WS;
+      wt[0][e] = n < ncols ? s.W[static_cast<int64_t>(rt * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
+    }
+  }
+  __syncthreads();
+  int buf = 0;
+  while (rt < rt_hi) {
+    const int nxt = next_live_tile(s, rt + 1, rt_hi, Kal);
+    if (nxt < rt_hi) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        const int rr = e / WS, n = e - rr * WS;
+        wreg[i] = n < ncols ? s.W[static_cast<int64_t>(nxt * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
+      }
+    }
     const int nlo = s.rt_nrange[2 * rt];
     const int nhi = min(s.rt_nrange[2 * rt + 1], Kal);
-    if (nhi <= nlo) continue;   // uniform over the workgroup
     const int r0 = rt * 16;
-    __syncthreads();
-    for (int e = threadIdx.x; e < 16 * ncols; e += 256) {
-      const int rr = e / ncols, n = e - rr * ncols;
-      wt[rr * 256 + n] = s.W[static_cast<int64_t>(r0 + rr) * s.NW + n];
-    }
-    __syncthreads();
-    if (!active) continue;
-    f4 vr = {0.f, 0.f, 0.f, 0.f}, vi = {0.f, 0.f, 0.f, 0.f};
+    const c32* w = wt[buf];
+    if (active) {
+      f4 vr = {0.f, 0.f, 0.f, 0.f}, vi = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int q = 0; q < MAXS; ++q) {
-      if (4 * q >= nlo && 4 * q < nhi) {
-        const c32 a = wt[li * 256 + 4 * q + lk];
-        vr = mfma(a.x, yre[q], vr);
-        vr = mfma(-a.y, yim[q], vr);
-        vi = mfma(a.x, yim[q], vi);
-        vi = mfma(a.y, yre[q], vi);
+      for (int q = 0; q < MAXS; ++q) {
+        if (4 * q >= nlo && 4 * q < nhi) {
+          const c32 a = w[li * WS + 4 * q + lk];
+          vr = mfma(a.x, yre[q], vr);
+          vr = mfma(-a.y, yim[q], vr);
+          vi = mfma(a.x, yim[q], vi);
+          vi = mfma(a.y, yre[q], vi);
+        }
       }
-    }
-    f4 du = {0.f, 0.f, 0.f, 0.f};
-    const float* dPr = s.dP + fg.dP + static_cast<int64_t>(r0 + li) * nF;
-    for (int q = 0; q < nFq; ++q) {
-      const int f = 4 * q + lk;
-      float a = 0.f, b = 0.f;
-      if (f < nF) {
-        a = dPr[f];
-        b = phi[(((s.f_lo + f) << fg.s_t) - (t0 + li)) & (L2 - 1)];
+      f4 du = {0.f, 0.f, 0.f, 0.f};
+      const float* dPr = s.dP + fg.dP + static_cast<int64_t>(r0 + li) * nF;
+      for (int q = 0; q < nFq; ++q) {
+        const int f = 4 * q + lk;
+        float a = 0.f, b = 0.f;
+        if (f < nF) {
+          a = dPr[f];
+          b = phi[(((s.f_lo + f) << fg.s_t) - (t0 + li)) & (L2 - 1)];
+        }
+        du = mfma(a, b, du);
       }
-      du = mfma(a, b, du);
-    }
-    float dvr[4], dvi[4];
+      float dvr[4], dvi[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const float m = sqrtf(vr[v] * vr[v] + vi[v] * vi[v]);
-      dvr[v] = m > 0.f ? du[v] * (vr[v] / m) : 0.f;
-      dvi[v] = m > 0.f ? du[v] * (vi[v] / m) : 0.f;
-    }
+      for (int v = 0; v < 4; ++v) {
+        const float m = hw_sqrt(vr[v] * vr[v] + vi[v] * vi[v]);
+        const float sc = m > 0.f ? du[v] / m : 0.f;
+        dvr[v] = vr[v] * sc;
+        dvi[v] = vi[v] * sc;
+      }
 #pragma unroll
-    for (int nt = 0; nt < MAXNT; ++nt) {
-      if (nt < NT && nt * 16 < nhi && nt * 16 + 16 > nlo) {
+      for (int nt = 0; nt < MAXNT; ++nt) {
+        if (nt < NT && nt * 16 < nhi && nt * 16 + 16 > nlo) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const c32 a = wt[(4 * lk + v) * 256 + nt * 16 + li];
-          dyr[nt] = mfma(a.x, dvr[v], dyr[nt]);
-          dyr[nt] = mfma(a.y, dvi[v], dyr[nt]);
-          dyi[nt] = mfma(a.x, dvi[v], dyi[nt]);
-          dyi[nt] = mfma(-a.y, dvr[v], dyi[nt]);
+          for (int v = 0; v < 4; ++v) {
+            const c32 a = w[(4 * lk + v) * WS + nt * 16 + li];
+            dyr[nt] = mfma(a.x, dvr[v], dyr[nt]);
+            dyr[nt] = mfma(a.y, dvi[v], dyr[nt]);
+            dyi[nt] = mfma(a.x, dvi[v], dyi[nt]);
+            dyi[nt] = mfma(-a.y, dvr[v], dyi[nt]);
+          }
         }
       }
     }
+    if (nxt < rt_hi) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) wt[buf ^ 1][threadIdx.x + 256 * i] = wreg[i];
+    }
+    __syncthreads();
+    buf ^= 1;
+    rt = nxt;
   }
   if (!active) return;
   c32* dst = s.dYpart + fg.dYpart + static_cast<int64_t>(it.rs) * K * L2;
@@ -463,13 +584,32 @@ hipError_t run_dy_reduce(const DevSig& s, const SigPlan& p, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t run_freq_fwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
-  if (p.fwd_items.empty()) return hipSuccess;
-  if (p.NW <= 128)
-    hipLaunchKernelGGL(k_freq_fwd<32>, dim3(p.fwd_items.size()), dim3(256), 0, st, s);
-  else
-    hipLaunchKernelGGL(k_freq_fwd<64>, dim3(p.fwd_items.size()), dim3(256), 0, st, s);
+template <int S>
+hipError_t launch_fwd_s(const DevSig& s, const SigPlan::FwdLaunch& l, hipStream_t st) {
+  switch (l.FT) {
+    case 1: hipLaunchKernelGGL((k_freq_fwd<S, 1>), dim3(l.nitems), dim3(256), 0, st, s, l.item0); break;
+    case 2: hipLaunchKernelGGL((k_freq_fwd<S, 2>), dim3(l.nitems), dim3(256), 0, st, s, l.item0); break;
+    case 4: hipLaunchKernelGGL((k_freq_fwd<S, 4>), dim3(l.nitems), dim3(256), 0, st, s, l.item0); break;
+    default: hipLaunchKernelGGL((k_freq_fwd<S, 8>), dim3(l.nitems), dim3(256), 0, st, s, l.item0); break;
+  }
   return hipGetLastError();
+}
+
+hipError_t run_freq_fwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  for (const SigPlan::FwdLaunch& l : p.fwd_launches) {
+    if (l.RW != fwd_rw(l.S, l.FT)) return hipErrorInvalidValue;   // plan and kernel disagree
+    hipError_t e;
+    switch (l.S) {
+      case 4: e = launch_fwd_s<4>(s, l, st); break;
+      case 8: e = launch_fwd_s<8>(s, l, st); break;
+      case 16: e = launch_fwd_s<16>(s, l, st); break;
+      case 32: e = launch_fwd_s<32>(s, l, st); break;
+      case 64: e = launch_fwd_s<64>(s, l, st); break;
+      default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t run_freq_pool(const DevSig& s, const SigPlan& p, hipStream_t st) {

@@ -345,7 +345,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     rows += static_cast<int32_t>(round_up(ff.M, 16));
   }
   p.R_total = rows;
-  p.R_pad = static_cast<int32_t>(round_up(rows, 64));
+  p.R_pad = static_cast<int32_t>(round_up(rows, 512));   // whole workgroup row blocks
   p.W.assign(static_cast<size_t>(p.R_pad) * p.NW, cfloat{0.f, 0.f});
   {
     const int32_t L = p.N_fr;
@@ -471,10 +471,29 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
       if (hi > lo) p.mac_exec += 16.0 * (hi - lo) * fg.L2;
     }
   }
+  // Forward items, one launch per kernel shape: S = k-steps covering the group's rows
+  // (a power of two), FT = 16-frame tiles, RW = 16-row tiles per wave chosen so that the
+  // register-resident operands of a wave stay near 100 VGPRs.
+  {
+    const int32_t FT = nF <= 16 ? 1 : nF <= 32 ? 2 : nF <= 64 ? 4 : 8;
+    for (int32_t S = 4; S <= 64; S *= 2) {
+      int32_t RW = 4;
+      while (RW > 1 && RW * (2 * S + 4 * FT) > 100) RW /= 2;
+      SigPlan::FwdLaunch fl{S, RW, FT, static_cast<int32_t>(p.fwd_items.size()), 0};
+      for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
+        const FreqGroup& fg = p.fgroups[gi];
+        const int32_t need = ((fg.K + 3) / 4);
+        const int32_t bucket = need <= 4 ? 4 : need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 64;
+        if (bucket != S) continue;
+        for (int32_t tc = 0; tc < fg.n_tc; ++tc)
+          for (int32_t rb = 0; rb < p.R_pad / (64 * RW); ++rb) p.fwd_items.push_back(FwdItem{gi, rb, tc, 0});
+      }
+      fl.nitems = static_cast<int32_t>(p.fwd_items.size()) - fl.item0;
+      if (fl.nitems > 0) p.fwd_launches.push_back(fl);
+    }
+  }
   for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
     const FreqGroup& fg = p.fgroups[gi];
-    for (int32_t tc = 0; tc < fg.n_tc; ++tc)
-      for (int32_t rb = 0; rb < p.R_pad / 64; ++rb) p.fwd_items.push_back(FwdItem{gi, rb, tc, 0});
     for (int32_t tb = 0; tb < fg.n_tb; ++tb)
       for (int32_t rs = 0; rs < fg.RS; ++rs) p.bwd_items.push_back(BwdItem{gi, tb, rs, 0});
   }

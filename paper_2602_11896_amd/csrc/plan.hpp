@@ -78,7 +78,11 @@ struct SigPlan {
   std::vector<int32_t> tap_count;        // per row: taps above 1e-7 of peak among the first n columns
   std::vector<FrFilter> frf;
   std::vector<FreqGroup> fgroups;
-  std::vector<FwdItem> fwd_items;
+  std::vector<FwdItem> fwd_items;       // grouped by kernel shape, see fwd_launches
+  struct FwdLaunch {
+    int32_t S, RW, FT, item0, nitems;     // k-steps, row tiles per wave, frame tiles
+  };
+  std::vector<FwdLaunch> fwd_launches;
   std::vector<BwdItem> bwd_items;
   std::vector<RowJob> jobs;              // all stages; S1 jobs after the launches
   std::vector<GatherTerm> terms;
