@@ -45,7 +45,13 @@ struct SigTables {
 struct DeviceArena {
   void* base = nullptr;
   std::vector<SigTables> sig;
+  // streams over which the signals of a batch are spread, and the fork / join events
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> joins;
+  hipEvent_t fork = nullptr;
 };
+
+constexpr int kMaxStreams = 8;
 
 }  // namespace
 
@@ -73,6 +79,9 @@ struct jtfs_plan_s {
     for (auto& kv : dev) {
       int cur = 0;
       if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(kv.first) == hipSuccess) {
+        for (hipStream_t s : kv.second.streams) (void)hipStreamDestroy(s);
+        for (hipEvent_t e : kv.second.joins) (void)hipEventDestroy(e);
+        if (kv.second.fork) (void)hipEventDestroy(kv.second.fork);
         (void)hipFree(kv.second.base);
         (void)hipSetDevice(cur);
       }
@@ -146,9 +155,55 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     t.tasks = reinterpret_cast<const jtfs::RowTask*>(b + o[13]);
     a.sig.push_back(t);
   }
+  if (p->sig.size() > 1) {
+    const size_t ns = std::min<size_t>(p->sig.size(), kMaxStreams);
+    bool ok = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) == hipSuccess;
+    for (size_t i = 0; ok && i < ns; ++i) {
+      hipStream_t st = nullptr;
+      hipEvent_t ev = nullptr;
+      ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+      if (st) a.streams.push_back(st);
+      if (ev) a.joins.push_back(ev);
+    }
+    if (!ok) {
+      for (hipStream_t st : a.streams) (void)hipStreamDestroy(st);
+      for (hipEvent_t ev : a.joins) (void)hipEventDestroy(ev);
+      if (a.fork) (void)hipEventDestroy(a.fork);
+      (void)hipFree(a.base);
+      return fail(JTFS_ERR_HIP, "creating the batch streams failed");
+    }
+  }
   auto ins = p->dev.emplace(dev, std::move(a));
   *out = &ins.first->second;
   return JTFS_OK;
+}
+
+// Runs body(signal, stream) for every signal. A single signal runs on the caller's
+// stream; a batch is spread over the arena's streams, which first wait for the work
+// already enqueued on the caller's stream and are waited for by it at the end (event
+// fork / join, so the pattern is also valid under stream capture).
+template <class Body>
+jtfs_status for_each_signal(jtfs_plan_t plan, const DeviceArena* a, hipStream_t caller, Body body) {
+  if (plan->sig.size() == 1 || a->streams.empty()) {
+    for (size_t s = 0; s < plan->sig.size(); ++s) {
+      jtfs_status r = body(s, caller);
+      if (r != JTFS_OK) return r;
+    }
+    return JTFS_OK;
+  }
+  std::lock_guard<std::mutex> lock(plan->mu);
+  if (hipEventRecord(a->fork, caller) != hipSuccess) return fail(JTFS_ERR_HIP, "fork event record failed");
+  for (hipStream_t st : a->streams)
+    if (hipStreamWaitEvent(st, a->fork, 0) != hipSuccess) return fail(JTFS_ERR_HIP, "fork wait failed");
+  jtfs_status r = JTFS_OK;
+  for (size_t s = 0; s < plan->sig.size() && r == JTFS_OK; ++s) r = body(s, a->streams[s % a->streams.size()]);
+  for (size_t i = 0; i < a->streams.size(); ++i) {
+    if (hipEventRecord(a->joins[i], a->streams[i]) != hipSuccess ||
+        hipStreamWaitEvent(caller, a->joins[i], 0) != hipSuccess)
+      return fail(JTFS_ERR_HIP, "join failed");
+  }
+  return r;
 }
 
 jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void* ws) {
@@ -418,15 +473,12 @@ jtfs_status jtfs_forward(jtfs_plan_t plan, const float* x, float* S, void* ws, s
   const DeviceArena* a = nullptr;
   jtfs_status r = device_tables(plan, &a);
   if (r != JTFS_OK) return r;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  for (size_t s = 0; s < plan->sig.size(); ++s) {
+  return for_each_signal(plan, a, static_cast<hipStream_t>(stream), [&](size_t s, hipStream_t st) {
     jtfs::DevSig d = make_devsig(plan, s, a->sig[s], ws);
     d.x = x + plan->x_off[s];
     d.S = S + plan->s_off[s];
-    r = forward_signal(plan, d, plan->sig[s], st);
-    if (r != JTFS_OK) return r;
-  }
-  return JTFS_OK;
+    return forward_signal(plan, d, plan->sig[s], st);
+  });
 }
 
 jtfs_status jtfs_backward(jtfs_plan_t plan, const float* x, const float* dS, float* dx, void* ws, size_t ws_bytes,
@@ -437,16 +489,14 @@ jtfs_status jtfs_backward(jtfs_plan_t plan, const float* x, const float* dS, flo
   const DeviceArena* a = nullptr;
   jtfs_status r = device_tables(plan, &a);
   if (r != JTFS_OK) return r;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  for (size_t s = 0; s < plan->sig.size(); ++s) {
+  const bool reuse = (flags & JTFS_REUSE_FORWARD) != 0;
+  return for_each_signal(plan, a, static_cast<hipStream_t>(stream), [&](size_t s, hipStream_t st) {
     jtfs::DevSig d = make_devsig(plan, s, a->sig[s], ws);
     d.x = x + plan->x_off[s];
     d.dS = dS + plan->s_off[s];
     d.dx = dx + plan->x_off[s];
-    r = backward_signal(plan, d, plan->sig[s], (flags & JTFS_REUSE_FORWARD) != 0, st);
-    if (r != JTFS_OK) return r;
-  }
-  return JTFS_OK;
+    return backward_signal(plan, d, plan->sig[s], reuse, st);
+  });
 }
 
 jtfs_status jtfs_metamer_step(jtfs_plan_t plan, float* y, const float* S_target, const jtfs_opt* opt, float* loss,
@@ -458,11 +508,10 @@ jtfs_status jtfs_metamer_step(jtfs_plan_t plan, float* y, const float* S_target,
   const DeviceArena* a = nullptr;
   jtfs_status r = device_tables(plan, &a);
   if (r != JTFS_OK) return r;
-  hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t nv = state_vectors(opt->kind);
   const int64_t Nt = plan->n_total;
   float* scal_base = opt->state + nv * Nt;
-  for (size_t s = 0; s < plan->sig.size(); ++s) {
+  return for_each_signal(plan, a, static_cast<hipStream_t>(stream), [&](size_t s, hipStream_t st) -> jtfs_status {
     const jtfs::SigPlan& sp = plan->sig[s];
     char* seg = static_cast<char*>(ws) + plan->ws_off[s];
     float* S_y = reinterpret_cast<float*>(seg + sp.ws.S);
@@ -472,7 +521,7 @@ jtfs_status jtfs_metamer_step(jtfs_plan_t plan, float* y, const float* S_target,
     float* ys = y + plan->x_off[s];
     d.x = ys;
     d.S = S_y;
-    r = forward_signal(plan, d, sp, st);
+    jtfs_status r = forward_signal(plan, d, sp, st);
     if (r != JTFS_OK) return r;
     jtfs_plan_t p = plan;
     STAGE(16, jtfs::run_loss(S_y, S_target + plan->s_off[s], dS, loss + s, sp.n_coeff, st));
@@ -484,8 +533,8 @@ jtfs_status jtfs_metamer_step(jtfs_plan_t plan, float* y, const float* S_target,
     float* v1 = nv > 1 ? opt->state + Nt + plan->x_off[s] : nullptr;
     float* v2 = nv > 2 ? opt->state + 2 * Nt + plan->x_off[s] : nullptr;
     STAGE(17, jtfs::run_update(*opt, ys, grad, loss + s, v0, v1, v2, scal_base + 4 * s, sp.N, st));
-  }
-  return JTFS_OK;
+    return JTFS_OK;
+  });
 }
 
 jtfs_status jtfs_timing_enable(jtfs_plan_t plan, int32_t on) {

@@ -120,9 +120,16 @@ __device__ inline void fwd_tile(const float (&ar)[S], const float (&ai)[S], cons
 }
 
 template <int S, int FT>
-__global__ __launch_bounds__(256, (S >= 32 ? 1 : 2)) void k_freq_fwd(DevSig s, int item0) {
+__global__ __launch_bounds__(256, (S >= 32 ? 1 : 2)) void k_freq_fwd(DevSig s, int item0, int run) {
   constexpr int RW = fwd_rw(S, FT);
-  const FwdItem it = s.fwd_items[item0 + blockIdx.x];
+  // Workgroups are dealt round-robin to the 8 XCDs. A run of `run` consecutive items
+  // (same group and time chunk, different row blocks: they read the same Y2 columns)
+  // is given to blocks of one XCD so that its L2 serves the re-reads; consecutive runs
+  // go to different XCDs to keep their loads even. gridDim.x is a multiple of 8 * run.
+  const int j = blockIdx.x >> 3;
+  const int item = ((j / run) * 8 + (blockIdx.x & 7)) * run + j % run;
+  const FwdItem it = s.fwd_items[item0 + item];
+  if (it.grp < 0) return;   // padding item (no barriers in this kernel)
   const FreqGroup fg = s.fgroups[it.grp];
   const int wave = wave_id();
   const int lane = threadIdx.x & 63;
@@ -587,10 +594,10 @@ hipError_t run_dy_reduce(const DevSig& s, const SigPlan& p, hipStream_t st) {
 template <int S>
 hipError_t launch_fwd_s(const DevSig& s, const SigPlan::FwdLaunch& l, hipStream_t st) {
   switch (l.FT) {
-    case 1: hipLaunchKernelGGL((k_freq_fwd<S, 1>), dim3(l.nitems), dim3(256), 0, st, s, l.item0); break;
-    case 2: hipLaunchKernelGGL((k_freq_fwd<S, 2>), dim3(l.nitems), dim3(256), 0, st, s, l.item0); break;
-    case 4: hipLaunchKernelGGL((k_freq_fwd<S, 4>), dim3(l.nitems), dim3(256), 0, st, s, l.item0); break;
-    default: hipLaunchKernelGGL((k_freq_fwd<S, 8>), dim3(l.nitems), dim3(256), 0, st, s, l.item0); break;
+    case 1: hipLaunchKernelGGL((k_freq_fwd<S, 1>), dim3(l.nitems), dim3(256), 0, st, s, l.item0, l.run); break;
+    case 2: hipLaunchKernelGGL((k_freq_fwd<S, 2>), dim3(l.nitems), dim3(256), 0, st, s, l.item0, l.run); break;
+    case 4: hipLaunchKernelGGL((k_freq_fwd<S, 4>), dim3(l.nitems), dim3(256), 0, st, s, l.item0, l.run); break;
+    default: hipLaunchKernelGGL((k_freq_fwd<S, 8>), dim3(l.nitems), dim3(256), 0, st, s, l.item0, l.run); break;
   }
   return hipGetLastError();
 }

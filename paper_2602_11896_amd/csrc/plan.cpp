@@ -441,7 +441,8 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     fg.j2 = grp.j2;
     fg.s_t = p.log2T - grp.j2;
     fg.phiT = add_lowpass_time(p, grp.L2, p.sigmaT, grp.j2);
-    fg.TC = static_cast<int32_t>(std::min<int64_t>(grp.L2, 2048));
+    // at most 64 time chunks per group, at least 2048 samples per chunk (or the whole row)
+    fg.TC = static_cast<int32_t>(std::max<int64_t>(std::min<int64_t>(grp.L2, 2048), grp.L2 / 64));
     fg.n_tc = static_cast<int32_t>(grp.L2 / fg.TC);
     fg.part = p.part_total;
     p.part_total += static_cast<int64_t>(fg.n_tc) * p.R_pad * nF;
@@ -479,7 +480,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     for (int32_t S = 4; S <= 64; S *= 2) {
       int32_t RW = 4;
       while (RW > 1 && RW * (2 * S + 4 * FT) > 100) RW /= 2;
-      SigPlan::FwdLaunch fl{S, RW, FT, static_cast<int32_t>(p.fwd_items.size()), 0};
+      SigPlan::FwdLaunch fl{S, RW, FT, static_cast<int32_t>(p.fwd_items.size()), 0, 0};
       for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
         const FreqGroup& fg = p.fgroups[gi];
         const int32_t need = ((fg.K + 3) / 4);
@@ -489,6 +490,16 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
           for (int32_t rb = 0; rb < p.R_pad / (64 * RW); ++rb) p.fwd_items.push_back(FwdItem{gi, rb, tc, 0});
       }
       fl.nitems = static_cast<int32_t>(p.fwd_items.size()) - fl.item0;
+      // Items come in runs of R_pad / (64 RW) row blocks sharing one time chunk; the
+      // kernel gives each run to one XCD and consecutive runs to different XCDs, so the
+      // count is padded to a multiple of 8 runs.
+      // (measured: neutral in time, about 10x less HBM traffic for S <= 16; for S >= 32
+      // the few long runs unbalance the XCDs, so those launches keep plain round-robin)
+      fl.run = S >= 32 ? 1 : p.R_pad / (64 * RW);
+      while (fl.nitems % (8 * fl.run)) {
+        p.fwd_items.push_back(FwdItem{-1, 0, 0, 0});
+        ++fl.nitems;
+      }
       if (fl.nitems > 0) p.fwd_launches.push_back(fl);
     }
   }

@@ -208,3 +208,31 @@ def jtfs_backward(plan: Plan, x, dS, dx=None, ws=None, reuse_forward=False):
 
 def jtfs_metamer_step(plan: Plan, y, S_target, opt: Optimizer, loss, ws):
     return plan.metamer_step(y, S_target, opt, loss, ws)
+
+
+class MetamerGraph:
+    """One metamer step of a plan captured as a HIP graph, replayed once per iteration.
+
+    Capture needs the plan's device tables uploaded and every buffer allocated, so one
+    step is first run eagerly and its effect on y, the optimiser state and the loss is
+    undone before capturing. Replays are bitwise identical to eager steps (all kernels
+    are deterministic and the graph holds no memset node).
+    """
+
+    def __init__(self, plan: Plan, y: torch.Tensor, S_target: torch.Tensor, opt: Optimizer, loss: torch.Tensor,
+                 ws: torch.Tensor):
+        self.plan, self.y, self.S_target, self.opt, self.loss, self.ws = plan, y, S_target, opt, loss, ws
+        y0, st0, l0 = y.clone(), opt.state.clone(), loss.clone()
+        plan.metamer_step(y, S_target, opt, loss, ws)
+        torch.cuda.synchronize(y.device)
+        y.copy_(y0)
+        opt.state.copy_(st0)
+        loss.copy_(l0)
+        torch.cuda.synchronize(y.device)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            plan.metamer_step(y, S_target, opt, loss, ws)
+        torch.cuda.synchronize(y.device)
+
+    def step(self) -> None:
+        self.graph.replay()
