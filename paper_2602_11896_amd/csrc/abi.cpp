@@ -39,6 +39,8 @@ struct SigTables {
   const jtfs::RowJob* jobs;
   const jtfs::RowTask* tasks;
   const jtfs::GatherTerm* terms;
+  const int32_t* segs;
+  const int32_t* segterms;
   const int64_t* s_off;
 };
 
@@ -128,6 +130,8 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     append_bytes(buf, o, sp.terms);
     append_bytes(buf, o, p->block_off[s]);
     append_bytes(buf, o, sp.tasks);
+    append_bytes(buf, o, sp.segs);
+    append_bytes(buf, o, sp.segterms);
   }
   DeviceArena a;
   if (hipMalloc(&a.base, buf.size() + 256) != hipSuccess) return fail(JTFS_ERR_NOMEM, "hipMalloc of plan tables failed");
@@ -153,6 +157,8 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     t.terms = reinterpret_cast<const jtfs::GatherTerm*>(b + o[11]);
     t.s_off = reinterpret_cast<const int64_t*>(b + o[12]);
     t.tasks = reinterpret_cast<const jtfs::RowTask*>(b + o[13]);
+    t.segs = reinterpret_cast<const int32_t*>(b + o[14]);
+    t.segterms = reinterpret_cast<const int32_t*>(b + o[15]);
     a.sig.push_back(t);
   }
   if (p->sig.size() > 1) {
@@ -224,6 +230,8 @@ jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void
   d.jobs = t.jobs;
   d.tasks = t.tasks;
   d.terms = t.terms;
+  d.segs = t.segs;
+  d.segterms = t.segterms;
   d.s_off = t.s_off;
   d.Xh = reinterpret_cast<jtfs::c32*>(base + w.Xh);
   d.Z1 = reinterpret_cast<jtfs::c32*>(base + w.Z1);

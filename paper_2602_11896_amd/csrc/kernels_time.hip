@@ -13,9 +13,9 @@
 //  L1UH  U1hat = DFT(|Z1|)                       (Sec. 3.2)           [src/dst: row offset]
 //  L2Y   Y2 = IDFT_L2(fold_k2(U1hat . psi2^(k1)))  (Sec. 3.3)         [src: U1hat row, band, shift k2]
 //  BYH   dY2hat = DFT(dY2) (row-split partials already summed in split 0)  [src: dY2 row]
-//  BU    dU1 = Re IDFT_L1(sum_terms band . tile(term source))        [terms t0..t1]
+//  BU    dU1 = Re IDFT_L1(sum_terms band . tile(term source))        [segments from t0]
 //  BZH   dZ1hat = DFT(dU1 . Z1 / |Z1|)  (0 where Z1 = 0)              [src: dU1, aux: Z1]
-//  BX    dx = unpad Re IDFT_Npad(sum_n1 psi1 . tile(dZ1hat))          [terms t0..t1]
+//  BX    dx = unpad Re IDFT_Npad(sum_n1 psi1 . tile(dZ1hat))          [segments from t0]
 // fold_k averages the 2^k aliased blocks of a spectrum; tile is its transpose up to
 // 2^-k; with both, a filter-and-subsample step and its adjoint are exact.
 #include <hip/hip_runtime.h>
@@ -46,11 +46,14 @@ __device__ inline c32 fold_gather(const c32* src, const Band& b, const float* va
   return c32{acc.x * sc, acc.y * sc};
 }
 
-// Adjoint gather: sum over terms of band[m] * src_t[m mod len_t], output bin m.
-__device__ inline c32 term_gather(const DevSig& s, const c32* base, int t0, int t1, int m) {
+// Adjoint gather: sum over terms of band[m] * src_t[m mod len_t], output bin m; only the
+// terms whose band meets m's 512-bin segment are visited (seg0 = the row's first segment).
+__device__ inline c32 term_gather(const DevSig& s, const c32* base, int seg0, int m) {
   c32 acc{0.f, 0.f};
-  for (int t = t0; t < t1; ++t) {
-    const GatherTerm g = s.terms[t];
+  const int sg = seg0 + (m >> 9);
+  const int first = s.segs[2 * sg], count = s.segs[2 * sg + 1];
+  for (int i = 0; i < count; ++i) {
+    const GatherTerm g = s.terms[s.segterms[first + i]];
     const Band b = s.bands[g.band];
     int d = m - b.lo;
     if (d < 0) d += b.L;
@@ -115,7 +118,7 @@ template <>
 struct Ops<ST_BU> {
   static constexpr int DIR = +1;
   __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
-    return term_gather(s, s.dYh, j.t0, j.t1, idx);
+    return term_gather(s, s.dYh, j.t0, idx);
   }
   __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.dU1[j.dst + idx] = v.x; }
 };
@@ -136,7 +139,7 @@ template <>
 struct Ops<ST_BX> {
   static constexpr int DIR = +1;
   __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
-    return term_gather(s, s.dZh, j.t0, j.t1, idx);
+    return term_gather(s, s.dZh, j.t0, idx);
   }
   __device__ static void store(const DevSig& s, const RowJob&, int idx, c32 v) {
     const int k = idx - s.pad_left;

@@ -608,6 +608,26 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     r.t1 = static_cast<int32_t>(p.terms.size());
     emit(ST_BX, {r});
   }
+  // Segment lists of the adjoint gathers (rows with a term range).
+  for (RowJob& j : p.jobs) {
+    if (j.t1 <= j.t0) continue;
+    const int32_t nseg = (j.n + 511) / 512;
+    const int32_t seg0 = static_cast<int32_t>(p.segs.size() / 2);
+    for (int32_t sg = 0; sg < nseg; ++sg) {
+      const int64_t a = int64_t(sg) * 512, b = std::min<int64_t>(j.n, a + 512);
+      const int32_t first = static_cast<int32_t>(p.segterms.size());
+      for (int32_t t = j.t0; t < j.t1; ++t) {
+        const Band& bd = p.bands[p.terms[t].band];
+        const int64_t L = bd.L;
+        const bool meets = L != j.n || bd.len >= L || ((a - bd.lo) % L + L) % L < bd.len || ((bd.lo - a) % L + L) % L < b - a;
+        if (meets) p.segterms.push_back(t);
+      }
+      p.segs.push_back(first);
+      p.segs.push_back(static_cast<int32_t>(p.segterms.size()) - first);
+    }
+    j.t0 = seg0;
+    j.t1 = seg0 + nseg;
+  }
   p.s1_job0 = static_cast<int32_t>(p.jobs.size());
   for (int32_t n1 = 0; n1 < N1; ++n1) {
     int32_t k1 = p.psi1[n1].k;

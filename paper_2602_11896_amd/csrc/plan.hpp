@@ -87,6 +87,9 @@ struct SigPlan {
   std::vector<BwdItem> bwd_items;
   std::vector<RowJob> jobs;              // all stages; S1 jobs after the launches
   std::vector<GatherTerm> terms;
+  // Adjoint gathers: per 512-bin segment of a gather row, the terms whose band meets it
+  // (pairs: first index into segterms, count); the row's RowJob.t0 is its first segment.
+  std::vector<int32_t> segs, segterms;
   std::vector<Launch> launches[ST_COUNT];     // two-pass (n > 4096) launches
   std::vector<RowTask> tasks;                  // single-pass workgroup tasks of every stage
   int32_t task0[ST_COUNT] = {0}, ntask[ST_COUNT] = {0};

@@ -28,7 +28,7 @@ struct RowJob {
   int32_t src_len; // length of the input grid
   int32_t n;       // transform length (power of two)
   int32_t shift;   // Fourier subsampling exponent: the fold averages 2^shift blocks
-  int32_t t0, t1;  // term range [t0, t1) for multi-term gathers
+  int32_t t0, t1;  // adjoint gathers: first and end segment (built from a term range)
 };
 
 // A workgroup's share of a single-pass transform stage: `count` consecutive rows of
