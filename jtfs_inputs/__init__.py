@@ -24,6 +24,7 @@ __all__ = [
     "concatenated_signal",
     "white_noise_like",
     "batched_workload",
+    "decoder_init",
 ]
 
 
@@ -127,3 +128,22 @@ def batched_workload(n_signals: int = 64, meta_seed: int = 99, first_seed: int =
         rng = np.random.default_rng(first_seed + i)
         out.append((harmonic_am_signal(n, fs, rng), log2_T, F))
     return out
+
+
+def decoder_init(layers, kernel: int, leak: float, seed: int) -> np.ndarray:
+    """Seeded initial parameters of the warm-start decoder, packed flat.
+
+    ``layers`` lists (C_out, C_in, stride) per layer. Layer l contributes its weights
+    [C_out, C_in, kernel] (row-major) followed by its C_out biases. Weights are normal
+    with standard deviation gain / sqrt(fan_in), where fan_in = C_in * ceil(kernel / stride)
+    counts the taps that meet a non-zero sample after zero-stuffing, gain is
+    sqrt(2 / (1 + leak^2)) for hidden layers and 1 for the last; biases start at 0.
+    """
+    rng = np.random.default_rng(seed)
+    parts = []
+    for idx, (co, ci, s) in enumerate(layers):
+        fan_in = ci * (-(-kernel // s))
+        gain = 1.0 if idx == len(layers) - 1 else math.sqrt(2.0 / (1.0 + leak * leak))
+        parts.append(rng.normal(0.0, gain / math.sqrt(fan_in), size=co * ci * kernel))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts)
