@@ -188,6 +188,17 @@ jtfs_status jtfs_metamer_step(jtfs_plan_t plan, float* y, const float* S_target,
                               float* loss, void* ws, size_t ws_bytes, jtfs_stream_t stream);
 
 /*
+ * jtfs_loss - per-signal metamer loss and its gradient with respect to S (Sec. 2.3):
+ * loss[s] = scale ||S_s - T_s||^2 / N_s and dS_s = 2 scale (S_s - T_s) / N_s, where
+ * N_s = ||T_s||^2 if `relative` (the relative loss; N_s = 1 when T_s = 0) and 1 otherwise.
+ * S, S_target, dS: n_coeff_total device floats in the plan's coefficient layout (dS is
+ * overwritten and may not alias S or S_target); loss: batch device floats. Enqueued
+ * on `stream`; sums are taken in FP64 in a fixed order.
+ */
+jtfs_status jtfs_loss(jtfs_plan_t plan, const float* S, const float* S_target, float* dS, float* loss,
+                      int32_t relative, float scale, jtfs_stream_t stream);
+
+/*
  * Stage timing (for measurement). While enabled, every kernel stage enqueued by
  * jtfs_forward / jtfs_backward / jtfs_metamer_step on this plan is bracketed by two HIP
  * events on the same stream. jtfs_timing_read waits for the recorded events, writes
@@ -207,6 +218,65 @@ jtfs_status jtfs_timing_read(jtfs_plan_t plan, double* ms, int64_t* counts, int3
 
 /* Release a plan and its device tables. NULL is ignored. */
 void jtfs_plan_destroy(jtfs_plan_t plan);
+
+/* ------------------------------------------------------------------------------------
+ * Learned warm start (an addition to the method; the paper starts descent from noise,
+ * Sec. 2.3). A 1-D convolutional decoder maps the coefficients of one signal, read as
+ * c_in rows of n_frames frames (every block of the coefficient layout has n_frames
+ * frames per row), to a waveform y that seeds the descent:
+ *   a_0 = log(1 + S / eps);  z_l[o, t] = b_l[o] + sum_{i,k} W_l[o, i, k] up(a_{l-1})[i, t + k - 4]
+ *   a_l = max(z_l, leak z_l) for l < L;  y = z_L[0]
+ * where up() inserts stride[l] - 1 zeros after every sample (a transposed convolution
+ * with "same" alignment). Weights, activations and activation gradients are stored in
+ * bfloat16, products accumulate in FP32 (MFMA), parameters and Adam state are FP32.
+ *
+ * Parameters are one caller-owned FP32 device vector, layer by layer: W_l as
+ * [C_out][C_in][9] (row-major) followed by b_l[C_out]; C_in of layer 0 is c_in, C_out
+ * of the last layer is 1, every other count is `channels`.
+ * ------------------------------------------------------------------------------------ */
+typedef struct jtfs_dec_s* jtfs_dec_t;
+#define JTFS_DEC_MAX_LAYERS 8
+typedef struct {
+  int32_t c_in;        /* coefficient rows per frame (>= 1) */
+  int32_t n_frames;    /* frames per row (a multiple of 8) */
+  int32_t channels;    /* hidden channels: must be 128 */
+  int32_t kernel;      /* taps per filter: must be 9 */
+  int32_t n_layers;    /* 2 .. JTFS_DEC_MAX_LAYERS */
+  int32_t stride[JTFS_DEC_MAX_LAYERS];   /* upsampling factor per layer: 1, 2 or 4; the last must be 1 */
+  float leak;          /* leaky-ReLU slope, in (0, 1] */
+  float eps;           /* input compression scale (> 0) */
+} jtfs_dec_config;
+
+/* Validates the configuration and sizes the workspace for up to max_batch signals. */
+jtfs_status jtfs_dec_create(const jtfs_dec_config* cfg, int32_t max_batch, jtfs_dec_t* out);
+
+/* n_params: parameter vector length; out_len: samples per output waveform
+ * (n_frames times the product of the strides); ws_bytes: workspace for max_batch. */
+jtfs_status jtfs_dec_query(jtfs_dec_t dec, int64_t* n_params, int64_t* out_len, size_t* ws_bytes);
+
+/*
+ * jtfs_dec_forward - y[b] = decoder(S[b]) for b < batch <= max_batch. S: batch x c_in x
+ * n_frames device floats (coefficients, >= 0); y: batch x out_len device floats
+ * (overwritten). ws keeps the bfloat16 weights and every activation for jtfs_dec_backward.
+ */
+jtfs_status jtfs_dec_forward(jtfs_dec_t dec, const float* params, const float* S, int32_t batch, float* y, void* ws,
+                             size_t ws_bytes, jtfs_stream_t stream);
+
+/*
+ * jtfs_dec_backward - grad = d<dy, y>/d params summed over the batch (n_params device
+ * floats, overwritten). ws must hold the state of a jtfs_dec_forward call with the same
+ * params, batch and workspace, enqueued earlier on the same stream.
+ */
+jtfs_status jtfs_dec_backward(jtfs_dec_t dec, const float* params, int32_t batch, const float* dy, float* grad,
+                              void* ws, size_t ws_bytes, jtfs_stream_t stream);
+
+/* One bias-corrected Adam step on params (FP32); m, v: n_params device floats each,
+ * zero before step 1; step counts from 1. */
+jtfs_status jtfs_dec_adam_step(jtfs_dec_t dec, float* params, const float* grad, float* m, float* v, int64_t step,
+                               float lr, float beta1, float beta2, float eps, jtfs_stream_t stream);
+
+/* Release a decoder description. NULL is ignored. */
+void jtfs_dec_destroy(jtfs_dec_t dec);
 
 const char* jtfs_status_str(jtfs_status s);
 const char* jtfs_last_error(void);

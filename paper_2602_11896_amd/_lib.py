@@ -50,6 +50,15 @@ class jtfs_opt(ctypes.Structure):
                 ("bold_down", ctypes.c_float), ("state", c_void_p)]
 
 
+JTFS_DEC_MAX_LAYERS = 8
+
+
+class jtfs_dec_config(ctypes.Structure):
+    _fields_ = [("c_in", c_int32), ("n_frames", c_int32), ("channels", c_int32), ("kernel", c_int32),
+                ("n_layers", c_int32), ("stride", c_int32 * JTFS_DEC_MAX_LAYERS), ("leak", ctypes.c_float),
+                ("eps", ctypes.c_float)]
+
+
 # (name, restype, argtypes) for every exported function of include/jtfs.h
 SIGNATURES = [
     ("jtfs_plan", c_int32, [POINTER(jtfs_params), c_int32, POINTER(c_void_p)]),
@@ -66,9 +75,17 @@ SIGNATURES = [
     ("jtfs_backward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_uint32, c_void_p]),
     ("jtfs_metamer_step", c_int32, [c_void_p, c_void_p, c_void_p, POINTER(jtfs_opt), c_void_p, c_void_p, c_size_t,
                                     c_void_p]),
+    ("jtfs_loss", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, ctypes.c_float, c_void_p]),
     ("jtfs_timing_enable", c_int32, [c_void_p, c_int32]),
     ("jtfs_timing_read", c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64), c_int32]),
     ("jtfs_plan_destroy", None, [c_void_p]),
+    ("jtfs_dec_create", c_int32, [POINTER(jtfs_dec_config), c_int32, POINTER(c_void_p)]),
+    ("jtfs_dec_query", c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_size_t)]),
+    ("jtfs_dec_forward", c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("jtfs_dec_backward", c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("jtfs_dec_adam_step", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, c_void_p]),
+    ("jtfs_dec_destroy", None, [c_void_p]),
     ("jtfs_status_str", c_char_p, [c_int32]),
     ("jtfs_last_error", c_char_p, []),
 ]

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/jtfs.h"
+#include "dec.hpp"
 #include "device.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
@@ -545,6 +546,19 @@ jtfs_status jtfs_metamer_step(jtfs_plan_t plan, float* y, const float* S_target,
   });
 }
 
+jtfs_status jtfs_loss(jtfs_plan_t plan, const float* S, const float* S_target, float* dS, float* loss,
+                      int32_t relative, float scale, jtfs_stream_t stream) {
+  if (!plan || !S || !S_target || !dS || !loss) return fail(JTFS_ERR_ARG, "NULL argument");
+  if (dS == S || dS == S_target) return fail(JTFS_ERR_ARG, "dS may not alias S or S_target");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (size_t s = 0; s + 1 < plan->s_off.size(); ++s) {
+    const int64_t o = plan->s_off[s], n = plan->s_off[s + 1] - o;
+    const hipError_t e = jtfs::run_rel_loss(S + o, S_target + o, dS + o, loss + s, n, relative, scale, st);
+    if (e != hipSuccess) return fail(JTFS_ERR_HIP, std::string("loss kernel: ") + hipGetErrorString(e));
+  }
+  return JTFS_OK;
+}
+
 jtfs_status jtfs_timing_enable(jtfs_plan_t plan, int32_t on) {
   if (!plan) return fail(JTFS_ERR_ARG, "NULL plan");
   plan->timing = on != 0;
@@ -588,5 +602,14 @@ const char* jtfs_status_str(jtfs_status s) {
 }
 
 const char* jtfs_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+namespace jtfs {
+// Records the detail string of a failure for jtfs_last_error (used by the decoder ABI).
+jtfs_status report(jtfs_status s, const std::string& msg) { return fail(s, msg); }
+}  // namespace jtfs
+
+extern "C" {
 
 }  // extern "C"

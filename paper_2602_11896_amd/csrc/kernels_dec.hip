@@ -1,0 +1,748 @@
+// Warm-start decoder kernels: transposed-convolution layers as implicit GEMMs on
+// v_mfma_f32_16x16x32_bf16 (bfloat16 operands, FP32 accumulation), their data and
+// weight gradients, the one-channel output layer in FP32 vector arithmetic, Adam.
+//
+// Layer l:  z[o, t] = b[o] + sum_{i,k} W[o, i, k] up_s(a)[i, t + k - 4],  a' = lrelu(z).
+// Polyphase form used by every kernel: for output t = s m + r only the taps with
+// (r + k - 4) divisible by s meet a non-zero sample, at input u = m + (r + k - 4) / s.
+//
+// MFMA 16x16x32 operand layout (one wave): lane l holds row (l mod 16) of A and column
+// (l mod 16) of B, each as 8 consecutive K values starting at 8 (l / 16); the result
+// holds D[4 (l / 16) + v][l mod 16] in accumulator v. Both operands are loaded with the
+// same K order, so the product does not depend on how the unit orders K internally.
+#include <hip/hip_runtime.h>
+
+#include "dec.hpp"
+
+namespace jtfs {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kRowB = kDecC + 8;   // LDS row pitch of a bf16 tile (272 bytes)
+constexpr int kRowF = kDecC + 4;   // LDS row pitch of an FP32 tile
+constexpr int fwd_pitch(int s) { return s == 4 ? kDecC : kRowB; }
+
+__device__ inline f32x4 mma(uint4 a, uint4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                  0, 0);
+}
+
+// Round to nearest even (finite inputs).
+__device__ inline uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ inline float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ inline float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ inline float bf_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+__device__ inline int wave_index() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+__device__ inline uint4 ld16(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+__device__ inline void st16(uint16_t* p, uint4 v) { *reinterpret_cast<uint4*>(p) = v; }
+
+// Eight bf16 starting E elements into the 16 held by (lo, hi).
+template <int E>
+__device__ inline uint4 realign(uint4 lo, uint4 hi) {
+  const uint32_t d[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+  uint32_t o[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if constexpr (E % 2 == 0) {
+      o[i] = d[E / 2 + i];
+    } else {
+      o[i] = (d[E / 2 + i] >> 16) | (d[E / 2 + i + 1] << 16);
+    }
+  }
+  return uint4{o[0], o[1], o[2], o[3]};
+}
+
+// ---------------------------------------------------------------------------------------
+// Weight copies and input map
+
+__global__ void k_cast_wf(const float* __restrict__ W, int c_in, int cip, int c_out, uint16_t* __restrict__ wf) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(c_out) * kDecK * cip) return;
+  const int ci = static_cast<int>(i % cip);
+  const int k = static_cast<int>((i / cip) % kDecK);
+  const int co = static_cast<int>(i / (int64_t(cip) * kDecK));
+  wf[i] = ci < c_in ? f2bf(W[(int64_t(co) * c_in + ci) * kDecK + k]) : uint16_t(0);
+}
+
+__global__ void k_cast_wd(const float* __restrict__ W, int c_in, int c_out, uint16_t* __restrict__ wd) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(c_in) * kDecK * c_out) return;
+  const int co = static_cast<int>(i % c_out);
+  const int k = static_cast<int>((i / c_out) % kDecK);
+  const int ci = static_cast<int>(i / (int64_t(c_out) * kDecK));
+  wd[i] = f2bf(W[(int64_t(co) * c_in + ci) * kDecK + k]);
+}
+
+__global__ void k_cast_out(const float* __restrict__ W, int n, float* __restrict__ wo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) wo[i] = bf2f(f2bf(W[i]));
+}
+
+__global__ void k_dec_input(const float* __restrict__ S, int c_in, int F, int cip, float eps,
+                            uint16_t* __restrict__ x_tc, uint16_t* __restrict__ x_ct) {
+  const int b = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= F * cip) return;
+  const int c = i % cip, f = i / cip;
+  const uint16_t v = c < c_in ? f2bf(log1pf(S[(int64_t(b) * c_in + c) * F + f] / eps)) : uint16_t(0);
+  x_tc[(int64_t(b) * F + f) * cip + c] = v;
+  uint16_t* row = x_ct + (int64_t(b) * cip + c) * (F + 2 * kDecPad);
+  row[kDecPad + f] = v;
+  if (f < kDecPad) {
+    row[f] = 0;
+    row[kDecPad + F + f] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Hidden layer forward. Workgroup: batch item blockIdx.y, input rows m in [64 bx, 64 bx + 64),
+// all s phases, all 128 output channels. Wave w: 32 rows (w & 1) x 64 channels (w >> 1).
+
+template <int S>
+__global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x, int cip, int t_in,
+                                                  const uint16_t* __restrict__ wf, const float* __restrict__ bias,
+                                                  float leak, uint16_t* __restrict__ out_tc,
+                                                  uint16_t* __restrict__ out_ct) {
+  extern __shared__ uint16_t tile[];   // [64 S][P]; unpadded at S = 4 to stay within 64 KiB
+  constexpr int P = fwd_pitch(S);
+  const int b = blockIdx.y, m0 = blockIdx.x * kDecTile;
+  const int w = wave_index();
+  const int lane = threadIdx.x & 63, g = lane >> 4, li = lane & 15;
+  const int mw = m0 + 32 * (w & 1), cw = 64 * (w >> 1);
+  const int t_out = S * t_in;
+  const uint16_t* xb = x + int64_t(b) * t_in * cip;
+  const uint4 zero{0u, 0u, 0u, 0u};
+
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < kDecK; ++k) {
+      if ((r + k - kDecH + 4 * S) % S != 0) continue;
+      const int d = (r + k - kDecH) / S;   // exact division
+      const uint16_t* arow[2];
+      bool aok[2];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const int u = mw + 16 * mb + li + d;
+        aok[mb] = u >= 0 && u < t_in;
+        arow[mb] = xb + int64_t(aok[mb] ? u : 0) * cip + 8 * g;
+      }
+      const uint16_t* brow[4];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) brow[cb] = wf + (int64_t(cw + 16 * cb + li) * kDecK + k) * cip + 8 * g;
+      for (int c0 = 0; c0 < cip; c0 += 32) {
+        uint4 A[2], Bv[4];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) A[mb] = aok[mb] ? ld16(arow[mb] + c0) : zero;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) Bv[cb] = ld16(brow[cb] + c0);
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) acc[mb][cb] = mma(A[mb], Bv[cb], acc[mb][cb]);
+      }
+    }
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const int co = cw + 16 * cb + li;
+        const float bo = bias[co];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ml = 32 * (w & 1) + 16 * mb + 4 * g + v;
+          const float z = acc[mb][cb][v] + bo;
+          tile[(ml * S + r) * P + co] = f2bf(z > 0.f ? z : leak * z);
+        }
+      }
+  }
+  __syncthreads();
+  const int t0 = m0 * S;
+  // TC rows
+  for (int i = threadIdx.x; i < kDecTile * S * 16; i += 256) {
+    const int row = i >> 4, c8 = (i & 15) * 8;
+    if (t0 + row < t_out) st16(out_tc + (int64_t(b) * t_out + t0 + row) * kDecC + c8, ld16(tile + row * P + c8));
+  }
+  // CT rows: 8 consecutive samples of one channel per thread (neighbouring threads take
+  // neighbouring channels, so the LDS reads are conflict-free)
+  const int n8 = kDecTile * S / 8;
+  const int64_t ct_len = t_out + 2 * kDecPad;
+  for (int i = threadIdx.x; i < kDecC * n8; i += 256) {
+    const int co = i % kDecC, ch = i / kDecC;
+    const int t = t0 + 8 * ch;
+    if (t >= t_out) continue;
+    uint32_t o[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      o[e] = uint32_t(tile[(8 * ch + 2 * e) * P + co]) | (uint32_t(tile[(8 * ch + 2 * e + 1) * P + co]) << 16);
+    st16(out_ct + (int64_t(b) * kDecC + co) * ct_len + kDecPad + t, uint4{o[0], o[1], o[2], o[3]});
+  }
+  if (blockIdx.x == 0)
+    for (int co = threadIdx.x; co < kDecC; co += 256) st16(out_ct + (int64_t(b) * kDecC + co) * ct_len, uint4{0, 0, 0, 0});
+  if (blockIdx.x == gridDim.x - 1)
+    for (int co = threadIdx.x; co < kDecC; co += 256)
+      st16(out_ct + (int64_t(b) * kDecC + co) * ct_len + kDecPad + t_out, uint4{0, 0, 0, 0});
+}
+
+// ---------------------------------------------------------------------------------------
+// Shared epilogue of the data-gradient kernels: a bf16 tile of dz rows u in [u0, u0 + 64)
+// (LDS, pitch kRowB) goes to the polyphase layout of stride S2.
+template <int S2>
+__device__ void store_polyphase(const uint16_t* tile, int b, int u0, int t_rows, uint16_t* __restrict__ dzp) {
+  const int M2 = t_rows / S2;
+  const int64_t row_len = M2 + 2 * kDecPad;
+  constexpr int n8 = kDecTile / S2 / 8;
+  const int m20 = u0 / S2;
+  for (int i = threadIdx.x; i < kDecC * S2 * n8; i += 256) {
+    const int ci = i / (S2 * n8), rem = i % (S2 * n8), r2 = rem / n8, ch = rem % n8;
+    const int m2 = m20 + 8 * ch;
+    if (m2 >= M2) continue;
+    uint32_t o[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ua = S2 * (8 * ch + 2 * e) + r2, ub = S2 * (8 * ch + 2 * e + 1) + r2;
+      o[e] = uint32_t(tile[ua * kRowB + ci]) | (uint32_t(tile[ub * kRowB + ci]) << 16);
+    }
+    st16(dzp + ((int64_t(b) * kDecC + ci) * S2 + r2) * row_len + kDecPad + m2, uint4{o[0], o[1], o[2], o[3]});
+  }
+  if (u0 == 0)
+    for (int i = threadIdx.x; i < kDecC * S2; i += 256) st16(dzp + (int64_t(b) * kDecC * S2 + i) * row_len, uint4{0, 0, 0, 0});
+  if (u0 + kDecTile >= t_rows)
+    for (int i = threadIdx.x; i < kDecC * S2; i += 256)
+      st16(dzp + (int64_t(b) * kDecC * S2 + i) * row_len + kDecPad + M2, uint4{0, 0, 0, 0});
+}
+
+// Masks an FP32 tile of da (LDS, pitch kRowF) with lrelu'(a_prev), writes dz TC rows and
+// the bf16 tile for the polyphase store.
+__device__ void mask_store_tc(const float* ftile, uint16_t* btile, int b, int u0, int t_rows,
+                              const uint16_t* __restrict__ a_tc, float leak, uint16_t* __restrict__ dz_tc) {
+  for (int i = threadIdx.x; i < kDecTile * 16; i += 256) {
+    const int row = i >> 4, c8 = (i & 15) * 8;
+    const int u = u0 + row;
+    if (u >= t_rows) continue;
+    const int64_t off = (int64_t(b) * t_rows + u) * kDecC + c8;
+    const uint4 a = ld16(a_tc + off);
+    const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
+    uint32_t o[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float d0 = ftile[row * kRowF + c8 + 2 * e], d1 = ftile[row * kRowF + c8 + 2 * e + 1];
+      const float m0 = bf_lo(aw[e]) > 0.f ? d0 : leak * d0;
+      const float m1 = bf_hi(aw[e]) > 0.f ? d1 : leak * d1;
+      o[e] = uint32_t(f2bf(m0)) | (uint32_t(f2bf(m1)) << 16);
+    }
+    const uint4 v{o[0], o[1], o[2], o[3]};
+    st16(dz_tc + off, v);
+    st16(btile + row * kRowB + c8, v);
+  }
+}
+
+// Hidden layer data gradient. Rows u of the layer input, channels ci:
+//   da[u, ci] = sum_k sum_co W[co, ci, k] dz[s u - k + 4, co]
+// Workgroup: batch item blockIdx.y, rows [64 bx, 64 bx + 64); wave w: 32 rows x 64 channels.
+template <int S, int S2>
+__global__ __launch_bounds__(256) void k_conv_dgrad(const uint16_t* __restrict__ dz, int t_out,
+                                                    const uint16_t* __restrict__ wd, int t_in,
+                                                    const uint16_t* __restrict__ a_prev, float leak,
+                                                    uint16_t* __restrict__ dz_prev, uint16_t* __restrict__ dzp_prev) {
+  extern __shared__ float smem[];
+  float* ftile = smem;                                                     // [64][kRowF]
+  uint16_t* btile = reinterpret_cast<uint16_t*>(smem + kDecTile * kRowF);  // [64][kRowB]
+  const int b = blockIdx.y, u0 = blockIdx.x * kDecTile;
+  const int w = wave_index();
+  const int lane = threadIdx.x & 63, g = lane >> 4, li = lane & 15;
+  const int uw = u0 + 32 * (w & 1), cw = 64 * (w >> 1);
+  const uint16_t* db = dz + int64_t(b) * t_out * kDecC;
+  const uint4 zero{0u, 0u, 0u, 0u};
+  f32x4 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < kDecK; ++k) {
+    const uint16_t* arow[2];
+    bool aok[2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      const int u = uw + 16 * mb + li;
+      const int t = S * u - k + kDecH;
+      aok[mb] = u < t_in && t >= 0 && t < t_out;
+      arow[mb] = db + int64_t(aok[mb] ? t : 0) * kDecC + 8 * g;
+    }
+    const uint16_t* brow[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) brow[cb] = wd + (int64_t(cw + 16 * cb + li) * kDecK + k) * kDecC + 8 * g;
+#pragma unroll
+    for (int c0 = 0; c0 < kDecC; c0 += 32) {
+      uint4 A[2], Bv[4];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) A[mb] = aok[mb] ? ld16(arow[mb] + c0) : zero;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) Bv[cb] = ld16(brow[cb] + c0);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[mb][cb] = mma(A[mb], Bv[cb], acc[mb][cb]);
+    }
+  }
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        ftile[(32 * (w & 1) + 16 * mb + 4 * g + v) * kRowF + cw + 16 * cb + li] = acc[mb][cb][v];
+  __syncthreads();
+  mask_store_tc(ftile, btile, b, u0, t_in, a_prev, leak, dz_prev);
+  __syncthreads();
+  store_polyphase<S2>(btile, b, u0, t_in, dzp_prev);
+}
+
+// ---------------------------------------------------------------------------------------
+// Hidden layer weight gradient for one tap KT:
+//   dW[co, ci, KT] = sum_b sum_m dz_P[b, co, r, m] x[b, ci, m - q],  4 - KT = s q + r, 0 <= r < s.
+// Workgroup: one chunk of (b, m) (blockIdx.x), 64 input channels (blockIdx.y); all 128 output
+// channels, wave w owning rows [32 w, 32 w + 32). Partials [chunk][9][128][cip], summed later.
+template <int S, int KT>
+__device__ void wgrad_tap(const uint16_t* __restrict__ dzp, const uint16_t* __restrict__ xct, int M, int cip, int b,
+                          int m_begin, int m_end, int ci0, float* __restrict__ part) {
+  constexpr int r = ((kDecH - KT) % S + S) % S;
+  constexpr int q = (kDecH - KT - r) / S;
+  constexpr int sh = -q;                       // x is read at m + sh
+  constexpr int e = ((sh % 8) + 8) % 8;
+  constexpr int lo_off = sh < 0 ? -8 : 0;
+  const int w = wave_index();
+  const int lane = threadIdx.x & 63, g = lane >> 4, li = lane & 15;
+  const int64_t row_len = M + 2 * kDecPad;
+  const uint4 zero{0u, 0u, 0u, 0u};
+  const uint16_t* arow[2];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+    arow[mb] = dzp + ((int64_t(b) * kDecC + 32 * w + 16 * mb + li) * S + r) * row_len + kDecPad;
+  const uint16_t* brow[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) brow[nb] = xct + (int64_t(b) * cip + ci0 + 16 * nb + li) * row_len + kDecPad + lo_off;
+  f32x4 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int m = m_begin; m < m_end; m += 32) {
+    const int mm = m + 8 * g;
+    const bool ok = mm < m_end;
+    uint4 A[2], Bv[4];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) A[mb] = ok ? ld16(arow[mb] + mm) : zero;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      if (ok) {
+        const uint4 lo = ld16(brow[nb] + mm);
+        if constexpr (e == 0) {
+          Bv[nb] = lo;
+        } else {
+          Bv[nb] = realign<e>(lo, ld16(brow[nb] + mm + 8));
+        }
+      } else {
+        Bv[nb] = zero;
+      }
+    }
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = mma(A[mb], Bv[nb], acc[mb][nb]);
+  }
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        part[(int64_t(KT) * kDecC + 32 * w + 16 * mb + 4 * g + v) * cip + ci0 + 16 * nb + li] = acc[mb][nb][v];
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__ dzp, const uint16_t* __restrict__ xct,
+                                                    int M, int cip, int chunks_per_b, float* __restrict__ part) {
+  const int chunk = blockIdx.x;
+  const int b = chunk / chunks_per_b, mc = chunk % chunks_per_b;
+  const int m_begin = mc * kDecChunk;
+  const int m_end = min(M, m_begin + kDecChunk);
+  const int ci0 = 64 * blockIdx.y;
+  float* p = part + int64_t(chunk) * kDecK * kDecC * cip;
+  switch (blockIdx.z) {
+    case 0: wgrad_tap<S, 0>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p); break;
+    case 1: wgrad_tap<S, 1>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p); break;
+    case 2: wgrad_tap<S, 2>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p); break;
+    case 3: wgrad_tap<S, 3>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p); break;
+    case 4: wgrad_tap<S, 4>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p); break;
+    case 5: wgrad_tap<S, 5>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p); break;
+    case 6: wgrad_tap<S, 6>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p); break;
+    case 7: wgrad_tap<S, 7>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p); break;
+    default: wgrad_tap<S, 8>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p); break;
+  }
+}
+
+// grad[(co c_in + ci) 9 + k] = sum over chunks of part[chunk][k][co][ci], fixed order.
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int n_chunks, int cip, int c_in,
+                               float* __restrict__ grad) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;   // over (k, co, ci < cip)
+  const int64_t per = int64_t(kDecK) * kDecC * cip;
+  if (i >= per) return;
+  const int ci = static_cast<int>(i % cip);
+  if (ci >= c_in) return;
+  const int co = static_cast<int>((i / cip) % kDecC);
+  const int k = static_cast<int>(i / (int64_t(cip) * kDecC));
+  float acc = 0.f;
+  for (int c = 0; c < n_chunks; ++c) acc += part[c * per + i];
+  grad[(int64_t(co) * c_in + ci) * kDecK + k] = acc;
+}
+
+// db[co] = sum over (b, r, m) of a polyphase gradient row set; one block per channel.
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dzp, int S, int M, int batch,
+                                                   float* __restrict__ grad_b) {
+  __shared__ double red[256];
+  const int co = blockIdx.x;
+  const int64_t row_len = M + 2 * kDecPad;
+  double acc = 0.0;
+  for (int b = 0; b < batch; ++b)
+    for (int r = 0; r < S; ++r) {
+      const uint16_t* row = dzp + ((int64_t(b) * kDecC + co) * S + r) * row_len + kDecPad;
+      for (int m = threadIdx.x; m < M; m += 256) acc += bf2f(row[m]);
+    }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad_b[co] = static_cast<float>(red[0]);
+}
+
+// ---------------------------------------------------------------------------------------
+// Output layer (one channel, stride 1), FP32 arithmetic on bf16 activations.
+
+// 24 samples x[t0 - 8 .. t0 + 16) of a CT row (padded index t0 .. t0 + 24).
+__device__ inline void load24(const uint16_t* row, int t0, float v[24]) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const uint4 u = ld16(row + t0 + 8 * q);
+    const uint32_t wv[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      v[8 * q + 2 * e] = bf_lo(wv[e]);
+      v[8 * q + 2 * e + 1] = bf_hi(wv[e]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_out_fwd(const uint16_t* __restrict__ xct, int T, const float* __restrict__ wo,
+                                                 const float* __restrict__ bias, float* __restrict__ y) {
+  const int b = blockIdx.y;
+  const int t0 = 8 * (blockIdx.x * 256 + threadIdx.x);
+  if (t0 >= T) return;
+  const int64_t row_len = T + 2 * kDecPad;
+  float acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = bias[0];
+  for (int ci = 0; ci < kDecC; ++ci) {
+    float v[24];
+    load24(xct + (int64_t(b) * kDecC + ci) * row_len, t0, v);
+#pragma unroll
+    for (int k = 0; k < kDecK; ++k) {
+      const float wk = wo[ci * kDecK + k];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[i] += wk * v[i + k + 4];
+    }
+  }
+  float* yo = y + int64_t(b) * T + t0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) yo[i] = acc[i];
+}
+
+// dz of the last hidden layer: da[u, ci] = sum_k w[ci][k] dy[u - k + 4], masked.
+template <int S2>
+__global__ __launch_bounds__(256) void k_out_dgrad(const float* __restrict__ dy, int T, const float* __restrict__ wo,
+                                                   const uint16_t* __restrict__ a_tc, float leak,
+                                                   uint16_t* __restrict__ dz_tc, uint16_t* __restrict__ dzp) {
+  extern __shared__ float smem[];
+  float* ftile = smem;                                                     // [64][kRowF]
+  uint16_t* btile = reinterpret_cast<uint16_t*>(smem + kDecTile * kRowF);  // [64][kRowB]
+  __shared__ float dys[kDecTile + 8];
+  const int b = blockIdx.y, u0 = blockIdx.x * kDecTile;
+  for (int i = threadIdx.x; i < kDecTile + 8; i += 256) {
+    const int t = u0 - kDecH + i;
+    dys[i] = (t >= 0 && t < T) ? dy[int64_t(b) * T + t] : 0.f;
+  }
+  __syncthreads();
+  // thread: channel ci = tid & 127, rows (tid >> 7) + 2 j
+  const int ci = threadIdx.x & (kDecC - 1);
+  float wk[kDecK];
+#pragma unroll
+  for (int k = 0; k < kDecK; ++k) wk[k] = wo[ci * kDecK + k];
+  for (int row = threadIdx.x >> 7; row < kDecTile; row += 2) {
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < kDecK; ++k) acc += wk[k] * dys[row - k + 2 * kDecH];
+    ftile[row * kRowF + ci] = acc;
+  }
+  __syncthreads();
+  mask_store_tc(ftile, btile, b, u0, T, a_tc, leak, dz_tc);
+  __syncthreads();
+  store_polyphase<S2>(btile, b, u0, T, dzp);
+}
+
+// Partials of dW_out[ci][k] = sum_t dy[t] x[ci][t + k - 4] over 2048-sample chunks.
+// Block: chunk blockIdx.x, channels 16 blockIdx.y + (tid >> 4); 16 lanes split the chunk.
+__global__ __launch_bounds__(256) void k_out_wgrad(const float* __restrict__ dy, int T, const uint16_t* __restrict__ xct,
+                                                   int chunks_per_b, float* __restrict__ part) {
+  const int chunk = blockIdx.x;
+  const int b = chunk / chunks_per_b, tc = chunk % chunks_per_b;
+  const int t_begin = tc * kDecOutChunk, t_end = min(T, t_begin + kDecOutChunk);
+  const int ci = 16 * blockIdx.y + (threadIdx.x >> 4), sub = threadIdx.x & 15;
+  const int64_t row_len = T + 2 * kDecPad;
+  const uint16_t* row = xct + (int64_t(b) * kDecC + ci) * row_len;
+  float acc[kDecK];
+#pragma unroll
+  for (int k = 0; k < kDecK; ++k) acc[k] = 0.f;
+  for (int t0 = t_begin + 8 * sub; t0 < t_end; t0 += 128) {
+    float v[24];
+    load24(row, t0, v);
+    const float4 d0 = *reinterpret_cast<const float4*>(dy + int64_t(b) * T + t0);
+    const float4 d1 = *reinterpret_cast<const float4*>(dy + int64_t(b) * T + t0 + 4);
+    const float d[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+#pragma unroll
+    for (int k = 0; k < kDecK; ++k)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[k] += d[i] * v[i + k + 4];
+  }
+#pragma unroll
+  for (int k = 0; k < kDecK; ++k) {
+    float a = acc[k];
+    a += __shfl_xor(a, 8, 16);
+    a += __shfl_xor(a, 4, 16);
+    a += __shfl_xor(a, 2, 16);
+    a += __shfl_xor(a, 1, 16);
+    acc[k] = a;
+  }
+  if (sub == 0)
+#pragma unroll
+    for (int k = 0; k < kDecK; ++k) part[(int64_t(chunk) * kDecC + ci) * kDecK + k] = acc[k];
+}
+
+__global__ void k_out_wgrad_reduce(const float* __restrict__ part, int n_chunks, float* __restrict__ grad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kDecC * kDecK) return;
+  float acc = 0.f;
+  for (int c = 0; c < n_chunks; ++c) acc += part[int64_t(c) * kDecC * kDecK + i];
+  grad[i] = acc;
+}
+
+// Sum of n floats into out[0] (one block, fixed order).
+__global__ __launch_bounds__(256) void k_sum(const float* __restrict__ x, int64_t n, float* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) acc += x[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = static_cast<float>(red[0]);
+}
+
+// ---------------------------------------------------------------------------------------
+
+__global__ void k_dec_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                           float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
+                           float bc2) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float a = b1 * m[i] + (1.0f - b1) * gi;
+  const float c = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = a;
+  v[i] = c;
+  p[i] -= lr * (a / bc1) / (sqrtf(c / bc2) + eps);
+}
+
+__global__ __launch_bounds__(1024) void k_rel_loss(const float* __restrict__ S, const float* __restrict__ T,
+                                                   float* __restrict__ dS, float* __restrict__ loss, int64_t n,
+                                                   int relative, float scale) {
+  __shared__ double red[2][1024];
+  double e = 0.0, t2 = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double d = double(S[i]) - double(T[i]);
+    e += d * d;
+    t2 += double(T[i]) * double(T[i]);
+  }
+  red[0][threadIdx.x] = e;
+  red[1][threadIdx.x] = t2;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  const double norm = relative ? (red[1][0] > 0.0 ? red[1][0] : 1.0) : 1.0;
+  const float f = static_cast<float>(2.0 * scale / norm);
+  for (int64_t i = threadIdx.x; i < n; i += 1024) dS[i] = f * (S[i] - T[i]);
+  if (threadIdx.x == 0) loss[0] = static_cast<float>(scale * red[0][0] / norm);
+}
+
+inline int blocks_for(int64_t n, int per) { return static_cast<int>((n + per - 1) / per); }
+
+template <int S>
+hipError_t launch_fwd(const uint16_t* x_tc, int cip, int t_in, int batch, const uint16_t* wf, const float* bias,
+                      float leak, uint16_t* out_tc, uint16_t* out_ct, hipStream_t st) {
+  const size_t lds = size_t(kDecTile) * S * fwd_pitch(S) * sizeof(uint16_t);
+  hipLaunchKernelGGL(k_conv_fwd<S>, dim3(blocks_for(t_in, kDecTile), batch), dim3(256), lds, st, x_tc, cip, t_in, wf,
+                     bias, leak, out_tc, out_ct);
+  return hipGetLastError();
+}
+
+constexpr size_t kDgradLds = size_t(kDecTile) * kRowF * sizeof(float) + size_t(kDecTile) * kRowB * sizeof(uint16_t);
+
+template <int S, int S2>
+hipError_t launch_dgrad(const uint16_t* dz, int t_out, const uint16_t* wd, int t_in, int batch, const uint16_t* a_prev,
+                        float leak, uint16_t* dz_prev, uint16_t* dzp_prev, hipStream_t st) {
+  hipLaunchKernelGGL((k_conv_dgrad<S, S2>), dim3(blocks_for(t_in, kDecTile), batch), dim3(256), kDgradLds, st, dz,
+                     t_out, wd, t_in, a_prev, leak, dz_prev, dzp_prev);
+  return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_dgrad_s(int s2, const uint16_t* dz, int t_out, const uint16_t* wd, int t_in, int batch,
+                          const uint16_t* a_prev, float leak, uint16_t* dz_prev, uint16_t* dzp_prev, hipStream_t st) {
+  switch (s2) {
+    case 1: return launch_dgrad<S, 1>(dz, t_out, wd, t_in, batch, a_prev, leak, dz_prev, dzp_prev, st);
+    case 2: return launch_dgrad<S, 2>(dz, t_out, wd, t_in, batch, a_prev, leak, dz_prev, dzp_prev, st);
+    case 4: return launch_dgrad<S, 4>(dz, t_out, wd, t_in, batch, a_prev, leak, dz_prev, dzp_prev, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t run_dec_cast(const float* W, int c_in, int cip, int c_out, uint16_t* wf, uint16_t* wd, float* wout,
+                        hipStream_t st) {
+  if (wout) {
+    const int n = c_out * c_in * kDecK;
+    hipLaunchKernelGGL(k_cast_out, dim3(blocks_for(n, 256)), dim3(256), 0, st, W, n, wout);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_cast_wf, dim3(blocks_for(int64_t(c_out) * kDecK * cip, 256)), dim3(256), 0, st, W, c_in, cip,
+                     c_out, wf);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !wd) return e;
+  hipLaunchKernelGGL(k_cast_wd, dim3(blocks_for(int64_t(c_in) * kDecK * c_out, 256)), dim3(256), 0, st, W, c_in, c_out,
+                     wd);
+  return hipGetLastError();
+}
+
+hipError_t run_dec_input(const float* S, int batch, int c_in, int F, int cip, float eps, uint16_t* x_tc,
+                         uint16_t* x_ct, hipStream_t st) {
+  hipLaunchKernelGGL(k_dec_input, dim3(blocks_for(int64_t(F) * cip, 256), batch), dim3(256), 0, st, S, c_in, F, cip,
+                     eps, x_tc, x_ct);
+  return hipGetLastError();
+}
+
+hipError_t run_dec_conv_fwd(int s, const uint16_t* x_tc, int cip, int t_in, int batch, const uint16_t* wf,
+                            const float* bias, float leak, uint16_t* out_tc, uint16_t* out_ct, hipStream_t st) {
+  switch (s) {
+    case 1: return launch_fwd<1>(x_tc, cip, t_in, batch, wf, bias, leak, out_tc, out_ct, st);
+    case 2: return launch_fwd<2>(x_tc, cip, t_in, batch, wf, bias, leak, out_tc, out_ct, st);
+    case 4: return launch_fwd<4>(x_tc, cip, t_in, batch, wf, bias, leak, out_tc, out_ct, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t run_dec_out_fwd(const uint16_t* x_ct, int T, int batch, const float* wout, const float* bias, float* y,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_out_fwd, dim3(blocks_for(T / 8, 256), batch), dim3(256), 0, st, x_ct, T, wout, bias, y);
+  return hipGetLastError();
+}
+
+hipError_t run_dec_out_bwd(const float* dy, int T, int batch, const float* wout, const uint16_t* a_tc,
+                           const uint16_t* a_ct, float leak, int s2, uint16_t* dz_tc, uint16_t* dzp, float* part,
+                           float* grad_w, float* grad_b, hipStream_t st) {
+  const dim3 grid(blocks_for(T, kDecTile), batch);
+  switch (s2) {
+    case 1: hipLaunchKernelGGL(k_out_dgrad<1>, grid, dim3(256), kDgradLds, st, dy, T, wout, a_tc, leak, dz_tc, dzp); break;
+    case 2: hipLaunchKernelGGL(k_out_dgrad<2>, grid, dim3(256), kDgradLds, st, dy, T, wout, a_tc, leak, dz_tc, dzp); break;
+    case 4: hipLaunchKernelGGL(k_out_dgrad<4>, grid, dim3(256), kDgradLds, st, dy, T, wout, a_tc, leak, dz_tc, dzp); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int cpb = blocks_for(T, kDecOutChunk);
+  const int n_chunks = cpb * batch;
+  hipLaunchKernelGGL(k_out_wgrad, dim3(n_chunks, kDecC / 16), dim3(256), 0, st, dy, T, a_ct, cpb, part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_out_wgrad_reduce, dim3(blocks_for(kDecC * kDecK, 256)), dim3(256), 0, st, part, n_chunks,
+                     grad_w);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, dy, int64_t(batch) * T, grad_b);
+  return hipGetLastError();
+}
+
+hipError_t run_dec_dgrad(int s, int s2, const uint16_t* dz_tc, int t_out, const uint16_t* wd, int t_in, int batch,
+                         const uint16_t* a_prev_tc, float leak, uint16_t* dz_prev_tc, uint16_t* dzp_prev,
+                         hipStream_t st) {
+  switch (s) {
+    case 1: return launch_dgrad_s<1>(s2, dz_tc, t_out, wd, t_in, batch, a_prev_tc, leak, dz_prev_tc, dzp_prev, st);
+    case 2: return launch_dgrad_s<2>(s2, dz_tc, t_out, wd, t_in, batch, a_prev_tc, leak, dz_prev_tc, dzp_prev, st);
+    case 4: return launch_dgrad_s<4>(s2, dz_tc, t_out, wd, t_in, batch, a_prev_tc, leak, dz_prev_tc, dzp_prev, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t run_dec_wgrad(int s, const uint16_t* dzp, const uint16_t* x_ct, int t_in, int cip, int c_in, int batch,
+                         float* part, float* grad_w, float* grad_b, hipStream_t st) {
+  const int cpb = blocks_for(t_in, kDecChunk);
+  const int n_chunks = cpb * batch;
+  const dim3 grid(n_chunks, cip / 64, kDecK);
+  switch (s) {
+    case 1: hipLaunchKernelGGL(k_conv_wgrad<1>, grid, dim3(256), 0, st, dzp, x_ct, t_in, cip, cpb, part); break;
+    case 2: hipLaunchKernelGGL(k_conv_wgrad<2>, grid, dim3(256), 0, st, dzp, x_ct, t_in, cip, cpb, part); break;
+    case 4: hipLaunchKernelGGL(k_conv_wgrad<4>, grid, dim3(256), 0, st, dzp, x_ct, t_in, cip, cpb, part); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(int64_t(kDecK) * kDecC * cip, 256)), dim3(256), 0, st, part,
+                     n_chunks, cip, c_in, grad_w);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bias_grad, dim3(kDecC), dim3(256), 0, st, dzp, s, t_in, batch, grad_b);
+  return hipGetLastError();
+}
+
+hipError_t run_dec_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
+                        float eps, float bc1, float bc2, hipStream_t st) {
+  hipLaunchKernelGGL(k_dec_adam, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, g, m, v, n, lr, beta1, beta2, eps, bc1,
+                     bc2);
+  return hipGetLastError();
+}
+
+hipError_t run_rel_loss(const float* S, const float* T, float* dS, float* loss, int64_t n, int relative, float scale,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_rel_loss, dim3(1), dim3(1024), 0, st, S, T, dS, loss, n, relative, scale);
+  return hipGetLastError();
+}
+
+}  // namespace jtfs

@@ -174,6 +174,22 @@ class Plan:
                                           ws.numel(), _stream(y.device)), "jtfs_metamer_step")
 
 
+    def loss(self, S: torch.Tensor, S_target: torch.Tensor, dS: torch.Tensor = None, loss: torch.Tensor = None,
+             relative: bool = True, scale: float = 1.0):
+        """Per-signal (relative) loss and its gradient with respect to S (jtfs_loss); returns (loss, dS)."""
+        _require(S, self.n_coeff, "S")
+        _require(S_target, self.n_coeff, "S_target")
+        if dS is None:
+            dS = torch.empty(self.n_coeff, dtype=torch.float32, device=S.device)
+        if loss is None:
+            loss = torch.empty(self.batch, dtype=torch.float32, device=S.device)
+        _require(dS, self.n_coeff, "dS")
+        _require(loss, self.batch, "loss")
+        L.check(L.lib().jtfs_loss(self._h, _ptr(S), _ptr(S_target), _ptr(dS), _ptr(loss), int(bool(relative)),
+                                  float(scale), _stream(S.device)), "jtfs_loss")
+        return loss, dS
+
+
 class Optimizer:
     """Descent settings plus the device state buffer of jtfs_opt."""
 
@@ -208,6 +224,10 @@ def jtfs_backward(plan: Plan, x, dS, dx=None, ws=None, reuse_forward=False):
 
 def jtfs_metamer_step(plan: Plan, y, S_target, opt: Optimizer, loss, ws):
     return plan.metamer_step(y, S_target, opt, loss, ws)
+
+
+def jtfs_loss(plan: Plan, S, S_target, dS=None, loss=None, relative=True, scale=1.0):
+    return plan.loss(S, S_target, dS, loss, relative, scale)
 
 
 class MetamerGraph:

@@ -107,3 +107,50 @@ def test_fft_tile_index_logic_host_emulation(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.strip().endswith("OK")
+
+
+def _dec(cfg, max_batch=2):
+    from paper_2602_11896_amd.decoder import Decoder
+    return Decoder(cfg, max_batch)
+
+
+def test_decoder_sizes_match_oracle():
+    from oracle import decoder as OD
+    from paper_2602_11896_amd.decoder import DecoderConfig
+    for strides, c_in, F in (([1, 4, 4, 4, 2, 2, 2, 1], 266, 128), ([2, 1], 3, 8), ([4, 1, 2, 1], 20, 16)):
+        cfg = DecoderConfig(c_in=c_in, n_frames=F, strides=strides)
+        ocfg = OD.DecoderConfig(c_in=c_in, n_frames=F, strides=strides)
+        d = _dec(cfg, 4)
+        assert d.n_params == OD.n_params(ocfg)
+        assert d.out_len == ocfg.out_len
+        assert d.ws_bytes > 0
+
+
+@pytest.mark.parametrize("field,value", [("channels", 64), ("kernel", 7), ("n_frames", 12), ("c_in", 0),
+                                         ("strides", [1]), ("strides", [3, 1]), ("strides", [1, 2]),
+                                         ("leak", 0.0), ("eps", -1.0)])
+def test_decoder_rejects(field, value):
+    from paper_2602_11896_amd.decoder import DecoderConfig
+    cfg = DecoderConfig(c_in=10, n_frames=16, strides=[2, 1])
+    setattr(cfg, field, value)
+    with pytest.raises(L.JTFSError) as e:
+        _dec(cfg)
+    assert e.value.status in (L.JTFS_ERR_ARG, L.JTFS_ERR_UNSUPPORTED)
+
+
+def test_decoder_host_argument_errors():
+    from paper_2602_11896_amd.decoder import DecoderConfig
+    d = _dec(DecoderConfig(c_in=10, n_frames=16, strides=[2, 1]), 2)
+    lib = L.lib()
+    buf = ctypes.create_string_buffer(16)
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert lib.jtfs_dec_forward(d._h, p, p, 3, p, p, d.ws_bytes, None) == L.JTFS_ERR_ARG        # batch > max
+    assert lib.jtfs_dec_forward(d._h, p, p, 1, p, p, d.ws_bytes - 1, None) == L.JTFS_ERR_WORKSPACE
+    assert lib.jtfs_dec_forward(d._h, None, p, 1, p, p, d.ws_bytes, None) == L.JTFS_ERR_ARG
+    assert lib.jtfs_dec_backward(d._h, p, 0, p, p, p, d.ws_bytes, None) == L.JTFS_ERR_ARG
+    assert lib.jtfs_dec_adam_step(d._h, p, p, p, p, 0, 1e-3, 0.9, 0.999, 1e-8, None) == L.JTFS_ERR_ARG
+    assert lib.jtfs_dec_adam_step(d._h, p, p, p, p, 1, 1e-3, 1.0, 0.999, 1e-8, None) == L.JTFS_ERR_ARG
+    lib.jtfs_dec_destroy(None)
+    plan = J.Plan(J.Params(*CONFIGS["tiny"][:8], periodic=CONFIGS["tiny"][8]))
+    assert lib.jtfs_loss(plan._h, p, p, p, p, 1, 1.0, None) == L.JTFS_ERR_ARG               # dS aliases S
+    assert lib.jtfs_loss(plan._h, None, p, p, p, 1, 1.0, None) == L.JTFS_ERR_ARG
