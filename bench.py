@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 METRIC = "JTFS fwd+bwd iters/s at N=2^16; time to rel loss 1e-2, plain vs learned init"
 CFG2 = dict(n=65536, J=12, Q1=12, Q2=2, J_fr=4, Q_fr=2, log2_T=13, F=24.0)
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0   # dense
 PEAK_HBM_GBS = 8000.0
 
 
@@ -78,6 +79,66 @@ def cpu_baseline() -> dict:
                        f"{spent:.1f} s of CPU work measured")}
 
 
+def config4_part(n_signals: int) -> dict:
+    """Second half of the metric: time to relative loss 1e-2 from the learned start versus
+    white noise (held-out seeds 0..n-1, N = 2^16, Adam lr 0.1; see runs.config4)."""
+    from paper_2602_11896_amd import runs
+    r = runs.config4(n_signals=n_signals, learned_steps=100, plain_max_steps=5000, extra_target=1e-3,
+                     extra_cap=300)
+    keep = ("n_signals", "median_rel_loss_decoder", "learned_reached_0.01", "plain_reached_0.01",
+            "learned_median_seconds_0.01", "plain_median_seconds_0.01", "learned_median_steps_0.01",
+            "plain_median_steps_0.01", "learned_median_seconds_0.001", "plain_median_seconds_0.001",
+            "plain_seconds_per_step")
+    out = {k: r[k] for k in keep}
+    a, b = r["learned_median_seconds_0.01"], r["plain_median_seconds_0.01"]
+    out["speedup_to_0.01"] = round(b / a, 2) if a and b else None
+    return out
+
+
+def decoder_part(batch: int = 16, reps: int = 10) -> dict:
+    """Decoder forward + backward (weights and data gradients) at the trained shape, batch 16,
+    against the dense BF16 MFMA peak. Algorithmic work: per layer 9 C_in C_out MACs per
+    input sample (the non-zero taps after zero-stuffing), three times (forward, data
+    gradient except for the first layer, weight gradient), 2 flops per MAC."""
+    import numpy as np
+    import torch
+    import jtfs_inputs as ji
+    from paper_2602_11896_amd.decoder import Decoder, DecoderConfig
+    cfg = DecoderConfig()
+    dec = Decoder(cfg, batch)
+    theta = torch.as_tensor(ji.decoder_init(cfg.layer_shapes(), cfg.kernel, cfg.leak, 0), dtype=torch.float32,
+                            device="cuda")
+    rng = np.random.default_rng(0)
+    S = torch.as_tensor(np.exp(rng.uniform(-9, -2.3, batch * cfg.c_in * cfg.n_frames)), dtype=torch.float32,
+                        device="cuda")
+    dy = torch.as_tensor(rng.normal(size=batch * dec.out_len), dtype=torch.float32, device="cuda")
+    ws = dec.workspace()
+    y = torch.empty(batch * dec.out_len, device="cuda")
+    g = torch.empty(dec.n_params, device="cuda")
+    for _ in range(2):
+        dec.forward(theta, S, batch, y=y, ws=ws)
+        dec.backward(theta, dy, batch, ws, grad=g)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        dec.forward(theta, S, batch, y=y, ws=ws)
+        dec.backward(theta, dy, batch, ws, grad=g)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    T, macs = cfg.n_frames, 0.0
+    for i, (co, ci, s) in enumerate(cfg.layer_shapes()):
+        per = 9.0 * ci * co * T
+        macs += per * (3 if i > 0 else 2)
+        T *= s
+    flops = 2.0 * macs * batch
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"batch": batch, "ms_fwd_bwd": round(ms, 3), "algorithmic_gflop": round(flops / 1e9, 1),
+            "achieved": round(tf, 2), "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / PEAK_BF16_MFMA_TFLOPS, 4)}
+
+
 def hbm_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter record (FETCH_SIZE and
     WRITE_SIZE scaled by a copy of known size), or None when the kernel source changed
@@ -102,6 +163,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-config4", action="store_true", help="skip the learned-start and decoder measurements")
+    ap.add_argument("--config4-signals", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (to scale HBM counters)")
     args = ap.parse_args()
@@ -178,6 +241,9 @@ def main() -> int:
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
         "roofline": roofline,
     }
+    if not args.no_config4:
+        out["config4"] = config4_part(args.config4_signals)
+        out["decoder"] = decoder_part()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

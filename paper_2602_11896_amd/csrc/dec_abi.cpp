@@ -74,11 +74,13 @@ jtfs_status build(jtfs_dec_s& d) {
       ly.out_ct = take(size_t(B) * jtfs::kDecC * (ly.t_out + 2 * jtfs::kDecPad) * 2);
       ly.dz_tc = take(size_t(B) * ly.t_out * jtfs::kDecC * 2);
       ly.dzp = take(size_t(B) * jtfs::kDecC * ly.stride * (ly.t_in + 2 * jtfs::kDecPad) * 2);
-      part_bytes = std::max(part_bytes, size_t(jtfs::dec_chunks(static_cast<int>(B), ly.t_in)) * jtfs::kDecK *
-                                            jtfs::kDecC * ly.cip * sizeof(float));
+      // weight partials, then B * 128 bias partials
+      part_bytes = std::max(part_bytes, (size_t(jtfs::dec_chunks(static_cast<int>(B), ly.t_in)) * jtfs::kDecK *
+                                             jtfs::kDecC * ly.cip + size_t(B) * jtfs::kDecC) * sizeof(float));
     } else {
-      part_bytes = std::max(part_bytes, size_t(jtfs::dec_out_chunks(static_cast<int>(B), ly.t_out)) * jtfs::kDecC *
-                                            jtfs::kDecK * sizeof(float));
+      // weight partials, then one bias partial per 8192 samples of dy
+      part_bytes = std::max(part_bytes, (size_t(jtfs::dec_out_chunks(static_cast<int>(B), ly.t_out)) * jtfs::kDecC *
+                                             jtfs::kDecK + size_t((B * ly.t_out + 8191) / 8192)) * sizeof(float));
     }
     d.layers.push_back(ly);
     ci = ly.c_out;

@@ -410,25 +410,47 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int n_chunks, int
   grad[(int64_t(co) * c_in + ci) * kDecK + k] = acc;
 }
 
-// db[co] = sum over (b, r, m) of a polyphase gradient row set; one block per channel.
-__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dzp, int S, int M, int batch,
-                                                   float* __restrict__ grad_b) {
+// Sum of each contiguous bf16 row (one block per row, FP64 accumulation in a fixed order).
+// A polyphase gradient [B][128][s][8 + M + 8] read as B * 128 rows of s (M + 16) samples
+// gives the per-(batch item, channel) bias-gradient partials (the pads are zero).
+__global__ __launch_bounds__(256) void k_rowsum_bf16(const uint16_t* __restrict__ x, int64_t row_len,
+                                                     float* __restrict__ out) {
   __shared__ double red[256];
-  const int co = blockIdx.x;
-  const int64_t row_len = M + 2 * kDecPad;
+  const uint16_t* row = x + int64_t(blockIdx.x) * row_len;
   double acc = 0.0;
-  for (int b = 0; b < batch; ++b)
-    for (int r = 0; r < S; ++r) {
-      const uint16_t* row = dzp + ((int64_t(b) * kDecC + co) * S + r) * row_len + kDecPad;
-      for (int m = threadIdx.x; m < M; m += 256) acc += bf2f(row[m]);
-    }
+  for (int64_t m = threadIdx.x; m < row_len; m += 256) acc += bf2f(row[m]);
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) grad_b[co] = static_cast<float>(red[0]);
+  if (threadIdx.x == 0) out[blockIdx.x] = static_cast<float>(red[0]);
+}
+
+// out[c] = sum_{r < rows} x[r * cols + c], fixed order.
+__global__ void k_colsum(const float* __restrict__ x, int rows, int cols, float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float acc = 0.f;
+  for (int r = 0; r < rows; ++r) acc += x[int64_t(r) * cols + c];
+  out[c] = acc;
+}
+
+// Sum of each contiguous FP32 row of row_len values (the last row may be shorter).
+__global__ __launch_bounds__(256) void k_rowsum_f32(const float* __restrict__ x, int64_t n, int64_t row_len,
+                                                    float* __restrict__ out) {
+  __shared__ double red[256];
+  const int64_t a = int64_t(blockIdx.x) * row_len, b = min(n, a + row_len);
+  double acc = 0.0;
+  for (int64_t i = a + threadIdx.x; i < b; i += 256) acc += x[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = static_cast<float>(red[0]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -548,20 +570,6 @@ __global__ void k_out_wgrad_reduce(const float* __restrict__ part, int n_chunks,
   float acc = 0.f;
   for (int c = 0; c < n_chunks; ++c) acc += part[int64_t(c) * kDecC * kDecK + i];
   grad[i] = acc;
-}
-
-// Sum of n floats into out[0] (one block, fixed order).
-__global__ __launch_bounds__(256) void k_sum(const float* __restrict__ x, int64_t n, float* __restrict__ out) {
-  __shared__ double red[256];
-  double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) acc += x[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = static_cast<float>(red[0]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -697,7 +705,14 @@ hipError_t run_dec_out_bwd(const float* dy, int T, int batch, const float* wout,
   hipLaunchKernelGGL(k_out_wgrad_reduce, dim3(blocks_for(kDecC * kDecK, 256)), dim3(256), 0, st, part, n_chunks,
                      grad_w);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, dy, int64_t(batch) * T, grad_b);
+  // output bias: partial sums over 8192-sample rows of dy, then their sum (partials after the
+  // weight partials in `part`)
+  const int64_t n = int64_t(batch) * T;
+  const int nrow = static_cast<int>((n + 8191) / 8192);
+  float* bpart = part + int64_t(n_chunks) * kDecC * kDecK;
+  hipLaunchKernelGGL(k_rowsum_f32, dim3(nrow), dim3(256), 0, st, dy, n, int64_t(8192), bpart);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, st, bpart, nrow, 1, grad_b);
   return hipGetLastError();
 }
 
@@ -728,7 +743,12 @@ hipError_t run_dec_wgrad(int s, const uint16_t* dzp, const uint16_t* x_ct, int t
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(int64_t(kDecK) * kDecC * cip, 256)), dim3(256), 0, st, part,
                      n_chunks, cip, c_in, grad_w);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bias_grad, dim3(kDecC), dim3(256), 0, st, dzp, s, t_in, batch, grad_b);
+  // bias: per-(batch item, channel) sums after the weight partials in `part`, then over the batch
+  float* bpart = part + int64_t(n_chunks) * kDecK * kDecC * cip;
+  hipLaunchKernelGGL(k_rowsum_bf16, dim3(batch * kDecC), dim3(256), 0, st, dzp, int64_t(s) * (t_in + 2 * kDecPad),
+                     bpart);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kDecC), 0, st, bpart, batch, kDecC, grad_b);
   return hipGetLastError();
 }
 
