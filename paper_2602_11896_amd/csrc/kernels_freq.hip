@@ -231,10 +231,17 @@ __global__ __launch_bounds__(256) void k_freq_pool(DevSig s) {
     __syncthreads();
     for (int e = threadIdx.x; e < Mrows * fc; e += 256) {
       const int r = e / fc, fl = e - r * fc;
-      float acc = 0.f;
-      for (int tc = 0; tc < fg.n_tc; ++tc)
-        acc += s.part[fg.part + (static_cast<int64_t>(tc) * s.R_pad + ff.row0 + r) * nF + f0 + fl];
-      P[r * fc + fl] = acc;
+      // eight independent partial sums (eight loads in flight), combined in a fixed order
+      const float* src = s.part + fg.part + static_cast<int64_t>(ff.row0 + r) * nF + f0 + fl;
+      const int64_t stride = static_cast<int64_t>(s.R_pad) * nF;
+      float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      int tc = 0;
+      for (; tc + 8 <= fg.n_tc; tc += 8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] += src[(tc + j) * stride];
+      }
+      for (int j = 0; tc < fg.n_tc; ++tc, ++j) a[j] += src[tc * stride];
+      P[r * fc + fl] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
     __syncthreads();
     for (int e = threadIdx.x; e < nb * fc; e += 256) {
@@ -425,11 +432,11 @@ __device__ inline int next_live_tile(const DevSig& s, int rt, int rt_hi, int Kal
 }
 
 template <int MAXS, int MAXNT>
-__global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s) {
+__global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
   constexpr int WS = 4 * MAXS;               // LDS row stride (columns)
-  constexpr int PER = (16 * WS) / 256;       // W elements staged per thread
+  constexpr int PER = (16 * WS + 255) / 256;  // W elements staged per thread
   __shared__ c32 wt[2][16 * WS];
-  const BwdItem it = s.bwd_items[blockIdx.x];
+  const BwdItem it = s.bwd_items[item0 + blockIdx.x];
   const FreqGroup fg = s.fgroups[it.grp];
   const int wave = wave_id();
   const int lane = threadIdx.x & 63;
@@ -633,12 +640,19 @@ hipError_t run_freq_dP(const DevSig& s, const SigPlan& p, hipStream_t st) {
 }
 
 hipError_t run_freq_bwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
-  if (p.bwd_items.empty()) return hipSuccess;
-  if (p.NW <= 128)
-    hipLaunchKernelGGL((k_freq_bwd<32, 8>), dim3(p.bwd_items.size()), dim3(256), 0, st, s);
-  else
-    hipLaunchKernelGGL((k_freq_bwd<64, 16>), dim3(p.bwd_items.size()), dim3(256), 0, st, s);
-  return hipGetLastError();
+  for (const SigPlan::BwdLaunch& l : p.bwd_launches) {
+    const dim3 grid(l.nitems);
+    switch (l.S) {
+      case 4: hipLaunchKernelGGL((k_freq_bwd<4, 1>), grid, dim3(256), 0, st, s, l.item0); break;
+      case 8: hipLaunchKernelGGL((k_freq_bwd<8, 2>), grid, dim3(256), 0, st, s, l.item0); break;
+      case 16: hipLaunchKernelGGL((k_freq_bwd<16, 4>), grid, dim3(256), 0, st, s, l.item0); break;
+      case 32: hipLaunchKernelGGL((k_freq_bwd<32, 8>), grid, dim3(256), 0, st, s, l.item0); break;
+      default: hipLaunchKernelGGL((k_freq_bwd<64, 16>), grid, dim3(256), 0, st, s, l.item0); break;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace jtfs

@@ -441,8 +441,12 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     fg.j2 = grp.j2;
     fg.s_t = p.log2T - grp.j2;
     fg.phiT = add_lowpass_time(p, grp.L2, p.sigmaT, grp.j2);
-    // at most 64 time chunks per group, at least 2048 samples per chunk (or the whole row)
-    fg.TC = static_cast<int32_t>(std::max<int64_t>(std::min<int64_t>(grp.L2, 2048), grp.L2 / 64));
+    // Time chunks of the forward contraction: at least 256 samples (or the whole row), at
+    // most 128 chunks per group (64 when there are more than 16 frames, whose partial rows
+    // are longer). Smaller chunks give more workgroups to hide load latency; every chunk
+    // adds a partial row to sum (measured on MI355X at N = 2^16 with 8 and 128 frames).
+    const int64_t max_chunks = nF <= 16 ? 128 : 64;
+    fg.TC = static_cast<int32_t>(std::max<int64_t>(std::min<int64_t>(grp.L2, 256), grp.L2 / max_chunks));
     fg.n_tc = static_cast<int32_t>(grp.L2 / fg.TC);
     fg.part = p.part_total;
     p.part_total += static_cast<int64_t>(fg.n_tc) * p.R_pad * nF;
@@ -503,10 +507,20 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
       if (fl.nitems > 0) p.fwd_launches.push_back(fl);
     }
   }
-  for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
-    const FreqGroup& fg = p.fgroups[gi];
-    for (int32_t tb = 0; tb < fg.n_tb; ++tb)
-      for (int32_t rs = 0; rs < fg.RS; ++rs) p.bwd_items.push_back(BwdItem{gi, tb, rs, 0});
+  // Backward items bucketed like the forward, so that a group's launch sizes its
+  // registers and its staged W tiles (4 S columns) to its own row count.
+  for (int32_t S = 4; S <= 64; S *= 2) {
+    SigPlan::BwdLaunch bl{S, static_cast<int32_t>(p.bwd_items.size()), 0};
+    for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
+      const FreqGroup& fg = p.fgroups[gi];
+      const int32_t need = (fg.K + 3) / 4;
+      const int32_t bucket = need <= 4 ? 4 : need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 64;
+      if (bucket != S) continue;
+      for (int32_t tb = 0; tb < fg.n_tb; ++tb)
+        for (int32_t rs = 0; rs < fg.RS; ++rs) p.bwd_items.push_back(BwdItem{gi, tb, rs, 0});
+    }
+    bl.nitems = static_cast<int32_t>(p.bwd_items.size()) - bl.item0;
+    if (bl.nitems > 0) p.bwd_launches.push_back(bl);
   }
 
   // ---- row jobs of the time-axis stages, grouped by transform length

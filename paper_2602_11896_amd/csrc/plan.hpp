@@ -85,6 +85,12 @@ struct SigPlan {
   };
   std::vector<FwdLaunch> fwd_launches;
   std::vector<BwdItem> bwd_items;
+  // Backward launches, one per k-step bucket S (4..64; the groups with 4(S/2) < K <= 4S),
+  // each over bwd_items[item0, item0 + nitems).
+  struct BwdLaunch {
+    int32_t S, item0, nitems;
+  };
+  std::vector<BwdLaunch> bwd_launches;
   std::vector<RowJob> jobs;              // all stages; S1 jobs after the launches
   std::vector<GatherTerm> terms;
   // Adjoint gathers: per 512-bin segment of a gather row, the terms whose band meets it
