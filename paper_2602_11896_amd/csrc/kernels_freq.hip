@@ -275,17 +275,27 @@ __device__ inline int real_filter_of_row(const DevSig& s, int row) {
 __device__ inline c32 order1_v(const DevSig& s, int row, int f) {
   const c32* w = s.W + static_cast<int64_t>(row) * s.NW;
   const float* x = s.S1 + s.f_lo + f;
-  float vr = 0.f, vi = 0.f;
-  for (int n = 0; n < s.N1; ++n) {
-    const float a = x[static_cast<int64_t>(n) * s.nf_pad];
-    vr += w[n].x * a;
-    vi += w[n].y * a;
+  // four independent partial sums (loads in flight), combined in a fixed order
+  float vr[4] = {0.f, 0.f, 0.f, 0.f}, vi[4] = {0.f, 0.f, 0.f, 0.f};
+  int n = 0;
+  for (; n + 4 <= s.N1; n += 4) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float a = x[static_cast<int64_t>(n + j) * s.nf_pad];
+      vr[j] += w[n + j].x * a;
+      vi[j] += w[n + j].y * a;
+    }
   }
-  return c32{vr, vi};
+  for (int j = 0; n < s.N1; ++n, ++j) {
+    const float a = x[static_cast<int64_t>(n) * s.nf_pad];
+    vr[j] += w[n].x * a;
+    vi[j] += w[n].y * a;
+  }
+  return c32{(vr[0] + vr[1]) + (vr[2] + vr[3]), (vi[0] + vi[1]) + (vi[2] + vi[3])};
 }
 
-__global__ __launch_bounds__(256) void k_o1_v(DevSig s) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(64) void k_o1_v(DevSig s) {
+  const int e = blockIdx.x * 64 + threadIdx.x;
   if (e >= s.R_pad * s.nF) return;
   const int row = e / s.nF, f = e - row * s.nF;
   const int g = real_filter_of_row(s, row);
@@ -297,30 +307,33 @@ __global__ __launch_bounds__(256) void k_o1_v(DevSig s) {
   s.o1[e] = c32{u, 0.f};
 }
 
-// phi_F averaging along log-frequency and unpadding of the order-1 paths.
+// phi_F averaging along log-frequency and unpadding of the order-1 paths. One wave per
+// output: the lanes split the sum over rows, then a fixed butterfly combines them.
 __global__ __launch_bounds__(256) void k_o1_pool(DevSig s) {
   const int g = blockIdx.y;
   const FrFilter ff = s.frf[g];
   const int nF = s.nF;
   const int nb = (s.N1 + (1 << s.sF) - 1) >> s.sF;
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= nb * nF) return;
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (e >= nb * nF) return;   // whole waves leave together (no barriers below)
   const int b = e / nF, f = e - b * nF;
-  float v;
+  float v = 0.f;
   if (ff.lowpass) {
-    v = s.o1[(ff.row0 + b) * nF + f].x;
+    v = lane == 0 ? s.o1[(ff.row0 + b) * nF + f].x : 0.f;
   } else {
     const int sh = s.sF - ff.k;
     const float* ph = s.tables + ff.phiF;
-    v = 0.f;
-    for (int r = 0; r < ff.M; ++r) v += ph[((b << sh) - r) & (ff.M - 1)] * s.o1[(ff.row0 + r) * nF + f].x;
+    for (int r = lane; r < ff.M; r += 64) v += ph[((b << sh) - r) & (ff.M - 1)] * s.o1[(ff.row0 + r) * nF + f].x;
   }
-  s.S[s.s_off[s.n_groups * s.n_g + g] + e] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane == 0) s.S[s.s_off[s.n_groups * s.n_g + g] + e] = v;
 }
 
 // Adjoint of the order-1 paths, step 1: per (row, frame) the gradient of V.
-__global__ __launch_bounds__(256) void k_o1_dv(DevSig s) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(64) void k_o1_dv(DevSig s) {
+  const int e = blockIdx.x * 64 + threadIdx.x;
   if (e >= s.R_pad * s.nF) return;
   const int nF = s.nF;
   const int row = e / nF, f = e - row * nF;
@@ -348,24 +361,34 @@ __global__ __launch_bounds__(256) void k_o1_dv(DevSig s) {
 
 // Step 2: dS1 contribution of filter g, Re(W_g^H dV), on every padded frame (zero
 // outside the kept ones); summed over g in a fixed order later.
-__global__ __launch_bounds__(256) void k_o1_ds1(DevSig s) {
+__global__ __launch_bounds__(64) void k_o1_ds1(DevSig s) {
   const int g = blockIdx.y;
   const FrFilter ff = s.frf[g];
-  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int e = blockIdx.x * 64 + threadIdx.x;
   if (e >= s.N1 * s.nf_pad) return;
   const int n = e / s.nf_pad, f = e - n * s.nf_pad;
-  float acc = 0.f;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
   const int fl = f - s.f_lo;
   if (fl >= 0 && fl < s.nF) {
     const int nb = (s.N1 + (1 << s.sF) - 1) >> s.sF;
     const int rows = ff.lowpass ? nb : ff.M;
-    for (int r = 0; r < rows; ++r) {
+    // four independent partial sums (loads in flight), combined in a fixed order
+    int r = 0;
+    for (; r + 4 <= rows; r += 4) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const c32 w = s.W[static_cast<int64_t>(ff.row0 + r + j) * s.NW + n];
+        const c32 d = s.o1[(ff.row0 + r + j) * s.nF + fl];
+        acc[j] += w.x * d.x + w.y * d.y;
+      }
+    }
+    for (int j = 0; r < rows; ++r, ++j) {
       const c32 w = s.W[static_cast<int64_t>(ff.row0 + r) * s.NW + n];
       const c32 d = s.o1[(ff.row0 + r) * s.nF + fl];
-      acc += w.x * d.x + w.y * d.y;
+      acc[j] += w.x * d.x + w.y * d.y;
     }
   }
-  s.dS1p[static_cast<int64_t>(g) * s.N1 * s.nf_pad + e] = acc;
+  s.dS1p[static_cast<int64_t>(g) * s.N1 * s.nf_pad + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 // Sum of the row-split partials of dY2 into split 0 (fixed order), groups with RS > 1.
@@ -450,23 +473,39 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
   const int ncols = NT * 16;
   const c32* Y = s.Y2 + fg.y2;
 
-  float yre[MAXS], yim[MAXS];
+  // Y2 operands kept as y_r, y_i - y_r and y_r + y_i: V = W Y2 by three real products
+  //   k1 = (w_r + w_i) y_r,  k2 = w_r (y_i - y_r),  k3 = w_i (y_r + y_i),
+  //   Re V = k1 - k3,  Im V = k1 + k2.
+  // (the widest variant keeps four real products, y_r and y_i, for want of registers)
+  constexpr bool G3 = MAXS <= 32;
+  float yre[MAXS], ydf[MAXS], ysm[G3 ? MAXS : 1];
 #pragma unroll
   for (int q = 0; q < MAXS; ++q) {
     yre[q] = 0.f;
-    yim[q] = 0.f;
+    ydf[q] = 0.f;
+    if constexpr (G3) ysm[q] = 0.f;
     const int n = 4 * q + lk;
     if (active && n < K) {
       const c32 y = Y[static_cast<int64_t>(n) * L2 + t0 + li];
       yre[q] = y.x;
-      yim[q] = y.y;
+      if constexpr (G3) {
+        ydf[q] = y.y - y.x;
+        ysm[q] = y.x + y.y;
+      } else {
+        ydf[q] = y.y;
+      }
     }
   }
-  f4 dyr[MAXNT], dyi[MAXNT];
+  // dY2 = W^H dV accumulated the same way: with w = a + ib,
+  //   k1 = (a - b) dv_r,  k2 = a (dv_i - dv_r),  k3 = b (dv_r + dv_i),
+  //   Re dY2 = k1 + k3,  Im dY2 = k1 + k2.
+  // (four products, widest variant: dk1 = Re, dk2 = Im)
+  f4 dk1[MAXNT], dk2[MAXNT], dk3[G3 ? MAXNT : 1];
 #pragma unroll
   for (int q = 0; q < MAXNT; ++q) {
-    dyr[q] = f4{0.f, 0.f, 0.f, 0.f};
-    dyi[q] = f4{0.f, 0.f, 0.f, 0.f};
+    dk1[q] = f4{0.f, 0.f, 0.f, 0.f};
+    dk2[q] = f4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (G3) dk3[q] = f4{0.f, 0.f, 0.f, 0.f};
   }
   const int nrt = s.R_pad >> 4;
   const int rt_lo = it.rs * fg.rt_per_split;
@@ -503,16 +542,28 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
     const int r0 = rt * 16;
     const c32* w = wt[buf];
     if (active) {
-      f4 vr = {0.f, 0.f, 0.f, 0.f}, vi = {0.f, 0.f, 0.f, 0.f};
+      f4 k1 = {0.f, 0.f, 0.f, 0.f}, k2 = {0.f, 0.f, 0.f, 0.f}, k3 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int q = 0; q < MAXS; ++q) {
         if (4 * q >= nlo && 4 * q < nhi) {
           const c32 a = w[li * WS + 4 * q + lk];
-          vr = mfma(a.x, yre[q], vr);
-          vr = mfma(-a.y, yim[q], vr);
-          vi = mfma(a.x, yim[q], vi);
-          vi = mfma(a.y, yre[q], vi);
+          if constexpr (G3) {
+            k1 = mfma(a.x + a.y, yre[q], k1);
+            k2 = mfma(a.x, ydf[q], k2);
+            k3 = mfma(a.y, ysm[q], k3);
+          } else {   // k1 = Re V, k2 = Im V (ydf holds y_i)
+            k1 = mfma(a.x, yre[q], k1);
+            k1 = mfma(-a.y, ydf[q], k1);
+            k2 = mfma(a.x, ydf[q], k2);
+            k2 = mfma(a.y, yre[q], k2);
+          }
         }
+      }
+      f4 vr, vi;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        vr[v] = G3 ? k1[v] - k3[v] : k1[v];
+        vi[v] = G3 ? k1[v] + k2[v] : k2[v];
       }
       f4 du = {0.f, 0.f, 0.f, 0.f};
       const float* dPr = s.dP + fg.dP + static_cast<int64_t>(r0 + li) * nF;
@@ -525,13 +576,15 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
         }
         du = mfma(a, b, du);
       }
-      float dvr[4], dvi[4];
+      float dvr[4], ddf[4], dsm[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const float m = hw_sqrt(vr[v] * vr[v] + vi[v] * vi[v]);
         const float sc = m > 0.f ? du[v] / m : 0.f;
-        dvr[v] = vr[v] * sc;
-        dvi[v] = vi[v] * sc;
+        const float r = vr[v] * sc, i = vi[v] * sc;
+        dvr[v] = r;
+        ddf[v] = i - r;
+        dsm[v] = r + i;
       }
 #pragma unroll
       for (int nt = 0; nt < MAXNT; ++nt) {
@@ -539,10 +592,17 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const c32 a = w[(4 * lk + v) * WS + nt * 16 + li];
-            dyr[nt] = mfma(a.x, dvr[v], dyr[nt]);
-            dyr[nt] = mfma(a.y, dvi[v], dyr[nt]);
-            dyi[nt] = mfma(a.x, dvi[v], dyi[nt]);
-            dyi[nt] = mfma(-a.y, dvr[v], dyi[nt]);
+            if constexpr (G3) {
+              dk1[nt] = mfma(a.x - a.y, dvr[v], dk1[nt]);
+              dk2[nt] = mfma(a.x, ddf[v], dk2[nt]);
+              dk3[nt] = mfma(a.y, dsm[v], dk3[nt]);
+            } else {   // dv_i = ddf + dv_r
+              const float di = ddf[v] + dvr[v];
+              dk1[nt] = mfma(a.x, dvr[v], dk1[nt]);
+              dk1[nt] = mfma(a.y, di, dk1[nt]);
+              dk2[nt] = mfma(a.x, di, dk2[nt]);
+              dk2[nt] = mfma(-a.y, dvr[v], dk2[nt]);
+            }
           }
         }
       }
@@ -563,7 +623,11 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int n = nt * 16 + 4 * lk + v;
-        if (n < K) dst[static_cast<int64_t>(n) * L2 + t0 + li] = c32{dyr[nt][v], dyi[nt][v]};
+        if (n < K) {
+          c32 d{dk1[nt][v], dk2[nt][v]};
+          if constexpr (G3) d = c32{dk1[nt][v] + dk3[nt][v], dk1[nt][v] + dk2[nt][v]};
+          dst[static_cast<int64_t>(n) * L2 + t0 + li] = d;
+        }
       }
     }
   }
@@ -572,18 +636,18 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
 }  // namespace
 
 hipError_t run_order1_fwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
-  const int rows = (p.R_pad * p.n_frames + 255) / 256;
-  hipLaunchKernelGGL(k_o1_v, dim3(rows), dim3(256), 0, st, s);
+  const int rows = (p.R_pad * p.n_frames + 63) / 64;
+  hipLaunchKernelGGL(k_o1_v, dim3(rows), dim3(64), 0, st, s);
   const int nb = (static_cast<int>(p.psi1.size()) + (1 << p.sF) - 1) >> p.sF;
-  hipLaunchKernelGGL(k_o1_pool, dim3((nb * p.n_frames + 255) / 256, p.fr_real.size()), dim3(256), 0, st, s);
+  hipLaunchKernelGGL(k_o1_pool, dim3((nb * p.n_frames + 3) / 4, p.fr_real.size()), dim3(256), 0, st, s);
   return hipGetLastError();
 }
 
 hipError_t run_order1_bwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
-  const int rows = (p.R_pad * p.n_frames + 255) / 256;
-  hipLaunchKernelGGL(k_o1_dv, dim3(rows), dim3(256), 0, st, s);
-  const int cells = (static_cast<int>(p.psi1.size()) * p.nf_pad + 255) / 256;
-  hipLaunchKernelGGL(k_o1_ds1, dim3(cells, p.fr_real.size()), dim3(256), 0, st, s);
+  const int rows = (p.R_pad * p.n_frames + 63) / 64;
+  hipLaunchKernelGGL(k_o1_dv, dim3(rows), dim3(64), 0, st, s);
+  const int cells = (static_cast<int>(p.psi1.size()) * p.nf_pad + 63) / 64;
+  hipLaunchKernelGGL(k_o1_ds1, dim3(cells, p.fr_real.size()), dim3(64), 0, st, s);
   return hipGetLastError();
 }
 
