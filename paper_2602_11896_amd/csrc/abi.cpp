@@ -42,6 +42,7 @@ struct SigTables {
   const jtfs::GatherTerm* terms;
   const int32_t* segs;
   const int32_t* segterms;
+  const jtfs::SplitTask* stasks;
   const int64_t* s_off;
 };
 
@@ -133,6 +134,7 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     append_bytes(buf, o, sp.tasks);
     append_bytes(buf, o, sp.segs);
     append_bytes(buf, o, sp.segterms);
+    append_bytes(buf, o, sp.stasks);
   }
   DeviceArena a;
   if (hipMalloc(&a.base, buf.size() + 256) != hipSuccess) return fail(JTFS_ERR_NOMEM, "hipMalloc of plan tables failed");
@@ -160,6 +162,7 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     t.tasks = reinterpret_cast<const jtfs::RowTask*>(b + o[13]);
     t.segs = reinterpret_cast<const int32_t*>(b + o[14]);
     t.segterms = reinterpret_cast<const int32_t*>(b + o[15]);
+    t.stasks = reinterpret_cast<const jtfs::SplitTask*>(b + o[16]);
     a.sig.push_back(t);
   }
   if (p->sig.size() > 1) {
@@ -233,6 +236,7 @@ jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void
   d.terms = t.terms;
   d.segs = t.segs;
   d.segterms = t.segterms;
+  d.stasks = t.stasks;
   d.s_off = t.s_off;
   d.Xh = reinterpret_cast<jtfs::c32*>(base + w.Xh);
   d.Z1 = reinterpret_cast<jtfs::c32*>(base + w.Z1);

@@ -24,6 +24,7 @@ struct DevSig {
   const GatherTerm* terms;
   const int32_t* segs;      // per gather segment: first index into segterms, count
   const int32_t* segterms;
+  const SplitTask* stasks;  // two-pass transform workgroups
   const int64_t* s_off;     // output offset of block (group gi, filter g) at gi*n_g + g;
                             // order-1 blocks at n_groups*n_g + (index in the real list)
   // ---- per-call arrays

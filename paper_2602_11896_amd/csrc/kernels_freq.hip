@@ -45,7 +45,7 @@ __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadId
 //   Re(ab) = P1 - P3,  Im(ab) = P1 + P2,
 // longer ones four (a_r b_r, a_i b_i, a_r b_i + a_i b_r), which needs fewer registers.
 constexpr int fwd_rw(int S, int FT) {
-  return 4 * (2 * S + 4 * FT) <= 100 ? 4 : (2 * (2 * S + 4 * FT) <= 100 ? 2 : 1);
+  return 2 * (2 * S + 4 * FT) <= 100 ? 2 : 1;
 }
 
 // Loads the Y2^T fragments and the Phi^T fragments of the 16-time tile starting at tt.

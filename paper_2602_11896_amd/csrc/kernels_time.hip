@@ -202,14 +202,17 @@ __global__ __launch_bounds__(256) void k_fft_rows(DevSig s, int task0) {
   }
 }
 
+// Two-pass transforms: every row of a stage, of any length above 4096, in one launch per
+// pass; each workgroup reads its row, length, block and scratch offset from the task list.
 template <int ST>
-__global__ __launch_bounds__(256) void k_fft_split1(DevSig s, int job0, int log2n) {
+__global__ __launch_bounds__(256) void k_fft_split1(DevSig s, int task0) {
   __shared__ c32 lds[4096];
   using O = Ops<ST>;
+  const SplitTask tk = s.stasks[task0 + blockIdx.x];
+  const int log2n = tk.log2n;
   const SplitGeom g = split_geom(log2n);
-  const int row = blockIdx.y;
-  const RowJob job = s.jobs[job0 + row];
-  const int n1_0 = blockIdx.x << g.log2C1;
+  const RowJob job = s.jobs[tk.job];
+  const int n1_0 = tk.blk << g.log2C1;
   for (int i = 0; i < 16; ++i) {
     int idx, slot;
     split_p1_load(g, n1_0, threadIdx.x + 256 * i, idx, slot);
@@ -217,7 +220,7 @@ __global__ __launch_bounds__(256) void k_fft_split1(DevSig s, int job0, int log2
   }
   __syncthreads();
   fft_tile<O::DIR>(lds, g.log2B, s.tw, s.log2_Npad);
-  c32* scr = s.scr + (static_cast<int64_t>(row) << log2n);
+  c32* scr = s.scr + tk.scr;
   const int tshift = s.log2_Npad - log2n;
   for (int i = 0; i < 16; ++i) {
     int slot, sidx, te;
@@ -229,14 +232,15 @@ __global__ __launch_bounds__(256) void k_fft_split1(DevSig s, int job0, int log2
 }
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_fft_split2(DevSig s, int job0, int log2n) {
+__global__ __launch_bounds__(256) void k_fft_split2(DevSig s, int task0) {
   __shared__ c32 lds[4096];
   using O = Ops<ST>;
+  const SplitTask tk = s.stasks[task0 + blockIdx.x];
+  const int log2n = tk.log2n;
   const SplitGeom g = split_geom(log2n);
-  const int row = blockIdx.y;
-  const RowJob job = s.jobs[job0 + row];
-  const int k2_0 = blockIdx.x << g.log2C2;
-  const c32* scr = s.scr + (static_cast<int64_t>(row) << log2n);
+  const RowJob job = s.jobs[tk.job];
+  const int k2_0 = tk.blk << g.log2C2;
+  const c32* scr = s.scr + tk.scr;
   for (int i = 0; i < 16; ++i) {
     const int e = threadIdx.x + 256 * i;
     lds[e] = scr[split_p2_load(g, k2_0, e)];
@@ -304,17 +308,10 @@ hipError_t run_stage_t(const DevSig& s, const SigPlan& p, hipStream_t st) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  for (const Launch& l : p.launches[ST]) {
-    const int log2n = 31 - __builtin_clz(static_cast<unsigned>(l.n));
-    {
-      const SplitGeom g = split_geom(log2n);
-      hipLaunchKernelGGL(k_fft_split1<ST>, dim3((1 << g.log2A) >> g.log2C1, l.njobs), dim3(256), 0, st, s, l.job0,
-                         log2n);
-      hipLaunchKernelGGL(k_fft_split2<ST>, dim3((1 << g.log2B) >> g.log2C2, l.njobs), dim3(256), 0, st, s, l.job0,
-                         log2n);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  if (p.split1_n[ST] > 0) {
+    hipLaunchKernelGGL(k_fft_split1<ST>, dim3(p.split1_n[ST]), dim3(256), 0, st, s, p.split1_0[ST]);
+    hipLaunchKernelGGL(k_fft_split2<ST>, dim3(p.split2_n[ST]), dim3(256), 0, st, s, p.split2_0[ST]);
+    return hipGetLastError();
   }
   return hipSuccess;
 }

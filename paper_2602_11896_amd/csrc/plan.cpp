@@ -2,6 +2,8 @@
 // once to FP32 when stored.
 #include "plan.hpp"
 
+#include "fft_core.hpp"
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -482,7 +484,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   {
     const int32_t FT = nF <= 16 ? 1 : nF <= 32 ? 2 : nF <= 64 ? 4 : 8;
     for (int32_t S = 4; S <= 64; S *= 2) {
-      int32_t RW = 4;
+      int32_t RW = 2;   // at most two row tiles per wave (measured: four cost occupancy)
       while (RW > 1 && RW * (2 * S + 4 * FT) > 100) RW /= 2;
       SigPlan::FwdLaunch fl{S, RW, FT, static_cast<int32_t>(p.fwd_items.size()), 0, 0};
       for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
@@ -529,6 +531,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   auto emit = [&](int stage, std::vector<RowJob> js) {
     std::stable_sort(js.begin(), js.end(), [](const RowJob& a, const RowJob& b) { return a.n > b.n; });
     p.task0[stage] = static_cast<int32_t>(p.tasks.size());
+    int64_t stage_scr = 0;
     size_t i = 0;
     while (i < js.size()) {
       size_t j = i;
@@ -536,7 +539,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
       Launch l{stage, js[i].n, static_cast<int32_t>(p.jobs.size()), static_cast<int32_t>(j - i)};
       for (size_t q = i; q < j; ++q) p.jobs.push_back(js[q]);
       if (l.n > 4096) {
-        p.scr_elems = std::max<int64_t>(p.scr_elems, int64_t(l.n) * l.njobs);
+        stage_scr += int64_t(l.n) * l.njobs;
         p.launches[stage].push_back(l);
       } else {
         const int32_t per = 4096 / l.n;
@@ -548,6 +551,22 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
       i = j;
     }
     p.ntask[stage] = static_cast<int32_t>(p.tasks.size()) - p.task0[stage];
+    // two-pass rows: one scratch row each, all lengths in one launch per pass
+    p.scr_elems = std::max(p.scr_elems, stage_scr);
+    for (int pass = 1; pass <= 2; ++pass) {
+      (pass == 1 ? p.split1_0 : p.split2_0)[stage] = static_cast<int32_t>(p.stasks.size());
+      int64_t scr = 0;
+      for (const Launch& l : p.launches[stage]) {
+        int32_t log2n = 0;
+        while ((1 << log2n) < l.n) ++log2n;
+        const SplitGeom g = split_geom(log2n);
+        const int32_t nblk = pass == 1 ? (1 << g.log2A) >> g.log2C1 : (1 << g.log2B) >> g.log2C2;
+        for (int32_t r = 0; r < l.njobs; ++r, scr += l.n)
+          for (int32_t b = 0; b < nblk; ++b) p.stasks.push_back(SplitTask{l.job0 + r, log2n, b, 0, scr});
+      }
+      (pass == 1 ? p.split1_n : p.split2_n)[stage] =
+          static_cast<int32_t>(p.stasks.size()) - (pass == 1 ? p.split1_0 : p.split2_0)[stage];
+    }
   };
   auto job = [](int64_t src, int64_t dst, int64_t aux, int32_t band, int32_t src_len, int32_t n, int32_t shift) {
     RowJob r{};

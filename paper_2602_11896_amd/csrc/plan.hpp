@@ -99,6 +99,12 @@ struct SigPlan {
   std::vector<Launch> launches[ST_COUNT];     // two-pass (n > 4096) launches
   std::vector<RowTask> tasks;                  // single-pass workgroup tasks of every stage
   int32_t task0[ST_COUNT] = {0}, ntask[ST_COUNT] = {0};
+  // Two-pass rows of a stage: every row of every length in one pass-1 launch and one
+  // pass-2 launch, each row with its own scratch (tasks of stage st: [split0, split0 + nsplit)
+  // for pass 1, then the same count shifted by nsplit1 for pass 2).
+  std::vector<SplitTask> stasks;
+  int32_t split1_0[ST_COUNT] = {0}, split1_n[ST_COUNT] = {0};
+  int32_t split2_0[ST_COUNT] = {0}, split2_n[ST_COUNT] = {0};
   int32_t s1_job0 = 0;                   // N1 jobs for the S1 stage
   // forward frequential work, in complex multiply-adds (contraction) and real ones (pooling)
   double mac_dense = 0, mac_banded = 0, mac_exec = 0, mac_pool = 0;

@@ -37,6 +37,13 @@ struct RowTask {
   int32_t job0, count, log2n, pad_;
 };
 
+// One workgroup of a two-pass (four-step) transform: its row job, log2 of the row length,
+// its column block (pass 1) or row block (pass 2), and the row's scratch offset.
+struct SplitTask {
+  int32_t job, log2n, blk, pad_;
+  int64_t scr;
+};
+
 // One term of a multi-term adjoint gather: out[m] += band[m] * src[m mod src_len]
 // for bins m of the output grid inside the band.
 struct GatherTerm {
