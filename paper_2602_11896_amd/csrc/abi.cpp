@@ -251,6 +251,7 @@ jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void
   d.dS1p = reinterpret_cast<float*>(base + w.dS1p);
   d.dU1 = reinterpret_cast<float*>(base + w.dU1);
   d.dZh = reinterpret_cast<jtfs::c32*>(base + w.dZh);
+  d.dXh = reinterpret_cast<jtfs::c32*>(base + w.dXh);
   d.o1 = reinterpret_cast<jtfs::c32*>(base + w.o1);
   d.N = static_cast<int32_t>(sp.N);
   d.N_pad = static_cast<int32_t>(sp.N_pad);

@@ -46,6 +46,7 @@ struct DevSig {
   float* dS1p;
   float* dU1;
   c32* dZh;
+  c32* dXh;   // gathered spectrum of the signal gradient (before the inverse DFT)
   c32* o1;                  // order-1 modulus / gradient rows (R_pad x nF)
   // ---- sizes
   int32_t N, N_pad, pad_left, log2_Npad;

@@ -138,14 +138,22 @@ struct Ops<ST_BZH> {
 template <>
 struct Ops<ST_BX> {
   static constexpr int DIR = +1;
-  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
-    return term_gather(s, s.dZh, j.t0, idx);
-  }
+  // the gather itself runs beforehand in k_bx_gather, over the whole spectrum at once
+  __device__ static c32 load(const DevSig& s, const RowJob&, int idx) { return s.dXh[idx]; }
   __device__ static void store(const DevSig& s, const RowJob&, int idx, c32 v) {
     const int k = idx - s.pad_left;
     if (k >= 0 && k < s.N) s.dx[k] = v.x;
   }
 };
+
+// Gather of the first-order adjoint onto the padded signal spectrum,
+//   dXhat[m] = sum_n1 psi1_n1[m] dZ1hat_n1[m mod L1_n1],
+// one thread per bin (the inverse DFT of stage BX reads the result).
+__global__ __launch_bounds__(256) void k_bx_gather(DevSig s, int job) {
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  if (m >= s.N_pad) return;
+  s.dXh[m] = term_gather(s, s.dZh, s.jobs[job].t0, m);
+}
 
 // One radix-2^LR pass over the tile (two barriers: all reads before any write).
 template <int DIR, int LR>
@@ -303,6 +311,11 @@ __global__ __launch_bounds__(256) void k_ds1h(DevSig s) {
 
 template <int ST>
 hipError_t run_stage_t(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  if (ST == ST_BX) {
+    hipLaunchKernelGGL(k_bx_gather, dim3((p.N_pad + 255) / 256), dim3(256), 0, st, s, p.bx_job);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (p.ntask[ST] > 0) {
     hipLaunchKernelGGL(k_fft_rows<ST>, dim3(p.ntask[ST]), dim3(256), 0, st, s, p.task0[ST]);
     hipError_t e = hipGetLastError();

@@ -639,6 +639,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     for (int32_t n1 = 0; n1 < N1; ++n1)
       p.terms.push_back(GatherTerm{p.z1_off[n1], p.band_psi1[n1], Np >> p.psi1[n1].k});
     r.t1 = static_cast<int32_t>(p.terms.size());
+    p.bx_job = static_cast<int32_t>(p.jobs.size());   // emit() appends this single row next
     emit(ST_BX, {r});
   }
   // Segment lists of the adjoint gathers (rows with a term range).

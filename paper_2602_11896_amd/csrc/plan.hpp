@@ -103,6 +103,7 @@ struct SigPlan {
   // pass-2 launch, each row with its own scratch (tasks of stage st: [split0, split0 + nsplit)
   // for pass 1, then the same count shifted by nsplit1 for pass 2).
   std::vector<SplitTask> stasks;
+  int32_t bx_job = -1;   // the job of the final gather onto the padded signal spectrum
   int32_t split1_0[ST_COUNT] = {0}, split1_n[ST_COUNT] = {0};
   int32_t split2_0[ST_COUNT] = {0}, split2_n[ST_COUNT] = {0};
   int32_t s1_job0 = 0;                   // N1 jobs for the S1 stage
