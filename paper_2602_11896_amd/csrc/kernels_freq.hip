@@ -212,6 +212,149 @@ __global__ __launch_bounds__(256, (S >= 32 ? 1 : 2)) void k_freq_fwd(DevSig s, i
   }
 }
 
+// Row-tile-loop forward (groups of at most 128 rows, at most 32 frames). Item: group, row
+// split, chunk of 64 MT times. Each wave keeps the Y2 operands (as y_r, y_i - y_r,
+// y_r + y_i) and the Phi_T^T fragments of its MT 16-time tiles in registers and loops over
+// the row tiles of the split; W tiles are staged in LDS, double buffered as in the backward.
+// Per row tile and time tile: V^T = Y2^T W^T by three real products
+//   k1 = y_r (w_r + w_i),  k2 = (y_i - y_r) w_r,  k3 = (y_r + y_i) w_i,
+//   Re V = k1 - k3,  Im V = k1 + k2,
+// then |V| in the accumulator layout and P^T += Phi_T^T |V^T|. The four waves' partial sums
+// of a row tile are added in a fixed order through LDS and written as the chunk's partial.
+template <int MAXS, int FT>
+__global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
+  constexpr int MT = (FT == 1 ? 32 : 16) / MAXS > 1 ? (FT == 1 ? 32 : 16) / MAXS : 1;
+  constexpr int WS = 4 * MAXS;                // LDS row stride (columns)
+  constexpr int PER = (16 * WS + 255) / 256;  // W elements staged per thread
+  __shared__ c32 wt[2][16 * WS];
+  __shared__ float red[2][4][FT * 256];
+  const FwdItem it = s.fwd_items[item0 + blockIdx.x];
+  const FreqGroup fg = s.fgroups[it.grp];
+  const int wave = wave_id();
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int L2 = fg.L2;
+  const int K = fg.K;
+  const int Kal = (K + 3) & ~3;
+  const int nF = s.nF;
+  const c32* Y = s.Y2 + fg.y2;
+  const float* phi = s.tables + fg.phiT;
+  const int tbase = it.tc * fg.TC;
+
+  float yre[MT][MAXS], ydf[MT][MAXS], ysm[MT][MAXS], ph[MT][FT][4];
+  bool act[MT];
+#pragma unroll
+  for (int j = 0; j < MT; ++j) {
+    const int t0 = tbase + (4 * j + wave) * 16;
+    act[j] = t0 < L2;
+#pragma unroll
+    for (int q = 0; q < MAXS; ++q) {
+      const int n = 4 * q + lk;
+      c32 y{0.f, 0.f};
+      if (act[j] && n < K) y = Y[static_cast<int64_t>(n) * L2 + t0 + li];
+      yre[j][q] = y.x;
+      ydf[j][q] = y.y - y.x;
+      ysm[j][q] = y.x + y.y;
+    }
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) {
+      const int f = ft * 16 + li;
+      const int fc = (s.f_lo + f) << fg.s_t;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        ph[j][ft][v] = (act[j] && f < nF) ? phi[(fc - (t0 + 4 * lk + v)) & (L2 - 1)] : 0.f;
+    }
+  }
+
+  const int nrt = s.R_pad >> 4;
+  const int rt_lo = it.rb * fg.rt_fwd;
+  const int rt_hi = min(nrt, rt_lo + fg.rt_fwd);
+  const int ncols = min(WS, s.NW);
+  c32 wreg[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    if (e < 16 * WS) {
+      const int rr = e / WS, n = e - rr * WS;
+      wt[0][e] = n < ncols ? s.W[static_cast<int64_t>(rt_lo * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
+    }
+  }
+  __syncthreads();
+  float* part = s.part + fg.part + static_cast<int64_t>(it.tc) * s.R_pad * nF;
+  int buf = 0;
+  for (int rt = rt_lo; rt < rt_hi; ++rt) {
+    const bool next = rt + 1 < rt_hi;
+    if (next) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        if (e < 16 * WS) {
+          const int rr = e / WS, n = e - rr * WS;
+          wreg[i] = n < ncols ? s.W[static_cast<int64_t>((rt + 1) * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
+        }
+      }
+    }
+    const int nlo = s.rt_nrange[2 * rt];
+    const int nhi = min(s.rt_nrange[2 * rt + 1], Kal);
+    const c32* w = wt[buf];
+    f4 pacc[FT];
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) pacc[ft] = f4{0.f, 0.f, 0.f, 0.f};
+    if (nhi > nlo) {
+#pragma unroll
+      for (int j = 0; j < MT; ++j) {
+        if (act[j]) {
+          f4 k1 = {0.f, 0.f, 0.f, 0.f}, k2 = {0.f, 0.f, 0.f, 0.f}, k3 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int q = 0; q < MAXS; ++q) {
+            if (4 * q >= nlo && 4 * q < nhi) {
+              const c32 a = w[li * WS + 4 * q + lk];
+              k1 = mfma(yre[j][q], a.x + a.y, k1);
+              k2 = mfma(ydf[j][q], a.x, k2);
+              k3 = mfma(ysm[j][q], a.y, k3);
+            }
+          }
+          float u[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float re = k1[v] - k3[v], im = k1[v] + k2[v];
+            u[v] = hw_sqrt(re * re + im * im);
+          }
+#pragma unroll
+          for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) pacc[ft] = mfma(ph[j][ft][v], u[v], pacc[ft]);
+        }
+      }
+    }
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[buf][wave][ft * 256 + lane * 4 + v] = pacc[ft][v];
+    if (next) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        if (e < 16 * WS) wt[buf ^ 1][e] = wreg[i];
+      }
+    }
+    __syncthreads();
+    // P^T[f][r] of this row tile: element e = ft 256 + lane 4 + v holds frame
+    // ft 16 + 4 (lane / 16) + v of row lane mod 16
+#pragma unroll
+    for (int i = 0; i < FT; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int ln = (e & 255) >> 2, v = e & 3;
+      const int f = (e >> 8) * 16 + 4 * (ln >> 4) + v;
+      if (f < nF) {
+        const float sum = (red[buf][0][e] + red[buf][1][e]) + (red[buf][2][e] + red[buf][3][e]);
+        part[static_cast<int64_t>(rt * 16 + (ln & 15)) * nF + f] = sum;
+      }
+    }
+    buf ^= 1;
+  }
+}
+
 // Sum of the time-chunk partials, phi_F averaging along log-frequency (band-pass g) or
 // nothing more (g = phi_F), log-frequency unpadding, store into S.
 __global__ __launch_bounds__(256) void k_freq_pool(DevSig s) {
@@ -673,8 +816,30 @@ hipError_t launch_fwd_s(const DevSig& s, const SigPlan::FwdLaunch& l, hipStream_
   return hipGetLastError();
 }
 
+template <int S>
+hipError_t launch_fwd2_s(const DevSig& s, const SigPlan::FwdLaunch& l, hipStream_t st) {
+  switch (l.FT) {
+    case 1: hipLaunchKernelGGL((k_freq_fwd2<S, 1>), dim3(l.nitems), dim3(256), 0, st, s, l.item0); break;
+    case 2: hipLaunchKernelGGL((k_freq_fwd2<S, 2>), dim3(l.nitems), dim3(256), 0, st, s, l.item0); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t run_freq_fwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
   for (const SigPlan::FwdLaunch& l : p.fwd_launches) {
+    if (l.RW == 0) {   // row-tile-loop kernel
+      hipError_t e;
+      switch (l.S) {
+        case 4: e = launch_fwd2_s<4>(s, l, st); break;
+        case 8: e = launch_fwd2_s<8>(s, l, st); break;
+        case 16: e = launch_fwd2_s<16>(s, l, st); break;
+        case 32: e = launch_fwd2_s<32>(s, l, st); break;
+        default: return hipErrorInvalidValue;
+      }
+      if (e != hipSuccess) return e;
+      continue;
+    }
     if (l.RW != fwd_rw(l.S, l.FT)) return hipErrorInvalidValue;   // plan and kernel disagree
     hipError_t e;
     switch (l.S) {

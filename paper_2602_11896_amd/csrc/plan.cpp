@@ -435,6 +435,16 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   }
   const int32_t nF = p.n_frames;
   const int32_t n_rt = p.R_pad / 16;
+  const int32_t FT = nF <= 16 ? 1 : nF <= 32 ? 2 : nF <= 64 ? 4 : 8;
+  auto bucket_of = [](int32_t K) {
+    const int32_t need = (K + 3) / 4;
+    return need <= 4 ? 4 : need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 64;
+  };
+  // Forward kernel per group: the row-tile-loop kernel (W tiles in LDS, each wave keeping
+  // MT 16-time tiles of Y2 in registers) where its registers allow (S <= 32, FT <= 2),
+  // otherwise the register-W kernel.
+  auto fwd_loop = [&](int32_t S) { return S <= 32 && FT <= 2; };
+  auto fwd_mt = [&](int32_t S) { return std::max(1, (FT == 1 ? 32 : 16) / S); };
   for (const Grp& grp : p.groups) {
     FreqGroup fg{};
     fg.y2 = p.y2_total;
@@ -448,8 +458,19 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     // are longer). Smaller chunks give more workgroups to hide load latency; every chunk
     // adds a partial row to sum (measured on MI355X at N = 2^16 with 8 and 128 frames).
     const int64_t max_chunks = nF <= 16 ? 128 : 64;
-    fg.TC = static_cast<int32_t>(std::max<int64_t>(std::min<int64_t>(grp.L2, 256), grp.L2 / max_chunks));
-    fg.n_tc = static_cast<int32_t>(grp.L2 / fg.TC);
+    const int32_t S = bucket_of(grp.K);
+    if (fwd_loop(S)) {
+      // a workgroup's four waves cover 64 MT consecutive times (the last chunk may be short)
+      fg.TC = 64 * fwd_mt(S);
+      fg.n_tc = static_cast<int32_t>(std::max<int64_t>(1, grp.L2 / fg.TC));
+      const int32_t want = (512 + fg.n_tc - 1) / fg.n_tc;
+      const int32_t rs = std::max(1, std::min(want, n_rt / 4));
+      fg.rt_fwd = (n_rt + rs - 1) / rs;
+    } else {
+      fg.TC = static_cast<int32_t>(std::max<int64_t>(std::min<int64_t>(grp.L2, 256), grp.L2 / max_chunks));
+      fg.n_tc = static_cast<int32_t>(grp.L2 / fg.TC);
+      fg.rt_fwd = 0;
+    }
     fg.part = p.part_total;
     p.part_total += static_cast<int64_t>(fg.n_tc) * p.R_pad * nF;
     fg.dP = p.dP_total;
@@ -482,16 +503,27 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   // (a power of two), FT = 16-frame tiles, RW = 16-row tiles per wave chosen so that the
   // register-resident operands of a wave stay near 100 VGPRs.
   {
-    const int32_t FT = nF <= 16 ? 1 : nF <= 32 ? 2 : nF <= 64 ? 4 : 8;
     for (int32_t S = 4; S <= 64; S *= 2) {
+      if (fwd_loop(S)) {
+        // items (group, row split, time chunk)
+        SigPlan::FwdLaunch fl{S, 0, FT, static_cast<int32_t>(p.fwd_items.size()), 0, 0};
+        for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
+          const FreqGroup& fg = p.fgroups[gi];
+          if (bucket_of(fg.K) != S) continue;
+          const int32_t nrs = (n_rt + fg.rt_fwd - 1) / fg.rt_fwd;
+          for (int32_t tc = 0; tc < fg.n_tc; ++tc)
+            for (int32_t rs = 0; rs < nrs; ++rs) p.fwd_items.push_back(FwdItem{gi, rs, tc, 0});
+        }
+        fl.nitems = static_cast<int32_t>(p.fwd_items.size()) - fl.item0;
+        if (fl.nitems > 0) p.fwd_launches.push_back(fl);
+        continue;
+      }
       int32_t RW = 2;   // at most two row tiles per wave (measured: four cost occupancy)
       while (RW > 1 && RW * (2 * S + 4 * FT) > 100) RW /= 2;
       SigPlan::FwdLaunch fl{S, RW, FT, static_cast<int32_t>(p.fwd_items.size()), 0, 0};
       for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
         const FreqGroup& fg = p.fgroups[gi];
-        const int32_t need = ((fg.K + 3) / 4);
-        const int32_t bucket = need <= 4 ? 4 : need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 64;
-        if (bucket != S) continue;
+        if (bucket_of(fg.K) != S) continue;
         for (int32_t tc = 0; tc < fg.n_tc; ++tc)
           for (int32_t rb = 0; rb < p.R_pad / (64 * RW); ++rb) p.fwd_items.push_back(FwdItem{gi, rb, tc, 0});
       }

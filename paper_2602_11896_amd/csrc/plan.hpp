@@ -80,7 +80,8 @@ struct SigPlan {
   std::vector<FreqGroup> fgroups;
   std::vector<FwdItem> fwd_items;       // grouped by kernel shape, see fwd_launches
   struct FwdLaunch {
-    int32_t S, RW, FT, item0, nitems;     // k-steps, row tiles per wave, frame tiles
+    int32_t S, RW, FT, item0, nitems;     // k-steps, row tiles per wave (0: row-tile-loop
+                                          // kernel, items = (group, row split, chunk)), frame tiles
     int32_t run;                          // consecutive items sharing a time chunk
   };
   std::vector<FwdLaunch> fwd_launches;

@@ -63,7 +63,7 @@ struct FreqGroup {
   int32_t TC, n_tc;         // t-chunk length of the forward and number of chunks
   int32_t RS, rt_per_split; // backward row splits and row tiles per split
   int32_t n_tb;             // backward 64-column t-blocks
-  int32_t pad_;
+  int32_t rt_fwd;           // forward row tiles per row split (row-tile-loop forward kernel)
 };
 
 // Forward frequential work item: rows [rb*64, rb*64+64) x columns [tc*TC, (tc+1)*TC).
