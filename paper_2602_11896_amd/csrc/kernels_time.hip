@@ -187,10 +187,9 @@ __device__ void fft_tile(c32* lds, int log2n, const c32* tw, int log2tw) {
 
 // One workgroup per task: `count` rows of one length, all in one 4096-element tile.
 template <int ST>
-__global__ __launch_bounds__(256) void k_fft_rows(DevSig s, int task0) {
-  __shared__ c32 lds[4096];
+__device__ void rows_body(const DevSig& s, c32* lds, int task) {
   using O = Ops<ST>;
-  const RowTask tk = s.tasks[task0 + blockIdx.x];
+  const RowTask tk = s.tasks[task];
   const int log2n = tk.log2n;
   const int n = 1 << log2n;
 #pragma unroll 1
@@ -213,10 +212,9 @@ __global__ __launch_bounds__(256) void k_fft_rows(DevSig s, int task0) {
 // Two-pass transforms: every row of a stage, of any length above 4096, in one launch per
 // pass; each workgroup reads its row, length, block and scratch offset from the task list.
 template <int ST>
-__global__ __launch_bounds__(256) void k_fft_split1(DevSig s, int task0) {
-  __shared__ c32 lds[4096];
+__device__ void split1_body(const DevSig& s, c32* lds, int task) {
   using O = Ops<ST>;
-  const SplitTask tk = s.stasks[task0 + blockIdx.x];
+  const SplitTask tk = s.stasks[task];
   const int log2n = tk.log2n;
   const SplitGeom g = split_geom(log2n);
   const RowJob job = s.jobs[tk.job];
@@ -237,6 +235,17 @@ __global__ __launch_bounds__(256) void k_fft_split1(DevSig s, int task0) {
     if (O::DIR > 0) w.y = -w.y;
     scr[sidx] = cmul(lds[slot], w);
   }
+}
+
+// First launch of a stage: the short-row tasks (whole rows in one tile), then pass 1 of
+// every long row; the two sets are independent, so they share one launch.
+template <int ST>
+__global__ __launch_bounds__(256) void k_fft_stage1(DevSig s, int task0, int ntask, int split0) {
+  __shared__ c32 lds[4096];
+  if (static_cast<int>(blockIdx.x) < ntask)
+    rows_body<ST>(s, lds, task0 + blockIdx.x);
+  else
+    split1_body<ST>(s, lds, split0 + blockIdx.x - ntask);
 }
 
 template <int ST>
@@ -316,13 +325,13 @@ hipError_t run_stage_t(const DevSig& s, const SigPlan& p, hipStream_t st) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (p.ntask[ST] > 0) {
-    hipLaunchKernelGGL(k_fft_rows<ST>, dim3(p.ntask[ST]), dim3(256), 0, st, s, p.task0[ST]);
-    hipError_t e = hipGetLastError();
+  if (p.ntask[ST] + p.split1_n[ST] > 0) {
+    hipLaunchKernelGGL(k_fft_stage1<ST>, dim3(p.ntask[ST] + p.split1_n[ST]), dim3(256), 0, st, s, p.task0[ST],
+                       p.ntask[ST], p.split1_0[ST]);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (p.split1_n[ST] > 0) {
-    hipLaunchKernelGGL(k_fft_split1<ST>, dim3(p.split1_n[ST]), dim3(256), 0, st, s, p.split1_0[ST]);
+  if (p.split2_n[ST] > 0) {
     hipLaunchKernelGGL(k_fft_split2<ST>, dim3(p.split2_n[ST]), dim3(256), 0, st, s, p.split2_0[ST]);
     return hipGetLastError();
   }
