@@ -656,6 +656,21 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
   const float* phi = s.tables + fg.phiT;
   const int nF = s.nF;
   const int nFq = (nF + 3) >> 2;
+  // With at most 16 frames (and registers to spare), the Phi_T fragments of this wave's
+  // times are loaded once, and each row tile's pooled gradients travel with its W tile
+  // through LDS instead of being loaded inside the loop.
+  constexpr bool HOIST = MAXS <= 16;
+  __shared__ float dpt[2][HOIST ? 256 : 1];
+  const bool hoist = HOIST && nF <= 16;
+  const float* dPg = s.dP + fg.dP;
+  float bph[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int f = 4 * q + lk;
+    bph[q] = (hoist && active && f < nF) ? phi[(((s.f_lo + f) << fg.s_t) - (t0 + li)) & (L2 - 1)] : 0.f;
+  }
+  const bool dp_thread = hoist && static_cast<int>(threadIdx.x) < 16 * nF;
+  float dreg = 0.f;
 
   // stage the first live tile
   int rt = next_live_tile(s, rt_lo, rt_hi, Kal);
@@ -667,6 +682,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
       const int rr = e / WS, n = e - rr * WS;
       wt[0][e] = n < ncols ? s.W[static_cast<int64_t>(rt * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
     }
+    if (dp_thread) dpt[0][threadIdx.x] = dPg[static_cast<int64_t>(rt) * 16 * nF + threadIdx.x];
   }
   __syncthreads();
   int buf = 0;
@@ -679,6 +695,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
         const int rr = e / WS, n = e - rr * WS;
         wreg[i] = n < ncols ? s.W[static_cast<int64_t>(nxt * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
       }
+      if (dp_thread) dreg = dPg[static_cast<int64_t>(nxt) * 16 * nF + threadIdx.x];
     }
     const int nlo = s.rt_nrange[2 * rt];
     const int nhi = min(s.rt_nrange[2 * rt + 1], Kal);
@@ -709,15 +726,26 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
         vi[v] = G3 ? k1[v] + k2[v] : k2[v];
       }
       f4 du = {0.f, 0.f, 0.f, 0.f};
-      const float* dPr = s.dP + fg.dP + static_cast<int64_t>(r0 + li) * nF;
-      for (int q = 0; q < nFq; ++q) {
-        const int f = 4 * q + lk;
-        float a = 0.f, b = 0.f;
-        if (f < nF) {
-          a = dPr[f];
-          b = phi[(((s.f_lo + f) << fg.s_t) - (t0 + li)) & (L2 - 1)];
+      if (hoist) {
+        const float* dp = dpt[buf] + li * nF;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q < nFq) {
+            const int f = 4 * q + lk;
+            du = mfma(f < nF ? dp[f] : 0.f, bph[q], du);
+          }
         }
-        du = mfma(a, b, du);
+      } else {
+        const float* dPr = dPg + static_cast<int64_t>(r0 + li) * nF;
+        for (int q = 0; q < nFq; ++q) {
+          const int f = 4 * q + lk;
+          float a = 0.f, b = 0.f;
+          if (f < nF) {
+            a = dPr[f];
+            b = phi[(((s.f_lo + f) << fg.s_t) - (t0 + li)) & (L2 - 1)];
+          }
+          du = mfma(a, b, du);
+        }
       }
       float dvr[4], ddf[4], dsm[4];
 #pragma unroll
@@ -753,6 +781,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
     if (nxt < rt_hi) {
 #pragma unroll
       for (int i = 0; i < PER; ++i) wt[buf ^ 1][threadIdx.x + 256 * i] = wreg[i];
+      if (dp_thread) dpt[buf ^ 1][threadIdx.x] = dreg;
     }
     __syncthreads();
     buf ^= 1;
