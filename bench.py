@@ -28,12 +28,13 @@ PEAK_HBM_GBS = 8000.0
 def cpu_baseline() -> dict:
     """The FP64 oracle timed on this host on a bounded sample of the config-2 iteration.
 
-    An oracle forward + backward of config 2 takes minutes, so it is timed in parts:
+    An oracle forward + backward of config 2 takes about a minute, so it is timed in parts:
     the first layer and order-1 paths (forward and adjoint) exactly, and the second-order
-    groups through one sampled group (n2 with j2 = 3). Every second-order group does
-    the same work per time sample (a frequential DFT of N_fr points and the filters of
-    the frequential list per column), so a group's cost is taken as proportional to its
-    length L2 and the sampled group's cost per sample is applied to all groups.
+    groups through three sampled groups (one each with j2 = 2, 3, 4; about 15 s of CPU
+    work in all). Every second-order group does the same work per time sample (a
+    frequential DFT of N_fr points and the filters of the frequential list per column), so
+    a group's cost is taken as proportional to its length L2 and the sampled groups' cost
+    per sample is applied to all groups.
     """
     import numpy as np
 
@@ -45,36 +46,40 @@ def cpu_baseline() -> dict:
                    CFG2["F"])
     y = ji.white_noise_like(ji.config2_signal(2), 3)
     fc = fftroute.FilterCache(op)
-    sample = next(g for g in op.groups if g.j2 == 3)
-    blocks = [b for b in op.blocks if b.order == 2 and b.n2 == sample.n2]
+    samples = [next(g for g in op.groups if g.j2 == j) for j in (2, 3, 4)]
+    picked = {g.n2 for g in samples}
     dS_group = np.zeros(op.n_coeff)
-    for b in blocks:
-        dS_group[b.offset: b.offset + b.n_lambda * b.n_frames] = 1.0
+    for b in op.blocks:
+        if b.order == 2 and b.n2 in picked:
+            dS_group[b.offset: b.offset + b.n_lambda * b.n_frames] = 1.0
     dS_o1 = np.zeros(op.n_coeff)
     for b in op.blocks:
         if b.order == 1:
             dS_o1[b.offset: b.offset + b.n_lambda * b.n_frames] = 1.0
 
+    from threadpoolctl import threadpool_limits
+
     def timed(fn):
-        t0 = time.perf_counter()
-        fn()
-        return time.perf_counter() - t0
+        with threadpool_limits(limits=1):   # one host thread, as reported in "cores"
+            t0 = time.perf_counter()
+            fn()
+            return time.perf_counter() - t0
 
     fftroute.forward_partial(op, y, [], order1=False, fc=fc)          # fills the filter cache
     t_fl = timed(lambda: fftroute.forward_partial(op, y, [], order1=False, fc=fc))
     t_fl_o1 = timed(lambda: fftroute.forward_partial(op, y, [], order1=True, fc=fc))
-    t_fl_g = timed(lambda: fftroute.forward_partial(op, y, [sample.n2], order1=False, fc=fc))
+    t_fl_g = timed(lambda: fftroute.forward_partial(op, y, sorted(picked), order1=False, fc=fc))
     t_b_o1 = timed(lambda: fftroute.backward(op, y, dS_o1, fc=fc))
     t_b_g = timed(lambda: fftroute.backward(op, y, dS_group + dS_o1, fc=fc))
     t_g = max(t_fl_g - t_fl, 0.0) + max(t_b_g - t_b_o1, 0.0)
-    per_sample = t_g / (op.N_pad >> sample.j2)
+    per_sample = t_g / sum(op.N_pad >> g.j2 for g in samples)
     groups_total = sum(per_sample * (op.N_pad >> g.j2) for g in op.groups)
     total = t_fl_o1 + t_b_o1 + groups_total
     spent = t_fl + t_fl_o1 + t_fl_g + t_b_o1 + t_b_g
     return {"value": 1.0 / total, "unit": "iters/s", "cores": 1, "kind": "oracle",
             "sample": (f"config 2, FP64 NumPy oracle on one thread: first layer + order-1 paths timed in full "
-                       f"(fwd {t_fl_o1:.2f} s, bwd {t_b_o1:.2f} s), second-order group n2={sample.n2} "
-                       f"(j2=3, {sample.K} rows) timed fwd+bwd ({t_g:.2f} s) and extrapolated to all "
+                       f"(fwd {t_fl_o1:.2f} s, bwd {t_b_o1:.2f} s), second-order groups n2={sorted(picked)} "
+                       f"(j2=2,3,4) timed fwd+bwd ({t_g:.2f} s) and extrapolated to all "
                        f"{len(op.groups)} groups in proportion to their length: {total:.1f} s per iteration; "
                        f"{spent:.1f} s of CPU work measured")}
 

@@ -463,7 +463,9 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
       // a workgroup's four waves cover 64 MT consecutive times (the last chunk may be short)
       fg.TC = 64 * fwd_mt(S);
       fg.n_tc = static_cast<int32_t>(std::max<int64_t>(1, grp.L2 / fg.TC));
-      const int32_t want = (512 + fg.n_tc - 1) / fg.n_tc;
+      // about 256 workgroups per group: more row splits re-load the same Y2 operands
+      // (measured on MI355X, config 2: targets 16..4096 swept, 256 fastest)
+      const int32_t want = (256 + fg.n_tc - 1) / fg.n_tc;
       const int32_t rs = std::max(1, std::min(want, n_rt / 4));
       fg.rt_fwd = (n_rt + rs - 1) / rs;
     } else {
