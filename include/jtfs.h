@@ -219,6 +219,33 @@ jtfs_status jtfs_timing_read(jtfs_plan_t plan, double* ms, int64_t* counts, int3
 /* Release a plan and its device tables. NULL is ignored. */
 void jtfs_plan_destroy(jtfs_plan_t plan);
 
+/*
+ * Tile schedules (performance only: every choice computes the same transform, up to the
+ * order of floating-point sums). Zero in a field selects the default.
+ *   fwd_rows   workgroups per second-order group targeted by the forward contraction's row
+ *              splits (default 256; 16 .. 8192)
+ *   fwd_mt     forward time tiles per wave times the group's k-steps: 16 or 32 (default 32)
+ *   bwd_rows   workgroups per group targeted by the backward's row splits (default 256)
+ *   split_bias shift of the split point of transforms longer than 4096 points, n = A B with
+ *              log2 A = floor(log2 n / 2) + split_bias, clamped so that A, B <= 4096 (-2 .. 2)
+ */
+typedef struct {
+  int32_t fwd_rows, fwd_mt, bwd_rows, split_bias;
+} jtfs_tuning;
+
+/* jtfs_plan with explicit tile schedules (NULL = defaults). JTFS_ERR_ARG on a field out of range. */
+jtfs_status jtfs_plan_tuned(const jtfs_params* signals, int32_t batch, const jtfs_tuning* tuning, jtfs_plan_t* out);
+
+/*
+ * jtfs_autotune - pick tile schedules for these signals by measurement on the current
+ * device: starting from the defaults, each field in turn takes the candidate value that
+ * makes one forward + backward fastest (median of 3 timed runs on a seeded synthetic
+ * signal, HIP events on `stream`). Allocates and frees its own device buffers; blocks until
+ * done. On success *out holds the choice and, if ms is not NULL, *ms its time.
+ */
+jtfs_status jtfs_autotune(const jtfs_params* signals, int32_t batch, jtfs_stream_t stream, jtfs_tuning* out,
+                          double* ms);
+
 /* ------------------------------------------------------------------------------------
  * Learned warm start (an addition to the method; the paper starts descent from noise,
  * Sec. 2.3). A 1-D convolutional decoder maps the coefficients of one signal, read as

@@ -50,6 +50,10 @@ class jtfs_opt(ctypes.Structure):
                 ("bold_down", ctypes.c_float), ("state", c_void_p)]
 
 
+class jtfs_tuning(ctypes.Structure):
+    _fields_ = [("fwd_rows", c_int32), ("fwd_mt", c_int32), ("bwd_rows", c_int32), ("split_bias", c_int32)]
+
+
 JTFS_DEC_MAX_LAYERS = 8
 
 
@@ -62,6 +66,8 @@ class jtfs_dec_config(ctypes.Structure):
 # (name, restype, argtypes) for every exported function of include/jtfs.h
 SIGNATURES = [
     ("jtfs_plan", c_int32, [POINTER(jtfs_params), c_int32, POINTER(c_void_p)]),
+    ("jtfs_plan_tuned", c_int32, [POINTER(jtfs_params), c_int32, POINTER(jtfs_tuning), POINTER(c_void_p)]),
+    ("jtfs_autotune", c_int32, [POINTER(jtfs_params), c_int32, c_void_p, POINTER(jtfs_tuning), POINTER(c_double)]),
     ("jtfs_plan_query", c_int32, [c_void_p, POINTER(jtfs_plan_info)]),
     ("jtfs_plan_offsets", c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64)]),
     ("jtfs_plan_meta", c_int32, [c_void_p, c_int32, POINTER(jtfs_path), c_int64, POINTER(c_int64)]),

@@ -351,9 +351,15 @@ int64_t state_vectors(int32_t kind) {
 extern "C" {
 
 jtfs_status jtfs_plan(const jtfs_params* sig, int32_t batch, jtfs_plan_t* out) {
+  return jtfs_plan_tuned(sig, batch, nullptr, out);
+}
+
+jtfs_status jtfs_plan_tuned(const jtfs_params* sig, int32_t batch, const jtfs_tuning* tuning, jtfs_plan_t* out) {
   if (!out) return fail(JTFS_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!sig || batch < 1) return fail(JTFS_ERR_ARG, "need at least one signal");
+  jtfs_tuning tu;
+  if (!jtfs::resolve_tuning(tuning, tu)) return fail(JTFS_ERR_ARG, "tuning field out of range");
   std::unique_ptr<jtfs_plan_s> p(new (std::nothrow) jtfs_plan_s());
   if (!p) return fail(JTFS_ERR_NOMEM, "host allocation failed");
   try {
@@ -363,7 +369,7 @@ jtfs_status jtfs_plan(const jtfs_params* sig, int32_t batch, jtfs_plan_t* out) {
     size_t ws = 0;
     for (int32_t s = 0; s < batch; ++s) {
       std::string err;
-      jtfs_status st = jtfs::build_signal_plan(sig[s], p->sig[s], err);
+      jtfs_status st = jtfs::build_signal_plan(sig[s], p->sig[s], err, &tu);
       if (st != JTFS_OK) return fail(st, "signal " + std::to_string(s) + ": " + err);
       const jtfs::SigPlan& sp = p->sig[s];
       p->x_off.push_back(p->x_off.back() + sp.N);

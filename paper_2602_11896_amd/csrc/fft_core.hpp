@@ -146,15 +146,17 @@ struct SplitGeom {
   int log2n, log2A, log2B, log2C1, log2C2;
 };
 
-JTFS_HD inline SplitGeom split_geom(int log2n) {
+// log2A: the split point (A, B <= 4096 is required; default floor(log2n / 2)).
+JTFS_HD inline SplitGeom split_geom(int log2n, int log2A) {
   SplitGeom g;
   g.log2n = log2n;
-  g.log2A = log2n / 2;
+  g.log2A = log2A;
   g.log2B = log2n - g.log2A;
   g.log2C1 = 12 - g.log2B;
   g.log2C2 = 12 - g.log2A;
   return g;
 }
+JTFS_HD inline SplitGeom split_geom(int log2n) { return split_geom(log2n, log2n / 2); }
 
 // pass 1 load: input index and tile slot of element e (column base n1_0)
 JTFS_HD inline void split_p1_load(const SplitGeom& g, int n1_0, int e, int& idx, int& slot) {

@@ -221,9 +221,8 @@ __global__ __launch_bounds__(256, (S >= 32 ? 1 : 2)) void k_freq_fwd(DevSig s, i
 //   Re V = k1 - k3,  Im V = k1 + k2,
 // then |V| in the accumulator layout and P^T += Phi_T^T |V^T|. The four waves' partial sums
 // of a row tile are added in a fixed order through LDS and written as the chunk's partial.
-template <int MAXS, int FT>
+template <int MAXS, int FT, int MT>
 __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
-  constexpr int MT = (FT == 1 ? 32 : 16) / MAXS > 1 ? (FT == 1 ? 32 : 16) / MAXS : 1;
   constexpr int WS = 4 * MAXS;                // LDS row stride (columns)
   constexpr int PER = (16 * WS + 255) / 256;  // W elements staged per thread
   __shared__ c32 wt[2][16 * WS];
@@ -845,12 +844,19 @@ hipError_t launch_fwd_s(const DevSig& s, const SigPlan::FwdLaunch& l, hipStream_
   return hipGetLastError();
 }
 
+// Time tiles per wave: 16 / S or 32 / S (at least 1); with two frame tiles 16 / S only.
 template <int S>
 hipError_t launch_fwd2_s(const DevSig& s, const SigPlan::FwdLaunch& l, hipStream_t st) {
-  switch (l.FT) {
-    case 1: hipLaunchKernelGGL((k_freq_fwd2<S, 1>), dim3(l.nitems), dim3(256), 0, st, s, l.item0); break;
-    case 2: hipLaunchKernelGGL((k_freq_fwd2<S, 2>), dim3(l.nitems), dim3(256), 0, st, s, l.item0); break;
-    default: return hipErrorInvalidValue;
+  constexpr int LO = 16 / S > 1 ? 16 / S : 1, HI = 32 / S > 1 ? 32 / S : 1;
+  const dim3 g(l.nitems), b(256);
+  if (l.FT == 1 && l.MT == HI) {
+    hipLaunchKernelGGL((k_freq_fwd2<S, 1, HI>), g, b, 0, st, s, l.item0);
+  } else if (l.FT == 1 && l.MT == LO) {
+    hipLaunchKernelGGL((k_freq_fwd2<S, 1, LO>), g, b, 0, st, s, l.item0);
+  } else if (l.FT == 2 && l.MT == LO) {
+    hipLaunchKernelGGL((k_freq_fwd2<S, 2, LO>), g, b, 0, st, s, l.item0);
+  } else {
+    return hipErrorInvalidValue;   // plan and kernel disagree
   }
   return hipGetLastError();
 }

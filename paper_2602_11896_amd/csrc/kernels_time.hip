@@ -216,7 +216,7 @@ __device__ void split1_body(const DevSig& s, c32* lds, int task) {
   using O = Ops<ST>;
   const SplitTask tk = s.stasks[task];
   const int log2n = tk.log2n;
-  const SplitGeom g = split_geom(log2n);
+  const SplitGeom g = split_geom(log2n, tk.log2A);
   const RowJob job = s.jobs[tk.job];
   const int n1_0 = tk.blk << g.log2C1;
   for (int i = 0; i < 16; ++i) {
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_fft_split2(DevSig s, int task0) {
   using O = Ops<ST>;
   const SplitTask tk = s.stasks[task0 + blockIdx.x];
   const int log2n = tk.log2n;
-  const SplitGeom g = split_geom(log2n);
+  const SplitGeom g = split_geom(log2n, tk.log2A);
   const RowJob job = s.jobs[tk.job];
   const int k2_0 = tk.blk << g.log2C2;
   const c32* scr = s.scr + tk.scr;

@@ -168,7 +168,23 @@ int32_t subsampling_scale(double xi, double sigma) {
   return j;
 }
 
-jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& err) {
+bool resolve_tuning(const jtfs_tuning* in, jtfs_tuning& t) {
+  t = jtfs_tuning{256, 32, 256, 0};
+  if (!in) return true;
+  if (in->fwd_rows) t.fwd_rows = in->fwd_rows;
+  if (in->fwd_mt) t.fwd_mt = in->fwd_mt;
+  if (in->bwd_rows) t.bwd_rows = in->bwd_rows;
+  t.split_bias = in->split_bias;
+  return t.fwd_rows >= 16 && t.fwd_rows <= 8192 && (t.fwd_mt == 16 || t.fwd_mt == 32) && t.bwd_rows >= 16 &&
+         t.bwd_rows <= 8192 && t.split_bias >= -2 && t.split_bias <= 2;
+}
+
+jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& err, const jtfs_tuning* tune) {
+  jtfs_tuning tu;
+  if (!resolve_tuning(tune, tu)) {
+    err = "tuning field out of range";
+    return JTFS_ERR_ARG;
+  }
   p = SigPlan{};
   p.prm = prm;
   if (prm.n < 2 || prm.J < 0 || prm.Q1 < 1 || prm.Q2 < 1 || prm.J_fr < 0 || prm.Q_fr < 1 || prm.log2_T < 0 ||
@@ -444,7 +460,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   // MT 16-time tiles of Y2 in registers) where its registers allow (S <= 32, FT <= 2),
   // otherwise the register-W kernel.
   auto fwd_loop = [&](int32_t S) { return S <= 32 && FT <= 2; };
-  auto fwd_mt = [&](int32_t S) { return std::max(1, (FT == 1 ? 32 : 16) / S); };
+  auto fwd_mt = [&](int32_t S) { return std::max(1, (FT == 1 ? tu.fwd_mt : 16) / S); };
   for (const Grp& grp : p.groups) {
     FreqGroup fg{};
     fg.y2 = p.y2_total;
@@ -465,7 +481,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
       fg.n_tc = static_cast<int32_t>(std::max<int64_t>(1, grp.L2 / fg.TC));
       // about 256 workgroups per group: more row splits re-load the same Y2 operands
       // (measured on MI355X, config 2: targets 16..4096 swept, 256 fastest)
-      const int32_t want = (256 + fg.n_tc - 1) / fg.n_tc;
+      const int32_t want = (tu.fwd_rows + fg.n_tc - 1) / fg.n_tc;
       const int32_t rs = std::max(1, std::min(want, n_rt / 4));
       fg.rt_fwd = (n_rt + rs - 1) / rs;
     } else {
@@ -478,7 +494,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     fg.dP = p.dP_total;
     p.dP_total += static_cast<int64_t>(p.R_pad) * nF;
     fg.n_tb = static_cast<int32_t>((grp.L2 + 63) / 64);
-    int32_t want = (256 + fg.n_tb - 1) / fg.n_tb;
+    int32_t want = (tu.bwd_rows + fg.n_tb - 1) / fg.n_tb;
     fg.RS = std::max(1, std::min(want, n_rt / 4));
     fg.rt_per_split = (n_rt + fg.RS - 1) / fg.RS;
     fg.RS = (n_rt + fg.rt_per_split - 1) / fg.rt_per_split;
@@ -508,7 +524,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     for (int32_t S = 4; S <= 64; S *= 2) {
       if (fwd_loop(S)) {
         // items (group, row split, time chunk)
-        SigPlan::FwdLaunch fl{S, 0, FT, static_cast<int32_t>(p.fwd_items.size()), 0, 0};
+        SigPlan::FwdLaunch fl{S, 0, FT, static_cast<int32_t>(p.fwd_items.size()), 0, 0, fwd_mt(S)};
         for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
           const FreqGroup& fg = p.fgroups[gi];
           if (bucket_of(fg.K) != S) continue;
@@ -522,7 +538,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
       }
       int32_t RW = 2;   // at most two row tiles per wave (measured: four cost occupancy)
       while (RW > 1 && RW * (2 * S + 4 * FT) > 100) RW /= 2;
-      SigPlan::FwdLaunch fl{S, RW, FT, static_cast<int32_t>(p.fwd_items.size()), 0, 0};
+      SigPlan::FwdLaunch fl{S, RW, FT, static_cast<int32_t>(p.fwd_items.size()), 0, 0, 0};
       for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
         const FreqGroup& fg = p.fgroups[gi];
         if (bucket_of(fg.K) != S) continue;
@@ -593,10 +609,12 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
       for (const Launch& l : p.launches[stage]) {
         int32_t log2n = 0;
         while ((1 << log2n) < l.n) ++log2n;
-        const SplitGeom g = split_geom(log2n);
+        // both factors between 16 (one radix-16 pass per thread) and 4096 (one LDS tile)
+        const int32_t log2A = std::min(std::min(12, log2n - 4), std::max(std::max(4, log2n - 12), log2n / 2 + tu.split_bias));
+        const SplitGeom g = split_geom(log2n, log2A);
         const int32_t nblk = pass == 1 ? (1 << g.log2A) >> g.log2C1 : (1 << g.log2B) >> g.log2C2;
         for (int32_t r = 0; r < l.njobs; ++r, scr += l.n)
-          for (int32_t b = 0; b < nblk; ++b) p.stasks.push_back(SplitTask{l.job0 + r, log2n, b, 0, scr});
+          for (int32_t b = 0; b < nblk; ++b) p.stasks.push_back(SplitTask{l.job0 + r, log2n, b, log2A, scr});
       }
       (pass == 1 ? p.split1_n : p.split2_n)[stage] =
           static_cast<int32_t>(p.stasks.size()) - (pass == 1 ? p.split1_0 : p.split2_0)[stage];

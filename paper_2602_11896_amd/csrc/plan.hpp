@@ -83,6 +83,7 @@ struct SigPlan {
     int32_t S, RW, FT, item0, nitems;     // k-steps, row tiles per wave (0: row-tile-loop
                                           // kernel, items = (group, row split, chunk)), frame tiles
     int32_t run;                          // consecutive items sharing a time chunk
+    int32_t MT;                           // row-tile-loop kernel: 16-time tiles per wave
   };
   std::vector<FwdLaunch> fwd_launches;
   std::vector<BwdItem> bwd_items;
@@ -120,7 +121,11 @@ struct SigPlan {
 };
 
 // Builds the plan of one signal; on failure returns a status and sets `err`.
-jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& out, std::string& err);
+// Fills `out` for one signal; `tune` (may be NULL) selects tile schedules (jtfs_tuning).
+jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& out, std::string& err,
+                              const jtfs_tuning* tune = nullptr);
+// Resolves the zero fields of a tuning to their defaults; false if a field is out of range.
+bool resolve_tuning(const jtfs_tuning* in, jtfs_tuning& out);
 
 // Filterbank generator of Sec. 3.1 and the subsampling-scale rule, exposed for tests.
 std::vector<std::pair<double, double>> wavelet_bank(int J, int Q);

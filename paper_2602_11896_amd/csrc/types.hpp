@@ -40,7 +40,7 @@ struct RowTask {
 // One workgroup of a two-pass (four-step) transform: its row job, log2 of the row length,
 // its column block (pass 1) or row block (pass 2), and the row's scratch offset.
 struct SplitTask {
-  int32_t job, log2n, blk, pad_;
+  int32_t job, log2n, blk, log2A;   // log2A: the split point n = A B of this row
   int64_t scr;
 };
 

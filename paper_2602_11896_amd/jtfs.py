@@ -47,14 +47,43 @@ def _require(t: torch.Tensor, numel: int, name: str, dtype=torch.float32) -> Non
         raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
 
 
-class Plan:
-    """A JTFS plan for one or more signals (jtfs_plan)."""
+@dataclass
+class Tuning:
+    """Tile schedules of a plan (jtfs_tuning); 0 selects a field's default."""
+    fwd_rows: int = 0
+    fwd_mt: int = 0
+    bwd_rows: int = 0
+    split_bias: int = 0
 
-    def __init__(self, params: Union[Params, Sequence[Params]]):
+    def c(self) -> L.jtfs_tuning:
+        return L.jtfs_tuning(self.fwd_rows, self.fwd_mt, self.bwd_rows, self.split_bias)
+
+
+def autotune(params: Union[Params, Sequence[Params]], device="cuda"):
+    """Tile schedules measured fastest on this device (jtfs_autotune); returns (Tuning, ms)."""
+    plist = [params] if isinstance(params, Params) else list(params)
+    arr = (L.jtfs_params * len(plist))(*[p.c() for p in plist])
+    t = L.jtfs_tuning()
+    ms = ctypes.c_double()
+    L.check(L.lib().jtfs_autotune(arr, len(plist), _stream(torch.device(device)), ctypes.byref(t), ctypes.byref(ms)),
+            "jtfs_autotune")
+    return Tuning(t.fwd_rows, t.fwd_mt, t.bwd_rows, t.split_bias), ms.value
+
+
+class Plan:
+    """A JTFS plan for one or more signals (jtfs_plan / jtfs_plan_tuned)."""
+
+    def __init__(self, params: Union[Params, Sequence[Params]], tuning: "Tuning" = None):
         plist = [params] if isinstance(params, Params) else list(params)
         arr = (L.jtfs_params * len(plist))(*[p.c() for p in plist])
         handle = ctypes.c_void_p()
-        L.check(L.lib().jtfs_plan(arr, len(plist), ctypes.byref(handle)), "jtfs_plan")
+        if tuning is None:
+            L.check(L.lib().jtfs_plan(arr, len(plist), ctypes.byref(handle)), "jtfs_plan")
+        else:
+            tc = tuning.c()
+            L.check(L.lib().jtfs_plan_tuned(arr, len(plist), ctypes.byref(tc), ctypes.byref(handle)),
+                    "jtfs_plan_tuned")
+        self.tuning = tuning
         self._h = handle
         self._destroy = L.lib().jtfs_plan_destroy
         self.params = plist

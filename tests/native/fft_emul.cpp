@@ -96,9 +96,9 @@ static void ref_fft(std::vector<double>& re, std::vector<double>& im, int dir) {
 }
 
 // Emulates pass 1 and pass 2 workgroups of the two-pass split for one n-point row.
-static double check_split(int log2n, int dir, const std::vector<c32>& tw, int log2tw) {
+static double check_split(int log2n, int log2A, int dir, const std::vector<c32>& tw, int log2tw) {
   const int n = 1 << log2n;
-  SplitGeom g = split_geom(log2n);
+  SplitGeom g = split_geom(log2n, log2A);
   std::vector<double> xr(n), xi(n);
   std::vector<c32> x(n), scr(n), out(n);
   unsigned s = 777u + log2n;
@@ -143,12 +143,14 @@ int main() {
       std::printf("n=%6d dir=%+d rel_l2=%.3e\n", 1 << log2n, dir, e);
       if (!(e < 2e-6)) bad = 1;
     }
+  // every split point a plan may choose: both factors between 16 and 4096
   for (int log2n = 13; log2n <= 17; ++log2n)
-    for (int dir : {-1, 1}) {
-      double e = check_split(log2n, dir, tw, log2tw);
-      std::printf("split n=%6d dir=%+d rel_l2=%.3e\n", 1 << log2n, dir, e);
-      if (!(e < 3e-6)) bad = 1;
-    }
+    for (int log2A = (log2n - 12 > 4 ? log2n - 12 : 4); log2A <= (log2n - 4 < 12 ? log2n - 4 : 12); ++log2A)
+      for (int dir : {-1, 1}) {
+        double e = check_split(log2n, log2A, dir, tw, log2tw);
+        std::printf("split n=%6d A=%5d dir=%+d rel_l2=%.3e\n", 1 << log2n, 1 << log2A, dir, e);
+        if (!(e < 3e-6)) bad = 1;
+      }
   std::printf(bad ? "FAIL\n" : "OK\n");
   return bad;
 }

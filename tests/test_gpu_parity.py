@@ -263,3 +263,52 @@ def test_batched_plan_matches_single():
     Sb = fftroute.forward(make_plan(*b), xb)
     assert rel(S[: Sa.size], Sa) <= TOL_S
     assert rel(S[Sa.size:], Sb) <= TOL_S
+
+
+@pytest.mark.parametrize("tuning", [(128, 16, 512, 1), (1024, 32, 128, -1)])
+def test_tuned_plan_parity_cfg1(tuning):
+    """Other tile schedules (row splits, time tiles, split points) compute the same transform."""
+    say(f"[parity] tuned plan cfg1 {tuning}")
+    op = make_plan(*CFG1)
+    x = ji.config1_signal(0, n=op.N)
+    y = ji.white_noise_like(x, 1)
+    S_x = fftroute.forward(op, x)
+    S_y, cache = fftroute.forward(op, y, return_cache=True)
+    dS = 2.0 * (S_y - S_x)
+    g_ref = fftroute.backward(op, y, dS, cache=cache)
+    plan = J.Plan(J.Params(*CFG1), tuning=J.Tuning(*tuning))
+    ws = plan.workspace()
+    yd = dev(y)
+    S = plan.forward(yd, ws=ws)
+    err_s = rel(host(S), S_y)
+    dx = plan.backward(yd, dev(dS), ws=ws, reuse_forward=True)
+    err_g = rel(host(dx), g_ref)
+    say(f"[parity] tuned {tuning}: S rel {err_s:.3e}, dx rel {err_g:.3e}")
+    assert err_s <= TOL_S and err_g <= TOL_GRAD
+
+
+def test_tuned_plan_config2_sampled():
+    """A non-default tiling at full config-2 size against the oracle on sampled groups."""
+    say("[parity] tuned plan config 2 sampled")
+    op = make_plan(*CFG2)
+    x = ji.config2_signal(2)
+    n2s = [op.groups[0].n2, op.groups[-1].n2]
+    S_ref = fftroute.forward_partial(op, x, n2s)
+    plan = J.Plan(J.Params(*CFG2), tuning=J.Tuning(512, 16, 1024, -1))
+    S = host(plan.forward(dev(x)))
+    mask = ~np.isnan(S_ref)
+    err = rel(S[mask], S_ref[mask])
+    say(f"[parity] tuned config 2 sampled: rel L2 {err:.3e}")
+    assert err <= TOL_S
+
+
+def test_autotune_returns_a_working_schedule():
+    say("[autotune] cfg1")
+    tuning, ms = J.autotune(J.Params(*CFG1))
+    say(f"[autotune] {tuning} {ms:.3f} ms")
+    assert ms > 0.0
+    assert tuning.fwd_mt in (16, 32) and -2 <= tuning.split_bias <= 2
+    op = make_plan(*CFG1)
+    x = ji.config1_signal(0, n=op.N)
+    S = host(J.Plan(J.Params(*CFG1), tuning=tuning).forward(dev(x)))
+    assert rel(S, fftroute.forward(op, x)) <= TOL_S

@@ -154,3 +154,22 @@ def test_decoder_host_argument_errors():
     plan = J.Plan(J.Params(*CONFIGS["tiny"][:8], periodic=CONFIGS["tiny"][8]))
     assert lib.jtfs_loss(plan._h, p, p, p, p, 1, 1.0, None) == L.JTFS_ERR_ARG               # dS aliases S
     assert lib.jtfs_loss(plan._h, None, p, p, p, 1, 1.0, None) == L.JTFS_ERR_ARG
+
+
+@pytest.mark.parametrize("tuning", [(128, 16, 512, 1), (1024, 32, 128, -1), (0, 0, 0, 2), (16, 16, 8192, -2)])
+def test_tuned_plans_keep_the_layout(tuning):
+    """Tile schedules change neither the output layout nor the offsets of a plan."""
+    args = CONFIGS["cfg2"]
+    p0 = J.Plan(J.Params(*args[:8], periodic=args[8]))
+    p1 = J.Plan(J.Params(*args[:8], periodic=args[8]), tuning=J.Tuning(*tuning))
+    assert p1.n_coeff == p0.n_coeff and p1.n_samples == p0.n_samples
+    assert p1.s_offsets == p0.s_offsets and p1.x_offsets == p0.x_offsets
+    assert p1.meta() == p0.meta()
+
+
+@pytest.mark.parametrize("tuning", [(8, 0, 0, 0), (0, 24, 0, 0), (0, 0, 20000, 0), (0, 0, 0, 3), (0, 0, 0, -3)])
+def test_tuning_out_of_range_is_rejected(tuning):
+    args = CONFIGS["tiny"]
+    with pytest.raises(L.JTFSError) as e:
+        J.Plan(J.Params(*args[:8], periodic=args[8]), tuning=J.Tuning(*tuning))
+    assert e.value.status == L.JTFS_ERR_ARG
