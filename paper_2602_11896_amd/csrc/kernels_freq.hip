@@ -212,6 +212,15 @@ __global__ __launch_bounds__(256, (S >= 32 ? 1 : 2)) void k_freq_fwd(DevSig s, i
   }
 }
 
+// Integer division rounding towards minus infinity (b > 0).
+__device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// Start slot (frame index on the padded time axis) of the pooling window of forward chunk
+// tc of a windowed group: the first frame whose centre lies within the phi_T support.
+__device__ inline int window_start(const FreqGroup& fg, int tc) {
+  return -floor_div(fg.halo - tc * fg.TC, 1 << fg.s_t);   // ceil((tc TC - halo) / 2^s_t)
+}
+
 // Row-tile-loop forward (groups of at most 128 rows, at most 32 frames). Item: group, row
 // split, chunk of 64 MT times. Each wave keeps the Y2 operands (as y_r, y_i - y_r,
 // y_r + y_i) and the Phi_T^T fragments of its MT 16-time tiles in registers and loops over
@@ -221,6 +230,9 @@ __global__ __launch_bounds__(256, (S >= 32 ? 1 : 2)) void k_freq_fwd(DevSig s, i
 //   Re V = k1 - k3,  Im V = k1 + k2,
 // then |V| in the accumulator layout and P^T += Phi_T^T |V^T|. The four waves' partial sums
 // of a row tile are added in a fixed order through LDS and written as the chunk's partial.
+// Windowed groups (fg.fw > 0, plans with more than 32 frames) pool each chunk into the fw
+// frames starting at window_start(tc) (slots wrap around the padded time axis; frames
+// outside the kept ones get zero weight); the partial rows then hold fw window frames.
 template <int MAXS, int FT, int MT>
 __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
   constexpr int WS = 4 * MAXS;                // LDS row stride (columns)
@@ -239,6 +251,9 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
   const c32* Y = s.Y2 + fg.y2;
   const float* phi = s.tables + fg.phiT;
   const int tbase = it.tc * fg.TC;
+  const int nslot = L2 >> fg.s_t;   // frame slots on the padded time axis
+  const int slot0 = fg.fw > 0 ? window_start(fg, it.tc) : s.f_lo;
+  const int pst = fg.fw > 0 ? fg.fw : nF;   // partial row stride
 
   float yre[MT][MAXS], ydf[MT][MAXS], ysm[MT][MAXS], ph[MT][FT][4];
   bool act[MT];
@@ -257,11 +272,12 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
     }
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft) {
-      const int f = ft * 16 + li;
-      const int fc = (s.f_lo + f) << fg.s_t;
+      const int sl = ((slot0 + ft * 16 + li) % nslot + nslot) % nslot;
+      const int f = sl - s.f_lo;   // kept frame index
+      const int fc = sl << fg.s_t;
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        ph[j][ft][v] = (act[j] && f < nF) ? phi[(fc - (t0 + 4 * lk + v)) & (L2 - 1)] : 0.f;
+        ph[j][ft][v] = (act[j] && f >= 0 && f < nF) ? phi[(fc - (t0 + 4 * lk + v)) & (L2 - 1)] : 0.f;
     }
   }
 
@@ -279,7 +295,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
     }
   }
   __syncthreads();
-  float* part = s.part + fg.part + static_cast<int64_t>(it.tc) * s.R_pad * nF;
+  float* part = s.part + fg.part + static_cast<int64_t>(it.tc) * s.R_pad * pst;
   int buf = 0;
   for (int rt = rt_lo; rt < rt_hi; ++rt) {
     const bool next = rt + 1 < rt_hi;
@@ -344,10 +360,10 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
     for (int i = 0; i < FT; ++i) {
       const int e = threadIdx.x + 256 * i;
       const int ln = (e & 255) >> 2, v = e & 3;
-      const int f = (e >> 8) * 16 + 4 * (ln >> 4) + v;
-      if (f < nF) {
+      const int f = (e >> 8) * 16 + 4 * (ln >> 4) + v;   // kept frame, or window frame
+      if (f < pst) {
         const float sum = (red[buf][0][e] + red[buf][1][e]) + (red[buf][2][e] + red[buf][3][e]);
-        part[static_cast<int64_t>(rt * 16 + (ln & 15)) * nF + f] = sum;
+        part[static_cast<int64_t>(rt * 16 + (ln & 15)) * pst + f] = sum;
       }
     }
     buf ^= 1;
@@ -356,6 +372,8 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
 
 // Sum of the time-chunk partials, phi_F averaging along log-frequency (band-pass g) or
 // nothing more (g = phi_F), log-frequency unpadding, store into S.
+constexpr int kPoolFrames = 8;   // frames per pooling workgroup
+
 __global__ __launch_bounds__(256) void k_freq_pool(DevSig s) {
   __shared__ float P[8192];
   const int gi = blockIdx.x / s.n_g, g = blockIdx.x % s.n_g;
@@ -365,24 +383,46 @@ __global__ __launch_bounds__(256) void k_freq_pool(DevSig s) {
   const int nb = (fg.K + (1 << s.sF) - 1) >> s.sF;
   float* out = s.S + s.s_off[gi * s.n_g + g];
   const int Mrows = ff.lowpass ? nb : ff.M;
+  // blockIdx.y takes frames [8 y, 8 y + 8) (Mrows <= 1024, so the tile fits P)
   const int fw = max(1, min(nF, 8192 / Mrows));
+  const int fb = min(fw, kPoolFrames);
   const int sh = s.sF - ff.k;
   const float* ph = s.tables + ff.phiF;
-  for (int f0 = 0; f0 < nF; f0 += fw) {
-    const int fc = min(fw, nF - f0);
+  for (int f0 = blockIdx.y * fb; f0 < min(nF, (blockIdx.y + 1) * fb); f0 += fb) {
+    const int fc = min(fb, nF - f0);
     __syncthreads();
     for (int e = threadIdx.x; e < Mrows * fc; e += 256) {
       const int r = e / fc, fl = e - r * fc;
-      // eight independent partial sums (eight loads in flight), combined in a fixed order
-      const float* src = s.part + fg.part + static_cast<int64_t>(ff.row0 + r) * nF + f0 + fl;
-      const int64_t stride = static_cast<int64_t>(s.R_pad) * nF;
       float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      int tc = 0;
-      for (; tc + 8 <= fg.n_tc; tc += 8) {
+      if (fg.fw > 0) {
+        // windowed partials: chunk tc holds frame slot f_lo + f at window offset o < fw. The
+        // window of chunk t starts at ceil((t TC - halo) / 2^s_t), so only the chunks t with
+        // (slot - fw) 2^s_t + halo < t TC <= slot 2^s_t + halo hold the slot (t taken
+        // modulo the chunk count: the windows of t and t + n_tc differ by one turn).
+        const int nslot = fg.L2 >> fg.s_t;
+        const int w = 1 << fg.s_t;
+        const int slot = s.f_lo + f0 + fl;
+        const float* src = s.part + fg.part + static_cast<int64_t>(ff.row0 + r) * fg.fw;
+        const int64_t stride = static_cast<int64_t>(s.R_pad) * fg.fw;
+        int t_lo = floor_div((slot - fg.fw) * w + fg.halo, fg.TC);
+        const int t_hi = floor_div(slot * w + fg.halo, fg.TC);
+        if (t_hi - t_lo + 1 > fg.n_tc) t_lo = t_hi - fg.n_tc + 1;
+        for (int t = t_lo; t <= t_hi; ++t) {
+          const int tc = ((t % fg.n_tc) + fg.n_tc) % fg.n_tc;
+          const int o = ((slot - window_start(fg, tc)) % nslot + nslot) % nslot;
+          if (o < fg.fw) a[(t - t_lo) & 7] += src[tc * stride + o];
+        }
+      } else {
+        // eight independent partial sums (eight loads in flight), combined in a fixed order
+        const float* src = s.part + fg.part + static_cast<int64_t>(ff.row0 + r) * nF + f0 + fl;
+        const int64_t stride = static_cast<int64_t>(s.R_pad) * nF;
+        int tc = 0;
+        for (; tc + 8 <= fg.n_tc; tc += 8) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) a[j] += src[(tc + j) * stride];
+          for (int j = 0; j < 8; ++j) a[j] += src[(tc + j) * stride];
+        }
+        for (int j = 0; tc < fg.n_tc; ++tc, ++j) a[j] += src[tc * stride];
       }
-      for (int j = 0; tc < fg.n_tc; ++tc, ++j) a[j] += src[tc * stride];
       P[r * fc + fl] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
     __syncthreads();
@@ -669,6 +709,9 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
     bph[q] = (hoist && active && f < nF) ? phi[(((s.f_lo + f) << fg.s_t) - (t0 + li)) & (L2 - 1)] : 0.f;
   }
   const bool dp_thread = hoist && static_cast<int>(threadIdx.x) < 16 * nF;
+  // frame slots within the phi_T support of this wave's 16 times
+  const int sl0 = -floor_div(fg.halo - t0, 1 << fg.s_t);
+  const int nsl = floor_div(t0 + 15 + fg.halo, 1 << fg.s_t) - sl0 + 1;
   float dreg = 0.f;
 
   // stage the first live tile
@@ -733,6 +776,21 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
             const int f = 4 * q + lk;
             du = mfma(f < nF ? dp[f] : 0.f, bph[q], du);
           }
+        }
+      } else if (nsl < nF) {
+        // only the frames whose centres lie within the phi_T support of the wave's times
+        const float* dPr = dPg + static_cast<int64_t>(r0 + li) * nF;
+        const int nslot = L2 >> fg.s_t;
+        for (int q = 0; q < (nsl + 3) >> 2; ++q) {
+          const int k = 4 * q + lk;
+          const int sl = ((sl0 + k) % nslot + nslot) % nslot;
+          const int f = sl - s.f_lo;
+          float a = 0.f, b = 0.f;
+          if (k < nsl && f >= 0 && f < nF) {
+            a = dPr[f];
+            b = phi[((sl << fg.s_t) - (t0 + li)) & (L2 - 1)];
+          }
+          du = mfma(a, b, du);
         }
       } else {
         const float* dPr = dPg + static_cast<int64_t>(r0 + li) * nF;
@@ -892,7 +950,8 @@ hipError_t run_freq_fwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
 
 hipError_t run_freq_pool(const DevSig& s, const SigPlan& p, hipStream_t st) {
   if (p.groups.empty()) return hipSuccess;
-  hipLaunchKernelGGL(k_freq_pool, dim3(p.groups.size() * p.fr.size()), dim3(256), 0, st, s);
+  hipLaunchKernelGGL(k_freq_pool, dim3(p.groups.size() * p.fr.size(), (p.n_frames + kPoolFrames - 1) / kPoolFrames),
+                     dim3(256), 0, st, s);
   return hipGetLastError();
 }
 

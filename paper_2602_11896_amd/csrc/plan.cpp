@@ -461,6 +461,17 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   // otherwise the register-W kernel.
   auto fwd_loop = [&](int32_t S) { return S <= 32 && FT <= 2; };
   auto fwd_mt = [&](int32_t S) { return std::max(1, (FT == 1 ? tu.fwd_mt : 16) / S); };
+  // With more than 32 frames, a group whose phi_T is short next to its row can still use the
+  // row-tile-loop kernel: a chunk of TC times only reaches the frames whose centres lie
+  // within the phi_T support of it, at most (TC - 1 + 2 halo) / 2^s_t + 2 of them; if that is
+  // at most 32, the chunk pools into a 32-frame window starting at ceil((t0 - halo) / 2^s_t).
+  constexpr int32_t kWindow = 32;
+  auto fwd_window = [&](int32_t S, const FreqGroup& fg) {
+    if (FT <= 2 || S > 32) return false;
+    const int64_t TC = 64 * std::max(1, 16 / S);
+    if (TC >= fg.L2) return false;
+    return (TC - 1 + 2 * int64_t(fg.halo)) / (int64_t(1) << fg.s_t) + 2 <= kWindow;
+  };
   for (const Grp& grp : p.groups) {
     FreqGroup fg{};
     fg.y2 = p.y2_total;
@@ -469,15 +480,26 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     fg.j2 = grp.j2;
     fg.s_t = p.log2T - grp.j2;
     fg.phiT = add_lowpass_time(p, grp.L2, p.sigmaT, grp.j2);
+    {
+      float peak = 0.f;
+      for (int64_t d = 0; d < grp.L2; ++d) peak = std::max(peak, std::fabs(p.tables[fg.phiT + d]));
+      int64_t h = 0;
+      for (int64_t d = 0; d <= grp.L2 / 2; ++d)
+        if (std::fabs(p.tables[fg.phiT + d]) > 1e-9f * peak ||
+            std::fabs(p.tables[fg.phiT + (grp.L2 - d) % grp.L2]) > 1e-9f * peak)
+          h = d;
+      fg.halo = static_cast<int32_t>(h);
+    }
     // Time chunks of the forward contraction: at least 256 samples (or the whole row), at
     // most 128 chunks per group (64 when there are more than 16 frames, whose partial rows
     // are longer). Smaller chunks give more workgroups to hide load latency; every chunk
     // adds a partial row to sum (measured on MI355X at N = 2^16 with 8 and 128 frames).
     const int64_t max_chunks = nF <= 16 ? 128 : 64;
     const int32_t S = bucket_of(grp.K);
-    if (fwd_loop(S)) {
+    fg.fw = fwd_window(S, fg) ? kWindow : 0;
+    if (fwd_loop(S) || fg.fw > 0) {
       // a workgroup's four waves cover 64 MT consecutive times (the last chunk may be short)
-      fg.TC = 64 * fwd_mt(S);
+      fg.TC = 64 * (fg.fw > 0 ? std::max(1, 16 / S) : fwd_mt(S));
       fg.n_tc = static_cast<int32_t>(std::max<int64_t>(1, grp.L2 / fg.TC));
       // about 256 workgroups per group: more row splits re-load the same Y2 operands
       // (measured on MI355X, config 2: targets 16..4096 swept, 256 fastest)
@@ -490,7 +512,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
       fg.rt_fwd = 0;
     }
     fg.part = p.part_total;
-    p.part_total += static_cast<int64_t>(fg.n_tc) * p.R_pad * nF;
+    p.part_total += static_cast<int64_t>(fg.n_tc) * p.R_pad * (fg.fw > 0 ? fg.fw : nF);
     fg.dP = p.dP_total;
     p.dP_total += static_cast<int64_t>(p.R_pad) * nF;
     fg.n_tb = static_cast<int32_t>((grp.L2 + 63) / 64);
@@ -522,6 +544,19 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   // register-resident operands of a wave stay near 100 VGPRs.
   {
     for (int32_t S = 4; S <= 64; S *= 2) {
+      // windowed groups: the row-tile-loop kernel with two frame tiles
+      if (S <= 32 && FT > 2) {
+        SigPlan::FwdLaunch fl{S, 0, 2, static_cast<int32_t>(p.fwd_items.size()), 0, 0, std::max(1, 16 / S)};
+        for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
+          const FreqGroup& fg = p.fgroups[gi];
+          if (bucket_of(fg.K) != S || fg.fw == 0) continue;
+          const int32_t nrs = (n_rt + fg.rt_fwd - 1) / fg.rt_fwd;
+          for (int32_t tc = 0; tc < fg.n_tc; ++tc)
+            for (int32_t rs = 0; rs < nrs; ++rs) p.fwd_items.push_back(FwdItem{gi, rs, tc, 0});
+        }
+        fl.nitems = static_cast<int32_t>(p.fwd_items.size()) - fl.item0;
+        if (fl.nitems > 0) p.fwd_launches.push_back(fl);
+      }
       if (fwd_loop(S)) {
         // items (group, row split, time chunk)
         SigPlan::FwdLaunch fl{S, 0, FT, static_cast<int32_t>(p.fwd_items.size()), 0, 0, fwd_mt(S)};
@@ -541,7 +576,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
       SigPlan::FwdLaunch fl{S, RW, FT, static_cast<int32_t>(p.fwd_items.size()), 0, 0, 0};
       for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
         const FreqGroup& fg = p.fgroups[gi];
-        if (bucket_of(fg.K) != S) continue;
+        if (bucket_of(fg.K) != S || fg.fw > 0) continue;
         for (int32_t tc = 0; tc < fg.n_tc; ++tc)
           for (int32_t rb = 0; rb < p.R_pad / (64 * RW); ++rb) p.fwd_items.push_back(FwdItem{gi, rb, tc, 0});
       }

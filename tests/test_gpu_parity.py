@@ -312,3 +312,30 @@ def test_autotune_returns_a_working_schedule():
     x = ji.config1_signal(0, n=op.N)
     S = host(J.Plan(J.Params(*CFG1), tuning=tuning).forward(dev(x)))
     assert rel(S, fftroute.forward(op, x)) <= TOL_S
+
+
+CFG4 = (65536, 6, 8, 1, 3, 1, 9, 4)
+
+
+def test_config4_many_frames_parity():
+    """128 frames (T = 2^9 at N = 2^16): the forward pools each time chunk into a 32-frame
+    window and the backward visits only the frames within the phi_T support."""
+    say("[parity] config 4 (128 frames), full forward and backward")
+    op = make_plan(*CFG4)
+    x = ji.config4_signal(0)
+    y = ji.white_noise_like(x, 1)
+    S_x = fftroute.forward(op, x)
+    S_y, cache = fftroute.forward(op, y, return_cache=True)
+    plan = J.Plan(J.Params(*CFG4))
+    ws = plan.workspace()
+    yd = dev(y)
+    S = plan.forward(yd, ws=ws)
+    err = rel(host(S), S_y)
+    say(f"[parity] config 4 forward: rel L2 {err:.3e}")
+    assert err <= TOL_S
+    dS = 2.0 * (S_y - S_x)
+    g_ref = fftroute.backward(op, y, dS, cache=cache)
+    dx = plan.backward(yd, dev(dS), ws=ws, reuse_forward=True)
+    err = rel(host(dx), g_ref)
+    say(f"[parity] config 4 backward: rel L2 {err:.3e}")
+    assert err <= TOL_GRAD
