@@ -235,9 +235,11 @@ __device__ inline int window_start(const FreqGroup& fg, int tc) {
 // outside the kept ones get zero weight); the partial rows then hold fw window frames.
 template <int MAXS, int FT, int MT>
 __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
-  constexpr int WS = 4 * MAXS;                // LDS row stride (columns)
+  constexpr int WS = 4 * MAXS;                // W tile columns
+  constexpr int WSP = WS + 2;                 // LDS row pitch: a row stride of WS would put the
+                                              // 16 rows read by one instruction in one bank
   constexpr int PER = (16 * WS + 255) / 256;  // W elements staged per thread
-  __shared__ c32 wt[2][16 * WS];
+  __shared__ c32 wt[2][16 * WSP];
   __shared__ float red[2][4][FT * 256];
   const FwdItem it = s.fwd_items[item0 + blockIdx.x];
   const FreqGroup fg = s.fgroups[it.grp];
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
     const int e = threadIdx.x + 256 * i;
     if (e < 16 * WS) {
       const int rr = e / WS, n = e - rr * WS;
-      wt[0][e] = n < ncols ? s.W[static_cast<int64_t>(rt_lo * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
+      wt[0][rr * WSP + n] = n < ncols ? s.W[static_cast<int64_t>(rt_lo * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
     }
   }
   __syncthreads();
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
 #pragma unroll
           for (int q = 0; q < MAXS; ++q) {
             if (4 * q >= nlo && 4 * q < nhi) {
-              const c32 a = w[li * WS + 4 * q + lk];
+              const c32 a = w[li * WSP + 4 * q + lk];
               k1 = mfma(yre[j][q], a.x + a.y, k1);
               k2 = mfma(ydf[j][q], a.x, k2);
               k3 = mfma(ysm[j][q], a.y, k3);
@@ -350,7 +352,10 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const int e = threadIdx.x + 256 * i;
-        if (e < 16 * WS) wt[buf ^ 1][e] = wreg[i];
+        if (e < 16 * WS) {
+          const int rr = e / WS, n = e - rr * WS;
+          wt[buf ^ 1][rr * WSP + n] = wreg[i];
+        }
       }
     }
     __syncthreads();
@@ -638,9 +643,13 @@ __device__ inline int next_live_tile(const DevSig& s, int rt, int rt_hi, int Kal
 
 template <int MAXS, int MAXNT>
 __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
-  constexpr int WS = 4 * MAXS;               // LDS row stride (columns)
+  constexpr int WS = 4 * MAXS;               // W tile columns
+  // LDS row pitch (see the forward); the widest variant stays unpadded within 64 KiB
+  constexpr int WSP = MAXS >= 64 ? WS : WS + 2;
   constexpr int PER = (16 * WS + 255) / 256;  // W elements staged per thread
-  __shared__ c32 wt[2][16 * WS];
+  constexpr bool HOIST = MAXS <= 16;
+  // per buffer: the W tile, then (HOIST) 256 floats of pooled-gradient rows
+  __shared__ c32 wt[2][16 * WSP + (HOIST ? 128 : 0)];
   const BwdItem it = s.bwd_items[item0 + blockIdx.x];
   const FreqGroup fg = s.fgroups[it.grp];
   const int wave = wave_id();
@@ -698,8 +707,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
   // With at most 16 frames (and registers to spare), the Phi_T fragments of this wave's
   // times are loaded once, and each row tile's pooled gradients travel with its W tile
   // through LDS instead of being loaded inside the loop.
-  constexpr bool HOIST = MAXS <= 16;
-  __shared__ float dpt[2][HOIST ? 256 : 1];
+  auto dpt = [&](int b) { return reinterpret_cast<float*>(wt[b] + 16 * WSP); };
   const bool hoist = HOIST && nF <= 16;
   const float* dPg = s.dP + fg.dP;
   float bph[4];
@@ -722,9 +730,9 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
     for (int i = 0; i < PER; ++i) {
       const int e = threadIdx.x + 256 * i;
       const int rr = e / WS, n = e - rr * WS;
-      wt[0][e] = n < ncols ? s.W[static_cast<int64_t>(rt * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
+      wt[0][rr * WSP + n] = n < ncols ? s.W[static_cast<int64_t>(rt * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
     }
-    if (dp_thread) dpt[0][threadIdx.x] = dPg[static_cast<int64_t>(rt) * 16 * nF + threadIdx.x];
+    if (dp_thread) dpt(0)[threadIdx.x] = dPg[static_cast<int64_t>(rt) * 16 * nF + threadIdx.x];
   }
   __syncthreads();
   int buf = 0;
@@ -748,7 +756,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
 #pragma unroll
       for (int q = 0; q < MAXS; ++q) {
         if (4 * q >= nlo && 4 * q < nhi) {
-          const c32 a = w[li * WS + 4 * q + lk];
+          const c32 a = w[li * WSP + 4 * q + lk];
           if constexpr (G3) {
             k1 = mfma(a.x + a.y, yre[q], k1);
             k2 = mfma(a.x, ydf[q], k2);
@@ -769,7 +777,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
       }
       f4 du = {0.f, 0.f, 0.f, 0.f};
       if (hoist) {
-        const float* dp = dpt[buf] + li * nF;
+        const float* dp = dpt(buf) + li * nF;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (q < nFq) {
@@ -819,7 +827,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
         if (nt < NT && nt * 16 < nhi && nt * 16 + 16 > nlo) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const c32 a = w[(4 * lk + v) * WS + nt * 16 + li];
+            const c32 a = w[(4 * lk + v) * WSP + nt * 16 + li];
             if constexpr (G3) {
               dk1[nt] = mfma(a.x - a.y, dvr[v], dk1[nt]);
               dk2[nt] = mfma(a.x, ddf[v], dk2[nt]);
@@ -837,8 +845,12 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
     }
     if (nxt < rt_hi) {
 #pragma unroll
-      for (int i = 0; i < PER; ++i) wt[buf ^ 1][threadIdx.x + 256 * i] = wreg[i];
-      if (dp_thread) dpt[buf ^ 1][threadIdx.x] = dreg;
+      for (int i = 0; i < PER; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        const int rr = e / WS, n = e - rr * WS;
+        wt[buf ^ 1][rr * WSP + n] = wreg[i];
+      }
+      if (dp_thread) dpt(buf ^ 1)[threadIdx.x] = dreg;
     }
     __syncthreads();
     buf ^= 1;

@@ -40,6 +40,39 @@ def _batch_signals(args):
     return np.stack([ji.config4_signal(first + i) for i in range(batch)]).astype(np.float32)
 
 
+def _producer(q, worker: int, n_workers: int, batch: int) -> None:
+    """Batches worker, worker + n_workers, ... of the training stream, in order, into q."""
+    i = worker
+    while True:
+        q.put(_batch_signals((TRAIN_SEED0 + i * batch, batch)))
+        i += n_workers
+
+
+class _Batches:
+    """Training batches from daemon worker processes, each with its own bounded queue, read
+    round-robin so that batch i always holds seeds TRAIN_SEED0 + i B .. + B - 1."""
+
+    def __init__(self, batch: int, workers: int):
+        ctx = mp.get_context("fork")
+        self.qs = [ctx.Queue(maxsize=2) for _ in range(workers)]
+        self.ps = [ctx.Process(target=_producer, args=(q, w, workers, batch), daemon=True)
+                   for w, q in enumerate(self.qs)]
+        for p in self.ps:
+            p.start()
+        self.i = 0
+
+    def next(self) -> np.ndarray:
+        x = self.qs[self.i % len(self.qs)].get()
+        self.i += 1
+        return x
+
+    def stop(self) -> None:
+        for q in self.qs:
+            q.cancel_join_thread()
+        for p in self.ps:
+            p.terminate()
+
+
 def save_params(path: str, theta: np.ndarray, cfg: DecoderConfig, meta: dict) -> None:
     """Weights as bfloat16 bit patterns (the kernels use them rounded to bfloat16 anyway),
     biases as FP32."""
@@ -71,11 +104,8 @@ def load_params(path: str, cfg: DecoderConfig) -> np.ndarray:
 
 def train(seconds: float = 300.0, batch: int = 16, lr: float = 1e-3, init_seed: int = 0, workers: int = 12,
           log_every: int = 50, out: str = WEIGHTS, max_steps: int = 10 ** 9, resume: str = None) -> dict:
-    # the generator pool is forked before this process touches the GPU
-    ctx = mp.get_context("fork")
-    pool = ctx.Pool(workers)
-    jobs = ((TRAIN_SEED0 + i * batch, batch) for i in range(max_steps))
-    it = pool.imap(_batch_signals, jobs, chunksize=1)
+    # the generator processes are forked before this process touches the GPU
+    batches = _Batches(batch, workers)
     cfg = DecoderConfig()
     plan = Plan([CFG4] * batch)
     dec = Decoder(cfg, max_batch=batch)
@@ -106,7 +136,7 @@ def train(seconds: float = 300.0, batch: int = 16, lr: float = 1e-3, init_seed: 
     warm = 100
     try:
         while step < max_steps:
-            sig = next(it)
+            sig = batches.next()
             k = step % 2
             if copied[k] is not None:
                 copied[k].synchronize()
@@ -134,15 +164,16 @@ def train(seconds: float = 300.0, batch: int = 16, lr: float = 1e-3, init_seed: 
                     raise RuntimeError("training diverged")
             if elapsed >= seconds:
                 break
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        meta = {"steps": step, "batch": batch, "samples": step * batch, "seconds": round(wall, 1), "lr": lr,
+                "init_seed": init_seed, "train_seeds": [TRAIN_SEED0, TRAIN_SEED0 + step * batch - 1],
+                "final_mean_rel_loss": history[-1][2] if history else None}
+        if out:
+            save_params(out, theta.cpu().numpy(), cfg, meta)
+            print(json.dumps({"saved": out}), flush=True)
     finally:
-        pool.terminate()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    meta = {"steps": step, "batch": batch, "samples": step * batch, "seconds": round(wall, 1), "lr": lr,
-            "init_seed": init_seed, "train_seeds": [TRAIN_SEED0, TRAIN_SEED0 + step * batch - 1],
-            "final_mean_rel_loss": history[-1][2] if history else None}
-    if out:
-        save_params(out, theta.cpu().numpy(), cfg, meta)
+        batches.stop()
     meta["history"] = history
     return meta
 
