@@ -252,10 +252,21 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
   const int nF = s.nF;
   const c32* Y = s.Y2 + fg.y2;
   const float* phi = s.tables + fg.phiT;
-  const int tbase = it.tc * fg.TC;
   const int nslot = L2 >> fg.s_t;   // frame slots on the padded time axis
   const int slot0 = fg.fw > 0 ? window_start(fg, it.tc) : s.f_lo;
   const int pst = fg.fw > 0 ? fg.fw : nF;   // partial row stride
+  const int nrt = s.R_pad >> 4;
+  const int rt_lo = it.rb * fg.rt_fwd;
+  const int rt_hi = min(nrt, rt_lo + fg.rt_fwd);
+  const int ncols = min(WS, s.NW);
+  float* part = s.part + fg.part + static_cast<int64_t>(it.tc) * s.R_pad * pst;
+
+  // nsub passes over consecutive 64 MT-time sub-chunks of the chunk; every pass adds its
+  // pooled sums to the chunk's partial rows (the first pass stores them)
+  // (only windowed plans, launched with two frame tiles, take more than one pass)
+  const int nsub = FT == 2 ? fg.nsub : 1;
+  for (int sub = 0; sub < nsub; ++sub) {
+  const int tbase = it.tc * fg.TC + sub * 64 * MT;
 
   float yre[MT][MAXS], ydf[MT][MAXS], ysm[MT][MAXS], ph[MT][FT][4];
   bool act[MT];
@@ -283,10 +294,6 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
     }
   }
 
-  const int nrt = s.R_pad >> 4;
-  const int rt_lo = it.rb * fg.rt_fwd;
-  const int rt_hi = min(nrt, rt_lo + fg.rt_fwd);
-  const int ncols = min(WS, s.NW);
   c32 wreg[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
@@ -297,7 +304,6 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
     }
   }
   __syncthreads();
-  float* part = s.part + fg.part + static_cast<int64_t>(it.tc) * s.R_pad * pst;
   int buf = 0;
   for (int rt = rt_lo; rt < rt_hi; ++rt) {
     const bool next = rt + 1 < rt_hi;
@@ -368,10 +374,13 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
       const int f = (e >> 8) * 16 + 4 * (ln >> 4) + v;   // kept frame, or window frame
       if (f < pst) {
         const float sum = (red[buf][0][e] + red[buf][1][e]) + (red[buf][2][e] + red[buf][3][e]);
-        part[static_cast<int64_t>(rt * 16 + (ln & 15)) * pst + f] = sum;
+        float* dst = part + static_cast<int64_t>(rt * 16 + (ln & 15)) * pst + f;
+        *dst = sub == 0 ? sum : *dst + sum;
       }
     }
     buf ^= 1;
+  }
+  __syncthreads();   // the next pass restages wt[0] and rewrites red
   }
 }
 

@@ -465,12 +465,17 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   // row-tile-loop kernel: a chunk of TC times only reaches the frames whose centres lie
   // within the phi_T support of it, at most (TC - 1 + 2 halo) / 2^s_t + 2 of them; if that is
   // at most 32, the chunk pools into a 32-frame window starting at ceil((t0 - halo) / 2^s_t).
+  // A workgroup covers 64 MT times per pass (registers); long rows take nsub passes per
+  // chunk (at most 64 chunks), all pooled into the chunk's window.
   constexpr int32_t kWindow = 32;
-  auto fwd_window = [&](int32_t S, const FreqGroup& fg) {
-    if (FT <= 2 || S > 32) return false;
-    const int64_t TC = 64 * std::max(1, 16 / S);
-    if (TC >= fg.L2) return false;
-    return (TC - 1 + 2 * int64_t(fg.halo)) / (int64_t(1) << fg.s_t) + 2 <= kWindow;
+  auto window_nsub = [&](int32_t S, const FreqGroup& fg) {
+    if (FT <= 2 || S > 32) return 0;
+    const int64_t sub = 64 * std::max(1, 16 / S);
+    if (sub >= fg.L2) return 0;
+    const int64_t nsub = std::max<int64_t>(1, fg.L2 / sub / 64);
+    const int64_t TC = sub * nsub;
+    if (TC >= fg.L2) return 0;
+    return (TC - 1 + 2 * int64_t(fg.halo)) / (int64_t(1) << fg.s_t) + 2 <= kWindow ? static_cast<int32_t>(nsub) : 0;
   };
   for (const Grp& grp : p.groups) {
     FreqGroup fg{};
@@ -496,10 +501,13 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     // adds a partial row to sum (measured on MI355X at N = 2^16 with 8 and 128 frames).
     const int64_t max_chunks = nF <= 16 ? 128 : 64;
     const int32_t S = bucket_of(grp.K);
-    fg.fw = fwd_window(S, fg) ? kWindow : 0;
+    const int32_t wnsub = window_nsub(S, fg);
+    fg.fw = wnsub > 0 ? kWindow : 0;
+    fg.nsub = std::max(1, wnsub);
     if (fwd_loop(S) || fg.fw > 0) {
-      // a workgroup's four waves cover 64 MT consecutive times (the last chunk may be short)
-      fg.TC = 64 * (fg.fw > 0 ? std::max(1, 16 / S) : fwd_mt(S));
+      // a workgroup's four waves cover 64 MT consecutive times per pass, nsub passes per
+      // chunk (the last chunk may be short)
+      fg.TC = 64 * (fg.fw > 0 ? std::max(1, 16 / S) : fwd_mt(S)) * fg.nsub;
       fg.n_tc = static_cast<int32_t>(std::max<int64_t>(1, grp.L2 / fg.TC));
       // about 256 workgroups per group: more row splits re-load the same Y2 operands
       // (measured on MI355X, config 2: targets 16..4096 swept, 256 fastest)

@@ -66,6 +66,8 @@ struct FreqGroup {
   int32_t rt_fwd;           // forward row tiles per row split (row-tile-loop forward kernel)
   int32_t halo;             // phi_T support: |phi_T[d]| <= 1e-9 max beyond circular distance halo
   int32_t fw;               // > 0: each forward chunk pools into a window of fw frames (see plan)
+  int32_t nsub;             // row-tile-loop forward: sub-chunks of TC / nsub times per workgroup
+  int32_t pad_;
 };
 
 // Forward frequential work item: rows [rb*64, rb*64+64) x columns [tc*TC, (tc+1)*TC).
