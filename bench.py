@@ -144,10 +144,10 @@ def decoder_part(batch: int = 16, reps: int = 10) -> dict:
             "frac": round(tf / PEAK_BF16_MFMA_TFLOPS, 4)}
 
 
-def hbm_traffic(kernel: str):
+def hbm_traffic(kernel: str, tuning):
     """HBM bytes per launch of `kernel` from the committed counter record (FETCH_SIZE and
     WRITE_SIZE scaled by a copy of known size), or None when the kernel source changed
-    since the counters were taken."""
+    since the counters were taken or the plan uses other tile schedules than the record's."""
     import hashlib
     rec_path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
@@ -156,6 +156,11 @@ def hbm_traffic(kernel: str):
     except (OSError, ValueError, KeyError):
         return None
     if hashlib.sha1(src).hexdigest()[: len(rec["sha1_prefix"])] != rec["sha1_prefix"]:
+        return None
+    # the launch shapes of freq_fwd follow fwd_rows and fwd_mt, those of freq_bwd bwd_rows
+    fields = {"freq_fwd": (0, 1), "freq_bwd": (2,)}.get(kernel, (0, 1, 2, 3))
+    rt = rec.get("tuning")
+    if rt is None or any(rt[i] != tuning[i] for i in fields):
         return None
     # a stage may launch several shapes of the kernel (one per group size): sum them
     hits = [mb for k, mb in rec["hbm_MB_per_launch"].items() if k.startswith("k_" + kernel + "<")]
@@ -169,6 +174,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-config4", action="store_true", help="skip the learned-start and decoder measurements")
+    ap.add_argument("--no-autotune", action="store_true", help="plan with the default tile schedules")
+    ap.add_argument("--tuning", default=None, metavar="FWD_ROWS,FWD_MT,BWD_ROWS,SPLIT_BIAS",
+                    help="plan with these tile schedules instead of measuring them (e.g. to profile the "
+                         "launch configuration an earlier run chose)")
     ap.add_argument("--config4-signals", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (to scale HBM counters)")
@@ -194,7 +203,16 @@ def main() -> int:
     import paper_2602_11896_amd as J
 
     dev = torch.device("cuda:0")
-    plan = J.Plan(J.Params(**CFG2))
+    tuning, tune_ms = (None, None)
+    if args.tuning:
+        f = [int(v) for v in args.tuning.split(",")]
+        if len(f) != 4:
+            sys.exit("--tuning takes four integers: fwd_rows,fwd_mt,bwd_rows,split_bias")
+        tuning = J.Tuning(*f)
+    elif not args.no_autotune:
+        # plan-time: tile schedules measured on this device (not part of the timed region)
+        tuning, tune_ms = J.autotune(J.Params(**CFG2), device=dev)
+    plan = J.Plan(J.Params(**CFG2), tuning=tuning)
     x = torch.as_tensor(ji.config2_signal(2), dtype=torch.float32, device=dev)
     y0 = torch.as_tensor(ji.white_noise_like(ji.config2_signal(2), 3), dtype=torch.float32, device=dev)
     ws = plan.workspace(dev)
@@ -232,8 +250,11 @@ def main() -> int:
         name, t_ms, n = "freq_fwd", fwd_ms / max(fwd_n, 1), fwd_n
         flops = 8.0 * cost["mac_banded"] + 2.0 * cost["mac_pool"]
     achieved = flops / (t_ms * 1e-3) / 1e12
+    # the schedules the plan ran with (a zero field of jtfs_tuning selects the library default)
+    t = tuning if tuning is not None else J.Tuning()
+    eff_tuning = [t.fwd_rows or 256, t.fwd_mt or 32, t.bwd_rows or 256, t.split_bias]
     roofline = {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": hbm_traffic(name),
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": hbm_traffic(name, eff_tuning),
                 "algorithmic_flop_per_launch": flops, "avg_launch_ms": round(t_ms, 4), "launches": n}
 
     out = {
@@ -245,6 +266,10 @@ def main() -> int:
                    "global_batch": 1, "seq_len": 65536, "parallelism": "single GPU"},
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
         "roofline": roofline,
+        "tuning": {"fwd_rows": eff_tuning[0], "fwd_mt": eff_tuning[1], "bwd_rows": eff_tuning[2],
+                   "split_bias": eff_tuning[3], "source": ("autotune" if tune_ms is not None else
+                                                           "--tuning" if args.tuning else "default"),
+                   "autotune_fwd_bwd_ms": None if tune_ms is None else round(tune_ms, 4)},
     }
     if not args.no_config4:
         out["config4"] = config4_part(args.config4_signals)

@@ -19,6 +19,7 @@ import json
 import math
 import multiprocessing as mp
 import os
+import queue
 import sys
 import time
 
@@ -40,11 +41,19 @@ def _batch_signals(args):
     return np.stack([ji.config4_signal(first + i) for i in range(batch)]).astype(np.float32)
 
 
-def _producer(q, worker: int, n_workers: int, batch: int) -> None:
-    """Batches worker, worker + n_workers, ... of the training stream, in order, into q."""
+def _producer(q, stop, worker: int, n_workers: int, batch: int) -> None:
+    """Batches worker, worker + n_workers, ... of the training stream, in order, into q,
+    until `stop` is set."""
+    q.cancel_join_thread()   # exit without waiting for unread batches to be flushed
     i = worker
-    while True:
-        q.put(_batch_signals((TRAIN_SEED0 + i * batch, batch)))
+    while not stop.is_set():
+        x = _batch_signals((TRAIN_SEED0 + i * batch, batch))
+        while not stop.is_set():
+            try:
+                q.put(x, timeout=0.2)
+                break
+            except queue.Full:
+                pass
         i += n_workers
 
 
@@ -54,8 +63,9 @@ class _Batches:
 
     def __init__(self, batch: int, workers: int):
         ctx = mp.get_context("fork")
+        self.stop_event = ctx.Event()
         self.qs = [ctx.Queue(maxsize=2) for _ in range(workers)]
-        self.ps = [ctx.Process(target=_producer, args=(q, w, workers, batch), daemon=True)
+        self.ps = [ctx.Process(target=_producer, args=(q, self.stop_event, w, workers, batch), daemon=True)
                    for w, q in enumerate(self.qs)]
         for p in self.ps:
             p.start()
@@ -67,10 +77,19 @@ class _Batches:
         return x
 
     def stop(self) -> None:
+        """Asks the workers to finish their current batch and exit; ends any that do not
+        within a few seconds."""
+        self.stop_event.set()
+        deadline = time.monotonic() + 10.0
+        for p in self.ps:
+            p.join(timeout=max(0.0, deadline - time.monotonic()))
+        for p in self.ps:
+            if p.is_alive():
+                p.terminate()
+                p.join(timeout=1.0)
         for q in self.qs:
             q.cancel_join_thread()
-        for p in self.ps:
-            p.terminate()
+            q.close()
 
 
 def save_params(path: str, theta: np.ndarray, cfg: DecoderConfig, meta: dict) -> None:
