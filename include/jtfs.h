@@ -80,6 +80,8 @@ typedef struct {
   int64_t n_coeff_total;    /* sum of coefficient counts: length of S / dS / S_target */
   size_t  ws_forward;       /* workspace bytes for jtfs_forward */
   size_t  ws_backward;      /* workspace bytes for jtfs_backward and jtfs_metamer_step */
+  size_t  ws_shared_forward;   /* workspace bytes for jtfs_forward_ex with JTFS_SHARED_WORKSPACE */
+  size_t  ws_shared_backward;  /* workspace bytes for jtfs_backward with JTFS_SHARED_WORKSPACE */
 } jtfs_plan_info;
 
 /* Optimiser of the metamer descent (Sec. 2.3). */
@@ -162,15 +164,33 @@ int64_t jtfs_opt_state_floats(jtfs_plan_t plan, int32_t kind);
 jtfs_status jtfs_forward(jtfs_plan_t plan, const float* x, float* S, void* ws, size_t ws_bytes,
                          jtfs_stream_t stream);
 
-/* Flags of jtfs_backward. */
-#define JTFS_REUSE_FORWARD 1u   /* ws still holds the intermediates of jtfs_forward(x) */
+/* Flags of jtfs_forward_ex and jtfs_backward. */
+#define JTFS_REUSE_FORWARD 1u   /* jtfs_backward only: ws still holds the intermediates of
+                                   jtfs_forward(x) (or jtfs_forward_ex with the same flags) */
+#define JTFS_SHARED_WORKSPACE 2u  /* the signals of a batch take turns in one workspace of
+                                     ws_shared_* bytes (the largest signal's need) instead of
+                                     each holding its own: they run one after another on
+                                     `stream`. For callers that recompute the forward in the
+                                     backward (the gradient of Sec. 2.3 needs only x): with a
+                                     batch of more than one signal, a shared-workspace forward
+                                     leaves only the last signal's intermediates, so
+                                     JTFS_REUSE_FORWARD together with this flag is rejected
+                                     (JTFS_ERR_ARG) unless the batch has one signal. */
+
+/*
+ * jtfs_forward_ex - jtfs_forward with flags (0 or JTFS_SHARED_WORKSPACE; anything else is
+ * JTFS_ERR_ARG). With JTFS_SHARED_WORKSPACE, ws needs ws_shared_forward bytes.
+ */
+jtfs_status jtfs_forward_ex(jtfs_plan_t plan, const float* x, float* S, void* ws, size_t ws_bytes,
+                            uint32_t flags, jtfs_stream_t stream);
 
 /*
  * jtfs_backward - dx = J_S(x)^T dS, the exact adjoint of jtfs_forward at x
  * (Sec. 2.3, Eqs. 5-7, composed in reverse order; the modulus has subgradient 0 at 0).
  * With dS = 2 (S(y) - S(x)) this is grad E. dS: n_coeff_total floats; dx:
- * n_samples_total floats (overwritten). ws: at least ws_backward bytes. Without
- * JTFS_REUSE_FORWARD the forward intermediates are recomputed from x first.
+ * n_samples_total floats (overwritten). ws: at least ws_backward bytes (ws_shared_backward
+ * with JTFS_SHARED_WORKSPACE). Without JTFS_REUSE_FORWARD the forward intermediates are
+ * recomputed from x first. Unknown flags are JTFS_ERR_ARG.
  */
 jtfs_status jtfs_backward(jtfs_plan_t plan, const float* x, const float* dS, float* dx, void* ws,
                           size_t ws_bytes, uint32_t flags, jtfs_stream_t stream);

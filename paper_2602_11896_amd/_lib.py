@@ -23,6 +23,7 @@ JTFS_OPT_MOMENTUM_BOLD = 1
 JTFS_OPT_ADAM = 2
 
 JTFS_REUSE_FORWARD = 1
+JTFS_SHARED_WORKSPACE = 2
 JTFS_N_STAGES = 19
 STAGE_NAMES = ["signal_dft", "l1_wavelet", "l1_modulus_dft", "l1_average", "order1_freq", "l2_wavelet",
                "freq_fwd", "freq_pool", "freq_dP", "freq_bwd", "order1_bwd", "l1_average_adj", "dY2_dft",
@@ -41,7 +42,8 @@ class jtfs_path(ctypes.Structure):
 
 class jtfs_plan_info(ctypes.Structure):
     _fields_ = [("batch", c_int32), ("n_samples_total", c_int64), ("n_coeff_total", c_int64),
-                ("ws_forward", c_size_t), ("ws_backward", c_size_t)]
+                ("ws_forward", c_size_t), ("ws_backward", c_size_t),
+                ("ws_shared_forward", c_size_t), ("ws_shared_backward", c_size_t)]
 
 
 class jtfs_opt(ctypes.Structure):
@@ -78,6 +80,7 @@ SIGNATURES = [
     ("jtfs_plan_cost", c_int32, [c_void_p, c_int32, POINTER(c_double)]),
     ("jtfs_opt_state_floats", c_int64, [c_void_p, c_int32]),
     ("jtfs_forward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("jtfs_forward_ex", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_uint32, c_void_p]),
     ("jtfs_backward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_uint32, c_void_p]),
     ("jtfs_metamer_step", c_int32, [c_void_p, c_void_p, c_void_p, POINTER(jtfs_opt), c_void_p, c_void_p, c_size_t,
                                     c_void_p]),

@@ -4,10 +4,12 @@ Two memory modes:
 * ``"store"``: the forward keeps its intermediates (first-layer scalogram, its DFT,
   second-order stacks) in a backward-sized workspace held by the autograd graph; the
   backward reuses them (``JTFS_REUSE_FORWARD``).
-* ``"recompute"``: only x is saved; the forward uses a transient forward-sized
-  workspace and the backward recomputes the time-axis intermediates from x before the
-  adjoint stages. Results are bitwise identical to ``"store"`` (every kernel is
-  deterministic); the saving is the workspace held between forward and backward.
+* ``"recompute"``: only x is saved; the backward recomputes the time-axis
+  intermediates from x before the adjoint stages. Both passes run the signals of a batch
+  one after another in one shared workspace sized for the largest signal
+  (``JTFS_SHARED_WORKSPACE``), so nothing is held between forward and backward and the
+  backward's peak is one signal's workspace instead of the whole batch's. Results are
+  bitwise identical to ``"store"`` (every kernel is deterministic).
 
 The transform is positively homogeneous of degree 1, so gradients are defined almost
 everywhere; where a modulus argument is exactly 0 the subgradient 0 is used.
@@ -26,10 +28,10 @@ class _JTFSFunction(torch.autograd.Function):
         if mode == "store":
             ws = plan.workspace(x.device, backward=True)
         elif mode == "recompute":
-            ws = plan.workspace(x.device, backward=False)
+            ws = plan.workspace(x.device, backward=False, shared=True)
         else:
             raise ValueError("mode must be 'store' or 'recompute'")
-        S = plan.forward(x, ws=ws)
+        S = plan.forward(x, ws=ws, shared=(mode == "recompute"))
         ctx.plan = plan
         ctx.mode = mode
         ctx.ws = ws if mode == "store" else None
@@ -45,7 +47,7 @@ class _JTFSFunction(torch.autograd.Function):
             dx = plan.backward(x, dS, ws=ctx.ws, reuse_forward=True)
             ctx.ws = None
         else:
-            dx = plan.backward(x, dS, ws=plan.workspace(x.device, backward=True))
+            dx = plan.backward(x, dS, ws=plan.workspace(x.device, backward=True, shared=True), shared=True)
         return dx, None, None
 
 

@@ -2,6 +2,7 @@
 // the plan tables, argument checks and the order of the kernel stages.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -65,6 +66,7 @@ struct jtfs_plan_s {
   std::vector<int64_t> x_off, s_off;             // batch + 1
   std::vector<size_t> ws_off;                    // per signal segment start (bytes)
   size_t ws_fwd = 0, ws_bwd = 0;
+  size_t ws_fwd_shared = 0, ws_bwd_shared = 0;   // the largest signal's forward / backward segment
   int64_t n_total = 0, c_total = 0;
   std::mutex mu;
   std::map<int, DeviceArena> dev;
@@ -189,13 +191,14 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
   return JTFS_OK;
 }
 
-// Runs body(signal, stream) for every signal. A single signal runs on the caller's
-// stream; a batch is spread over the arena's streams, which first wait for the work
+// Runs body(signal, stream) for every signal. A single signal, or every signal when
+// `serial` is set, runs on the caller's stream; otherwise a batch is spread over the arena's streams, which first wait for the work
 // already enqueued on the caller's stream and are waited for by it at the end (event
 // fork / join, so the pattern is also valid under stream capture).
 template <class Body>
-jtfs_status for_each_signal(jtfs_plan_t plan, const DeviceArena* a, hipStream_t caller, Body body) {
-  if (plan->sig.size() == 1 || a->streams.empty()) {
+jtfs_status for_each_signal(jtfs_plan_t plan, const DeviceArena* a, hipStream_t caller, Body body,
+                            bool serial = false) {
+  if (serial || plan->sig.size() == 1 || a->streams.empty()) {
     for (size_t s = 0; s < plan->sig.size(); ++s) {
       jtfs_status r = body(s, caller);
       if (r != JTFS_OK) return r;
@@ -216,9 +219,10 @@ jtfs_status for_each_signal(jtfs_plan_t plan, const DeviceArena* a, hipStream_t 
   return r;
 }
 
-jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void* ws) {
+// `shared`: every signal's segment starts at ws (JTFS_SHARED_WORKSPACE).
+jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void* ws, bool shared = false) {
   const jtfs::SigPlan& sp = p->sig[s];
-  char* base = static_cast<char*>(ws) + p->ws_off[s];
+  char* base = static_cast<char*>(ws) + (shared ? 0 : p->ws_off[s]);
   const jtfs::WsLayout& w = sp.ws;
   jtfs::DevSig d{};
   d.tw = t.tw;
@@ -377,6 +381,8 @@ jtfs_status jtfs_plan_tuned(const jtfs_params* sig, int32_t batch, const jtfs_tu
       p->ws_off.push_back(ws);
       p->ws_fwd = ws + sp.ws.fwd_end;
       ws += sp.ws.bwd_end;
+      p->ws_fwd_shared = std::max(p->ws_fwd_shared, sp.ws.fwd_end);
+      p->ws_bwd_shared = std::max(p->ws_bwd_shared, sp.ws.bwd_end);
       std::vector<int64_t> bo(sp.groups.size() * sp.fr.size() + sp.fr_real.size(), -1);
       size_t gi = 0, ri = 0;
       for (const jtfs_path& r : sp.paths) {
@@ -406,6 +412,8 @@ jtfs_status jtfs_plan_query(jtfs_plan_t plan, jtfs_plan_info* info) {
   info->n_coeff_total = plan->c_total;
   info->ws_forward = plan->ws_fwd;
   info->ws_backward = plan->ws_bwd;
+  info->ws_shared_forward = plan->ws_fwd_shared;
+  info->ws_shared_backward = plan->ws_bwd_shared;
   return JTFS_OK;
 }
 
@@ -488,35 +496,55 @@ int64_t jtfs_opt_state_floats(jtfs_plan_t plan, int32_t kind) {
 }
 
 jtfs_status jtfs_forward(jtfs_plan_t plan, const float* x, float* S, void* ws, size_t ws_bytes, jtfs_stream_t stream) {
+  return jtfs_forward_ex(plan, x, S, ws, ws_bytes, 0u, stream);
+}
+
+jtfs_status jtfs_forward_ex(jtfs_plan_t plan, const float* x, float* S, void* ws, size_t ws_bytes, uint32_t flags,
+                            jtfs_stream_t stream) {
   if (!plan || !x || !S || !ws) return fail(JTFS_ERR_ARG, "NULL argument");
-  if (ws_bytes < plan->ws_fwd) return fail(JTFS_ERR_WORKSPACE, "workspace smaller than ws_forward");
+  if (flags & ~JTFS_SHARED_WORKSPACE) return fail(JTFS_ERR_ARG, "unknown flags");
+  const bool shared = (flags & JTFS_SHARED_WORKSPACE) != 0;
+  if (ws_bytes < (shared ? plan->ws_fwd_shared : plan->ws_fwd))
+    return fail(JTFS_ERR_WORKSPACE, shared ? "workspace smaller than ws_shared_forward"
+                                           : "workspace smaller than ws_forward");
   const DeviceArena* a = nullptr;
   jtfs_status r = device_tables(plan, &a);
   if (r != JTFS_OK) return r;
-  return for_each_signal(plan, a, static_cast<hipStream_t>(stream), [&](size_t s, hipStream_t st) {
-    jtfs::DevSig d = make_devsig(plan, s, a->sig[s], ws);
-    d.x = x + plan->x_off[s];
-    d.S = S + plan->s_off[s];
-    return forward_signal(plan, d, plan->sig[s], st);
-  });
+  return for_each_signal(
+      plan, a, static_cast<hipStream_t>(stream),
+      [&](size_t s, hipStream_t st) {
+        jtfs::DevSig d = make_devsig(plan, s, a->sig[s], ws, shared);
+        d.x = x + plan->x_off[s];
+        d.S = S + plan->s_off[s];
+        return forward_signal(plan, d, plan->sig[s], st);
+      },
+      shared);
 }
 
 jtfs_status jtfs_backward(jtfs_plan_t plan, const float* x, const float* dS, float* dx, void* ws, size_t ws_bytes,
                           uint32_t flags, jtfs_stream_t stream) {
   if (!plan || !x || !dS || !dx || !ws) return fail(JTFS_ERR_ARG, "NULL argument");
-  if (ws_bytes < plan->ws_bwd) return fail(JTFS_ERR_WORKSPACE, "workspace smaller than ws_backward");
-  if (flags & ~JTFS_REUSE_FORWARD) return fail(JTFS_ERR_ARG, "unknown flags");
+  if (flags & ~(JTFS_REUSE_FORWARD | JTFS_SHARED_WORKSPACE)) return fail(JTFS_ERR_ARG, "unknown flags");
+  const bool reuse = (flags & JTFS_REUSE_FORWARD) != 0;
+  const bool shared = (flags & JTFS_SHARED_WORKSPACE) != 0;
+  if (reuse && shared && plan->sig.size() > 1)
+    return fail(JTFS_ERR_ARG, "a shared workspace holds one signal's forward: JTFS_REUSE_FORWARD needs a batch of one");
+  if (ws_bytes < (shared ? plan->ws_bwd_shared : plan->ws_bwd))
+    return fail(JTFS_ERR_WORKSPACE, shared ? "workspace smaller than ws_shared_backward"
+                                           : "workspace smaller than ws_backward");
   const DeviceArena* a = nullptr;
   jtfs_status r = device_tables(plan, &a);
   if (r != JTFS_OK) return r;
-  const bool reuse = (flags & JTFS_REUSE_FORWARD) != 0;
-  return for_each_signal(plan, a, static_cast<hipStream_t>(stream), [&](size_t s, hipStream_t st) {
-    jtfs::DevSig d = make_devsig(plan, s, a->sig[s], ws);
-    d.x = x + plan->x_off[s];
-    d.dS = dS + plan->s_off[s];
-    d.dx = dx + plan->x_off[s];
-    return backward_signal(plan, d, plan->sig[s], reuse, st);
-  });
+  return for_each_signal(
+      plan, a, static_cast<hipStream_t>(stream),
+      [&](size_t s, hipStream_t st) {
+        jtfs::DevSig d = make_devsig(plan, s, a->sig[s], ws, shared);
+        d.x = x + plan->x_off[s];
+        d.dS = dS + plan->s_off[s];
+        d.dx = dx + plan->x_off[s];
+        return backward_signal(plan, d, plan->sig[s], reuse, st);
+      },
+      shared);
 }
 
 jtfs_status jtfs_metamer_step(jtfs_plan_t plan, float* y, const float* S_target, const jtfs_opt* opt, float* loss,

@@ -776,14 +776,18 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   w.U1h = take(sizeof(cfloat) * p.z1_total);
   w.S1 = take(sizeof(float) * N1 * p.nf_pad);
   w.Y2 = take(sizeof(cfloat) * std::max<int64_t>(p.y2_total, 1));
-  w.part = take(sizeof(float) * std::max<int64_t>(p.part_total, 1));
+  // The frequential forward's pooled partials are dead once φ_F pooling has read them;
+  // the backward's dY2 row-split partials live from the frequential backward to the
+  // layer-2 adjoint DFT. No stage uses both, so they share one region.
+  w.part = take(std::max(sizeof(float) * std::max<int64_t>(p.part_total, 1),
+                         sizeof(cfloat) * std::max<int64_t>(p.dYpart_total, 1)));
   w.scr = take(sizeof(cfloat) * std::max<int64_t>(p.scr_elems, 1));
   w.S = take(sizeof(float) * p.n_coeff);
   w.dS = take(sizeof(float) * p.n_coeff);
   w.o1 = take(sizeof(cfloat) * p.R_pad * p.n_frames);
   w.fwd_end = o;
   w.dP = take(sizeof(float) * std::max<int64_t>(p.dP_total, 1));
-  w.dYpart = take(sizeof(cfloat) * std::max<int64_t>(p.dYpart_total, 1));
+  w.dYpart = w.part;
   w.dYh = take(sizeof(cfloat) * (p.y2_total + int64_t(N1) * p.Lf));
   w.dS1p = take(sizeof(float) * p.fr_real.size() * N1 * p.nf_pad);
   w.dU1 = take(sizeof(float) * p.z1_total);

@@ -45,6 +45,7 @@ struct Launch {
 };
 
 // Byte offsets of workspace regions for one signal (relative to the signal's segment).
+// part and dYpart are one region (never live at the same time).
 struct WsLayout {
   size_t Xh, Z1, U1h, S1, Y2, part, scr, S, dS, o1;   // forward (+ loss scratch)
   size_t fwd_end;

@@ -94,6 +94,8 @@ class Plan:
         self.n_coeff = info.n_coeff_total
         self.ws_forward = info.ws_forward
         self.ws_backward = info.ws_backward
+        self.ws_shared_forward = info.ws_shared_forward
+        self.ws_shared_backward = info.ws_shared_backward
         xo = (ctypes.c_int64 * (self.batch + 1))()
         so = (ctypes.c_int64 * (self.batch + 1))()
         L.check(L.lib().jtfs_plan_offsets(self._h, xo, so), "jtfs_plan_offsets")
@@ -161,24 +163,36 @@ class Plan:
         return int(L.lib().jtfs_opt_state_floats(self._h, kind))
 
     # ---------------------------------------------------------------- buffers
-    def workspace(self, device="cuda", backward: bool = True) -> torch.Tensor:
-        n = self.ws_backward if backward else self.ws_forward
+    def workspace(self, device="cuda", backward: bool = True, shared: bool = False) -> torch.Tensor:
+        """Workspace for forward (backward=False) or backward calls; `shared`: the size for
+        calls with shared=True, where the signals take turns in one segment."""
+        if shared:
+            n = self.ws_shared_backward if backward else self.ws_shared_forward
+        else:
+            n = self.ws_backward if backward else self.ws_forward
         return torch.empty(max(n, 1), dtype=torch.uint8, device=device)
 
     # ---------------------------------------------------------------- compute
-    def forward(self, x: torch.Tensor, S: torch.Tensor = None, ws: torch.Tensor = None) -> torch.Tensor:
+    def forward(self, x: torch.Tensor, S: torch.Tensor = None, ws: torch.Tensor = None,
+                shared: bool = False) -> torch.Tensor:
+        """S(x). shared=True: the signals run one after another in a workspace of
+        ws_shared_forward bytes (JTFS_SHARED_WORKSPACE)."""
         _require(x, self.n_samples, "x")
         if S is None:
             S = torch.empty(self.n_coeff, dtype=torch.float32, device=x.device)
         _require(S, self.n_coeff, "S")
         if ws is None:
-            ws = self.workspace(x.device, backward=False)
-        L.check(L.lib().jtfs_forward(self._h, _ptr(x), _ptr(S), _ptr(ws), ws.numel(), _stream(x.device)),
-                "jtfs_forward")
+            ws = self.workspace(x.device, backward=False, shared=shared)
+        flags = L.JTFS_SHARED_WORKSPACE if shared else 0
+        L.check(L.lib().jtfs_forward_ex(self._h, _ptr(x), _ptr(S), _ptr(ws), ws.numel(), flags,
+                                        _stream(x.device)), "jtfs_forward_ex")
         return S
 
     def backward(self, x: torch.Tensor, dS: torch.Tensor, dx: torch.Tensor = None, ws: torch.Tensor = None,
-                 reuse_forward: bool = False) -> torch.Tensor:
+                 reuse_forward: bool = False, shared: bool = False) -> torch.Tensor:
+        """dx = J_S(x)^T dS. shared=True: the signals run one after another in a workspace
+        of ws_shared_backward bytes (JTFS_SHARED_WORKSPACE; with a batch of several signals
+        it cannot be combined with reuse_forward)."""
         _require(x, self.n_samples, "x")
         _require(dS, self.n_coeff, "dS")
         if dx is None:
@@ -187,8 +201,8 @@ class Plan:
         if ws is None:
             if reuse_forward:
                 raise ValueError("reuse_forward needs the workspace of the preceding forward")
-            ws = self.workspace(x.device)
-        flags = L.JTFS_REUSE_FORWARD if reuse_forward else 0
+            ws = self.workspace(x.device, shared=shared)
+        flags = (L.JTFS_REUSE_FORWARD if reuse_forward else 0) | (L.JTFS_SHARED_WORKSPACE if shared else 0)
         L.check(L.lib().jtfs_backward(self._h, _ptr(x), _ptr(dS), _ptr(dx), _ptr(ws), ws.numel(), flags,
                                       _stream(x.device)), "jtfs_backward")
         return dx

@@ -56,6 +56,42 @@ def test_store_and_recompute_are_bitwise_equal():
     assert torch.equal(grads[0], grads[1])
 
 
+def test_shared_workspace_batch_is_bitwise_equal():
+    """A heterogeneous batch run in one shared workspace (signals one after another) gives
+    the same S and gradient, bit for bit, as with a segment per signal; the batched
+    store/recompute autograd modes agree bit for bit as well."""
+    params = [J.Params(*CFG1), J.Params(*TINY), J.Params(384, 4, 3, 2, 2, 2, 4, 3)]
+    print("[shared ws] batch cfg1 + tiny + 384", flush=True)
+    plan = J.Plan(params)
+    x = dev(np.concatenate([ji.config1_signal(7), ji.config1_signal(8, n=512), ji.config1_signal(9, n=384)]))
+    dS = dev(np.random.default_rng(5).normal(size=plan.n_coeff))
+    S_own = plan.forward(x)
+    S_sh = plan.forward(x, ws=plan.workspace(x.device, backward=False, shared=True), shared=True)
+    dx_own = plan.backward(x, dS)
+    ws_sh = plan.workspace(x.device, shared=True)
+    assert ws_sh.numel() < plan.ws_backward
+    dx_sh = plan.backward(x, dS, ws=ws_sh, shared=True)
+    torch.cuda.synchronize()
+    assert torch.equal(S_own, S_sh)
+    assert torch.equal(dx_own, dx_sh)
+    with pytest.raises(Exception):
+        plan.backward(x, dS, ws=ws_sh, shared=True, reuse_forward=True)
+    grads = []
+    for mode in ("store", "recompute"):
+        xx = x.clone().requires_grad_(True)
+        (A.jtfs(xx, plan, mode) * dS).sum().backward()
+        grads.append(xx.grad.clone())
+    assert torch.equal(grads[0], grads[1])
+    assert torch.equal(grads[0], dx_own)
+    # one signal: a shared forward can be reused by the backward
+    one = J.Plan(J.Params(*CFG1))
+    x1 = x[:8192]
+    ws1 = one.workspace(x.device, shared=True)
+    one.forward(x1, ws=ws1, shared=True)
+    dx1 = one.backward(x1, dS[:one.n_coeff], ws=ws1, shared=True, reuse_forward=True)
+    assert torch.equal(dx1, dx_own[:8192])
+
+
 def test_module_and_batch_autograd():
     print("[autograd] module on a batch", flush=True)
     m = A.JTFS([J.Params(*TINY), J.Params(*TINY)], mode="recompute")

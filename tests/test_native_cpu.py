@@ -100,6 +100,30 @@ def test_host_side_argument_errors():
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_shared_workspace_sizes_and_flags():
+    """JTFS_SHARED_WORKSPACE: the batch needs the largest signal's segment, not the sum,
+    and a shared forward cannot be reused by a batched backward."""
+    a, b = J.Params(*CONFIGS["tiny"]), J.Params(*CONFIGS["cfg1"])
+    batch = J.Plan([a, b, a])
+    single = [J.Plan(q) for q in (a, b)]
+    assert batch.ws_shared_forward == max(q.ws_forward for q in single)
+    assert batch.ws_shared_backward == max(q.ws_backward for q in single)
+    assert batch.ws_shared_backward < batch.ws_backward
+    for q in single:   # one signal: the shared segment is the signal's own
+        assert (q.ws_shared_forward, q.ws_shared_backward) == (q.ws_forward, q.ws_backward)
+    lib = L.lib()
+    fake = ctypes.c_void_p(0x1000)
+    SH, RE = L.JTFS_SHARED_WORKSPACE, L.JTFS_REUSE_FORWARD
+    h = batch._h
+    assert lib.jtfs_forward_ex(h, fake, fake, fake, batch.ws_shared_forward - 1, SH, None) == L.JTFS_ERR_WORKSPACE
+    assert lib.jtfs_forward_ex(h, fake, fake, fake, batch.ws_forward, RE, None) == L.JTFS_ERR_ARG
+    assert lib.jtfs_forward_ex(h, fake, fake, fake, batch.ws_forward, 4, None) == L.JTFS_ERR_ARG
+    assert lib.jtfs_backward(h, fake, fake, fake, fake, batch.ws_shared_backward - 1, SH, None) == L.JTFS_ERR_WORKSPACE
+    assert lib.jtfs_backward(h, fake, fake, fake, fake, batch.ws_backward, SH | RE, None) == L.JTFS_ERR_ARG
+    assert b"batch of one" in lib.jtfs_last_error()
+    assert lib.jtfs_backward(h, fake, fake, fake, fake, batch.ws_backward, 4, None) == L.JTFS_ERR_ARG
+
+
 def test_fft_tile_index_logic_host_emulation(tmp_path):
     exe = tmp_path / "fft_emul"
     subprocess.run(["g++", "-std=c++17", "-O2", "-o", str(exe), os.path.join(ROOT, "tests", "native", "fft_emul.cpp")],
