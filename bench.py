@@ -144,7 +144,17 @@ def decoder_part(batch: int = 16, reps: int = 10) -> dict:
             "frac": round(tf / PEAK_BF16_MFMA_TFLOPS, 4)}
 
 
-def hbm_traffic(kernel: str, tuning):
+def effective_tuning(t) -> dict:
+    """The schedules a plan runs with: a zero field of jtfs_tuning selects the library
+    default (256, 32, 256, 0), a zero per-bucket target the global one."""
+    import paper_2602_11896_amd as J
+    t = t if t is not None else J.Tuning()
+    fr, br = t.fwd_rows or 256, t.bwd_rows or 256
+    return {"fwd_rows": fr, "fwd_mt": t.fwd_mt or 32, "bwd_rows": br, "split_bias": t.split_bias,
+            "fwd_rows_k": [v or fr for v in t.fwd_rows_k], "bwd_rows_k": [v or br for v in t.bwd_rows_k]}
+
+
+def hbm_traffic(kernel: str, tuning: dict):
     """HBM bytes per launch of `kernel` from the committed counter record (FETCH_SIZE and
     WRITE_SIZE scaled by a copy of known size), or None when the kernel source changed
     since the counters were taken or the plan uses other tile schedules than the record's."""
@@ -157,10 +167,11 @@ def hbm_traffic(kernel: str, tuning):
         return None
     if hashlib.sha1(src).hexdigest()[: len(rec["sha1_prefix"])] != rec["sha1_prefix"]:
         return None
-    # the launch shapes of freq_fwd follow fwd_rows and fwd_mt, those of freq_bwd bwd_rows
-    fields = {"freq_fwd": (0, 1), "freq_bwd": (2,)}.get(kernel, (0, 1, 2, 3))
+    # the launch shapes of freq_fwd follow fwd_mt and its row targets, those of freq_bwd
+    # the backward row targets
+    fields = {"freq_fwd": ("fwd_mt", "fwd_rows_k"), "freq_bwd": ("bwd_rows_k",)}.get(kernel, tuple(tuning))
     rt = rec.get("tuning")
-    if rt is None or any(rt[i] != tuning[i] for i in fields):
+    if not isinstance(rt, dict) or any(rt.get(f) != tuning[f] for f in fields):
         return None
     # a stage may launch several shapes of the kernel (one per group size): sum them
     hits = [mb for k, mb in rec["hbm_MB_per_launch"].items() if k.startswith("k_" + kernel + "<")]
@@ -175,9 +186,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-config4", action="store_true", help="skip the learned-start and decoder measurements")
     ap.add_argument("--no-autotune", action="store_true", help="plan with the default tile schedules")
-    ap.add_argument("--tuning", default=None, metavar="FWD_ROWS,FWD_MT,BWD_ROWS,SPLIT_BIAS",
+    ap.add_argument("--tuning", default=None, metavar="FWD_ROWS,FWD_MT,BWD_ROWS,SPLIT_BIAS[,F4..F64,B4..B64]",
                     help="plan with these tile schedules instead of measuring them (e.g. to profile the "
-                         "launch configuration an earlier run chose)")
+                         "launch configuration an earlier run chose): the four global fields, optionally "
+                         "followed by the five forward and five backward per-bucket row targets")
     ap.add_argument("--config4-signals", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (to scale HBM counters)")
@@ -206,9 +218,10 @@ def main() -> int:
     tuning, tune_ms = (None, None)
     if args.tuning:
         f = [int(v) for v in args.tuning.split(",")]
-        if len(f) != 4:
-            sys.exit("--tuning takes four integers: fwd_rows,fwd_mt,bwd_rows,split_bias")
-        tuning = J.Tuning(*f)
+        if len(f) not in (4, 14):
+            sys.exit("--tuning takes 4 integers (fwd_rows,fwd_mt,bwd_rows,split_bias) or 14 (then the "
+                     "five forward and five backward per-bucket row targets)")
+        tuning = J.Tuning(*f[:4]) if len(f) == 4 else J.Tuning(*f[:4], tuple(f[4:9]), tuple(f[9:14]))
     elif not args.no_autotune:
         # plan-time: tile schedules measured on this device (not part of the timed region)
         tuning, tune_ms = J.autotune(J.Params(**CFG2), device=dev)
@@ -250,9 +263,7 @@ def main() -> int:
         name, t_ms, n = "freq_fwd", fwd_ms / max(fwd_n, 1), fwd_n
         flops = 8.0 * cost["mac_banded"] + 2.0 * cost["mac_pool"]
     achieved = flops / (t_ms * 1e-3) / 1e12
-    # the schedules the plan ran with (a zero field of jtfs_tuning selects the library default)
-    t = tuning if tuning is not None else J.Tuning()
-    eff_tuning = [t.fwd_rows or 256, t.fwd_mt or 32, t.bwd_rows or 256, t.split_bias]
+    eff_tuning = effective_tuning(tuning)
     roofline = {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": hbm_traffic(name, eff_tuning),
                 "algorithmic_flop_per_launch": flops, "avg_launch_ms": round(t_ms, 4), "launches": n}
@@ -266,10 +277,9 @@ def main() -> int:
                    "global_batch": 1, "seq_len": 65536, "parallelism": "single GPU"},
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
         "roofline": roofline,
-        "tuning": {"fwd_rows": eff_tuning[0], "fwd_mt": eff_tuning[1], "bwd_rows": eff_tuning[2],
-                   "split_bias": eff_tuning[3], "source": ("autotune" if tune_ms is not None else
-                                                           "--tuning" if args.tuning else "default"),
-                   "autotune_fwd_bwd_ms": None if tune_ms is None else round(tune_ms, 4)},
+        "tuning": dict(eff_tuning, source=("autotune" if tune_ms is not None else
+                                           "--tuning" if args.tuning else "default"),
+                       autotune_fwd_bwd_ms=None if tune_ms is None else round(tune_ms, 4)),
     }
     if not args.no_config4:
         out["config4"] = config4_part(args.config4_signals)

@@ -248,9 +248,16 @@ void jtfs_plan_destroy(jtfs_plan_t plan);
  *   bwd_rows   workgroups per group targeted by the backward's row splits (default 256)
  *   split_bias shift of the split point of transforms longer than 4096 points, n = A B with
  *              log2 A = floor(log2 n / 2) + split_bias, clamped so that A, B <= 4096 (-2 .. 2)
+ *   fwd_rows_k, bwd_rows_k
+ *              the same targets for the groups of one k-step bucket (a group with K stacked
+ *              first-order rows needs ceil(K / 4) k-steps, rounded up to S = 4, 8, 16, 32 or
+ *              64; entry log2(S) - 2); 0 takes fwd_rows / bwd_rows. The buckets' kernels
+ *              differ in registers and LDS, hence in how many workgroups fit per CU.
  */
+#define JTFS_N_BUCKETS 5
 typedef struct {
   int32_t fwd_rows, fwd_mt, bwd_rows, split_bias;
+  int32_t fwd_rows_k[JTFS_N_BUCKETS], bwd_rows_k[JTFS_N_BUCKETS];
 } jtfs_tuning;
 
 /* jtfs_plan with explicit tile schedules (NULL = defaults). JTFS_ERR_ARG on a field out of range. */
@@ -258,9 +265,10 @@ jtfs_status jtfs_plan_tuned(const jtfs_params* signals, int32_t batch, const jtf
 
 /*
  * jtfs_autotune - pick tile schedules for these signals by measurement on the current
- * device: starting from the defaults, each field in turn takes the candidate value that
- * makes one forward + backward fastest (median of 3 timed runs on a seeded synthetic
- * signal, HIP events on `stream`). Allocates and frees its own device buffers; blocks until
+ * device: starting from the defaults, each field in turn (then each bucket's row targets)
+ * takes the candidate value that makes one forward + backward fastest (median of 5 timed
+ * runs on a seeded synthetic signal, HIP events on `stream`; a candidate must beat the
+ * current choice by 0.5%). Allocates and frees its own device buffers; blocks until
  * done. On success *out holds the choice and, if ms is not NULL, *ms its time.
  */
 jtfs_status jtfs_autotune(const jtfs_params* signals, int32_t batch, jtfs_stream_t stream, jtfs_tuning* out,

@@ -52,8 +52,12 @@ class jtfs_opt(ctypes.Structure):
                 ("bold_down", ctypes.c_float), ("state", c_void_p)]
 
 
+JTFS_N_BUCKETS = 5
+
+
 class jtfs_tuning(ctypes.Structure):
-    _fields_ = [("fwd_rows", c_int32), ("fwd_mt", c_int32), ("bwd_rows", c_int32), ("split_bias", c_int32)]
+    _fields_ = [("fwd_rows", c_int32), ("fwd_mt", c_int32), ("bwd_rows", c_int32), ("split_bias", c_int32),
+                ("fwd_rows_k", c_int32 * JTFS_N_BUCKETS), ("bwd_rows_k", c_int32 * JTFS_N_BUCKETS)]
 
 
 JTFS_DEC_MAX_LAYERS = 8

@@ -65,7 +65,7 @@ struct Bench {
   Events ev;
   std::vector<float> host;
 
-  // Median of three timed forward + backward runs (after one untimed run) of a plan.
+  // Median of five timed forward + backward runs (after one untimed run) of a plan.
   jtfs_status time(const jtfs_tuning& t, double& ms) {
     jtfs_plan_t plan = nullptr;
     jtfs_status r = jtfs_plan_tuned(sig, batch, &t, &plan);
@@ -98,7 +98,7 @@ struct Bench {
     jtfs_status r = once();
     if (r != JTFS_OK) return r;
     std::vector<double> t;
-    for (int rep = 0; rep < 3; ++rep) {
+    for (int rep = 0; rep < 5; ++rep) {
       if (hipEventRecord(ev.a, st) != hipSuccess) return jtfs::report(JTFS_ERR_HIP, "autotune: event failed");
       if ((r = once()) != JTFS_OK) return r;
       float e = 0.f;
@@ -108,7 +108,7 @@ struct Bench {
       t.push_back(e);
     }
     std::sort(t.begin(), t.end());
-    ms = t[1];
+    ms = t[2];
     return JTFS_OK;
   }
 };
@@ -121,10 +121,22 @@ extern "C" jtfs_status jtfs_autotune(const jtfs_params* signals, int32_t batch, 
   Bench b{signals, batch, static_cast<hipStream_t>(stream), {}, {}, {}, {}, {}, {}};
   if (hipEventCreate(&b.ev.a) != hipSuccess || hipEventCreate(&b.ev.b) != hipSuccess)
     return jtfs::report(JTFS_ERR_HIP, "autotune: event creation failed");
-  jtfs_tuning cur{256, 32, 256, 0};
+  jtfs_tuning cur{256, 32, 256, 0, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
   double best = 0.0;
   jtfs_status r = b.time(cur, best);
   if (r != JTFS_OK) return r;
+  // a candidate replaces the current choice only if clearly faster (run-to-run spread of
+  // the median is a few tenths of a percent)
+  auto consider = [&](const jtfs_tuning& cand) -> jtfs_status {
+    double t = 0.0;
+    const jtfs_status rr = b.time(cand, t);
+    if (rr != JTFS_OK) return rr;
+    if (t < 0.995 * best) {
+      best = t;
+      cur = cand;
+    }
+    return JTFS_OK;
+  };
   struct Knob {
     int32_t jtfs_tuning::*field;
     std::vector<int32_t> values;
@@ -138,11 +150,21 @@ extern "C" jtfs_status jtfs_autotune(const jtfs_params* signals, int32_t batch, 
     for (int32_t v : k.values) {
       jtfs_tuning cand = base;
       cand.*(k.field) = v;
-      double t = 0.0;
-      if ((r = b.time(cand, t)) != JTFS_OK) return r;
-      if (t < best) {
-        best = t;
-        cur = cand;
+      if ((r = consider(cand)) != JTFS_OK) return r;
+    }
+  }
+  // then each k-step bucket's own row targets (its kernels fit a different number of
+  // workgroups per CU); a bucket without groups leaves the time unchanged and keeps 0
+  const int32_t per_bucket[] = {64, 128, 256, 512, 1024};
+  for (int bk = 0; bk < JTFS_N_BUCKETS; ++bk) {
+    for (int which = 0; which < 2; ++which) {
+      const jtfs_tuning base = cur;
+      const int32_t global = which == 0 ? base.fwd_rows : base.bwd_rows;
+      for (int32_t v : per_bucket) {
+        if (v == global) continue;
+        jtfs_tuning cand = base;
+        (which == 0 ? cand.fwd_rows_k : cand.bwd_rows_k)[bk] = v;
+        if ((r = consider(cand)) != JTFS_OK) return r;
       }
     }
   }

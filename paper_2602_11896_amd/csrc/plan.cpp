@@ -169,14 +169,22 @@ int32_t subsampling_scale(double xi, double sigma) {
 }
 
 bool resolve_tuning(const jtfs_tuning* in, jtfs_tuning& t) {
-  t = jtfs_tuning{256, 32, 256, 0};
-  if (!in) return true;
-  if (in->fwd_rows) t.fwd_rows = in->fwd_rows;
-  if (in->fwd_mt) t.fwd_mt = in->fwd_mt;
-  if (in->bwd_rows) t.bwd_rows = in->bwd_rows;
-  t.split_bias = in->split_bias;
-  return t.fwd_rows >= 16 && t.fwd_rows <= 8192 && (t.fwd_mt == 16 || t.fwd_mt == 32) && t.bwd_rows >= 16 &&
-         t.bwd_rows <= 8192 && t.split_bias >= -2 && t.split_bias <= 2;
+  t = jtfs_tuning{256, 32, 256, 0, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+  if (in) {
+    if (in->fwd_rows) t.fwd_rows = in->fwd_rows;
+    if (in->fwd_mt) t.fwd_mt = in->fwd_mt;
+    if (in->bwd_rows) t.bwd_rows = in->bwd_rows;
+    t.split_bias = in->split_bias;
+  }
+  bool ok = t.fwd_rows >= 16 && t.fwd_rows <= 8192 && (t.fwd_mt == 16 || t.fwd_mt == 32) && t.bwd_rows >= 16 &&
+            t.bwd_rows <= 8192 && t.split_bias >= -2 && t.split_bias <= 2;
+  for (int b = 0; b < JTFS_N_BUCKETS; ++b) {
+    const int32_t f = in ? in->fwd_rows_k[b] : 0, w = in ? in->bwd_rows_k[b] : 0;
+    ok = ok && (f == 0 || (f >= 16 && f <= 8192)) && (w == 0 || (w >= 16 && w <= 8192));
+    t.fwd_rows_k[b] = f ? f : t.fwd_rows;
+    t.bwd_rows_k[b] = w ? w : t.bwd_rows;
+  }
+  return ok;
 }
 
 jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& err, const jtfs_tuning* tune) {
@@ -456,6 +464,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     const int32_t need = (K + 3) / 4;
     return need <= 4 ? 4 : need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 64;
   };
+  auto bucket_index = [](int32_t S) { return S <= 4 ? 0 : S == 8 ? 1 : S == 16 ? 2 : S == 32 ? 3 : 4; };
   // Forward kernel per group: the row-tile-loop kernel (W tiles in LDS, each wave keeping
   // MT 16-time tiles of Y2 in registers) where its registers allow (S <= 32, FT <= 2),
   // otherwise the register-W kernel.
@@ -511,7 +520,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
       fg.n_tc = static_cast<int32_t>(std::max<int64_t>(1, grp.L2 / fg.TC));
       // about 256 workgroups per group: more row splits re-load the same Y2 operands
       // (measured on MI355X, config 2: targets 16..4096 swept, 256 fastest)
-      const int32_t want = (tu.fwd_rows + fg.n_tc - 1) / fg.n_tc;
+      const int32_t want = (tu.fwd_rows_k[bucket_index(S)] + fg.n_tc - 1) / fg.n_tc;
       const int32_t rs = std::max(1, std::min(want, n_rt / 4));
       fg.rt_fwd = (n_rt + rs - 1) / rs;
     } else {
@@ -524,7 +533,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     fg.dP = p.dP_total;
     p.dP_total += static_cast<int64_t>(p.R_pad) * nF;
     fg.n_tb = static_cast<int32_t>((grp.L2 + 63) / 64);
-    int32_t want = (tu.bwd_rows + fg.n_tb - 1) / fg.n_tb;
+    int32_t want = (tu.bwd_rows_k[bucket_index(S)] + fg.n_tb - 1) / fg.n_tb;
     fg.RS = std::max(1, std::min(want, n_rt / 4));
     fg.rt_per_split = (n_rt + fg.RS - 1) / fg.RS;
     fg.RS = (n_rt + fg.rt_per_split - 1) / fg.rt_per_split;

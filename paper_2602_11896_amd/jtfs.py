@@ -7,7 +7,7 @@ from __future__ import annotations
 
 import ctypes
 from dataclasses import dataclass
-from typing import Iterable, List, Sequence, Union
+from typing import Iterable, List, Sequence, Tuple, Union
 
 import torch
 
@@ -49,14 +49,26 @@ def _require(t: torch.Tensor, numel: int, name: str, dtype=torch.float32) -> Non
 
 @dataclass
 class Tuning:
-    """Tile schedules of a plan (jtfs_tuning); 0 selects a field's default."""
+    """Tile schedules of a plan (jtfs_tuning); 0 selects a field's default. fwd_rows_k and
+    bwd_rows_k hold per-bucket row targets for k-step buckets S = 4, 8, 16, 32, 64 (0: the
+    global field)."""
     fwd_rows: int = 0
     fwd_mt: int = 0
     bwd_rows: int = 0
     split_bias: int = 0
+    fwd_rows_k: Tuple[int, ...] = (0,) * L.JTFS_N_BUCKETS
+    bwd_rows_k: Tuple[int, ...] = (0,) * L.JTFS_N_BUCKETS
 
     def c(self) -> L.jtfs_tuning:
-        return L.jtfs_tuning(self.fwd_rows, self.fwd_mt, self.bwd_rows, self.split_bias)
+        if len(self.fwd_rows_k) != L.JTFS_N_BUCKETS or len(self.bwd_rows_k) != L.JTFS_N_BUCKETS:
+            raise ValueError(f"per-bucket targets need {L.JTFS_N_BUCKETS} entries")
+        arr = ctypes.c_int32 * L.JTFS_N_BUCKETS
+        return L.jtfs_tuning(self.fwd_rows, self.fwd_mt, self.bwd_rows, self.split_bias,
+                             arr(*self.fwd_rows_k), arr(*self.bwd_rows_k))
+
+    @staticmethod
+    def from_c(t: L.jtfs_tuning) -> "Tuning":
+        return Tuning(t.fwd_rows, t.fwd_mt, t.bwd_rows, t.split_bias, tuple(t.fwd_rows_k), tuple(t.bwd_rows_k))
 
 
 def autotune(params: Union[Params, Sequence[Params]], device="cuda"):
@@ -67,7 +79,7 @@ def autotune(params: Union[Params, Sequence[Params]], device="cuda"):
     ms = ctypes.c_double()
     L.check(L.lib().jtfs_autotune(arr, len(plist), _stream(torch.device(device)), ctypes.byref(t), ctypes.byref(ms)),
             "jtfs_autotune")
-    return Tuning(t.fwd_rows, t.fwd_mt, t.bwd_rows, t.split_bias), ms.value
+    return Tuning.from_c(t), ms.value
 
 
 class Plan:

@@ -265,7 +265,8 @@ def test_batched_plan_matches_single():
     assert rel(S[Sa.size:], Sb) <= TOL_S
 
 
-@pytest.mark.parametrize("tuning", [(128, 16, 512, 1), (1024, 32, 128, -1)])
+@pytest.mark.parametrize("tuning", [(128, 16, 512, 1), (1024, 32, 128, -1),
+                                    (256, 32, 256, 0, (16, 1024, 64, 512, 0), (1024, 16, 512, 64, 0))])
 def test_tuned_plan_parity_cfg1(tuning):
     """Other tile schedules (row splits, time tiles, split points) compute the same transform."""
     say(f"[parity] tuned plan cfg1 {tuning}")
@@ -294,7 +295,7 @@ def test_tuned_plan_config2_sampled():
     x = ji.config2_signal(2)
     n2s = [op.groups[0].n2, op.groups[-1].n2]
     S_ref = fftroute.forward_partial(op, x, n2s)
-    plan = J.Plan(J.Params(*CFG2), tuning=J.Tuning(512, 16, 1024, -1))
+    plan = J.Plan(J.Params(*CFG2), tuning=J.Tuning(512, 16, 1024, -1, (64, 1024, 128, 512, 0), (1024, 64, 512, 128, 0)))
     S = host(plan.forward(dev(x)))
     mask = ~np.isnan(S_ref)
     err = rel(S[mask], S_ref[mask])

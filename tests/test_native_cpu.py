@@ -180,7 +180,8 @@ def test_decoder_host_argument_errors():
     assert lib.jtfs_loss(plan._h, None, p, p, p, 1, 1.0, None) == L.JTFS_ERR_ARG
 
 
-@pytest.mark.parametrize("tuning", [(128, 16, 512, 1), (1024, 32, 128, -1), (0, 0, 0, 2), (16, 16, 8192, -2)])
+@pytest.mark.parametrize("tuning", [(128, 16, 512, 1), (1024, 32, 128, -1), (0, 0, 0, 2), (16, 16, 8192, -2),
+                                    (256, 32, 256, 0, (64, 1024, 16, 8192, 0), (8192, 16, 64, 1024, 512))])
 def test_tuned_plans_keep_the_layout(tuning):
     """Tile schedules change neither the output layout nor the offsets of a plan."""
     args = CONFIGS["cfg2"]
@@ -191,7 +192,8 @@ def test_tuned_plans_keep_the_layout(tuning):
     assert p1.meta() == p0.meta()
 
 
-@pytest.mark.parametrize("tuning", [(8, 0, 0, 0), (0, 24, 0, 0), (0, 0, 20000, 0), (0, 0, 0, 3), (0, 0, 0, -3)])
+@pytest.mark.parametrize("tuning", [(8, 0, 0, 0), (0, 24, 0, 0), (0, 0, 20000, 0), (0, 0, 0, 3), (0, 0, 0, -3),
+                                    (0, 0, 0, 0, (8, 0, 0, 0, 0), (0,) * 5), (0, 0, 0, 0, (0,) * 5, (0, 0, 0, 0, 9000))])
 def test_tuning_out_of_range_is_rejected(tuning):
     args = CONFIGS["tiny"]
     with pytest.raises(L.JTFSError) as e:
