@@ -31,6 +31,25 @@ __device__ inline f4 mfma(float a, float b, f4 c) { return __builtin_amdgcn_mfma
 // Hardware square root (v_sqrt_f32, within 1 ulp) for moduli and phases.
 __device__ inline float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// 1 / sqrt(x) for x >= the smallest normal float (v_rsq_f32, within 1 ulp), else 0:
+// the phase scale of the modulus adjoint, with subgradient 0 where the modulus vanishes
+// (below 1.1e-19 the square underflows anyway).
+__device__ inline float inv_modulus(float m2) {
+  return m2 >= 1.17549435e-38f ? __builtin_amdgcn_rsqf(m2) : 0.f;
+}
+
+// Read of a table the plan uploaded once and no kernel writes, through the constant
+// address space: a scalar load, which does not wait behind the wave's outstanding vector
+// loads (the next tile's prefetch) as a vector load of the same word would.
+__device__ inline int load_table(const int* p, int i) {
+  typedef const __attribute__((address_space(4))) int ConstInt;
+  return ((ConstInt*)p)[i];
+}
+
+// Keeps a value live in a register at this point: the reads that produce it are issued
+// (and waited for) here, not sunk into the conditional blocks that use it.
+__device__ inline void materialize(float& x) { asm volatile("" : "+v"(x)); }
+
 // Index of the calling thread's wave, as a wave-uniform (scalar) value.
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
@@ -142,8 +161,8 @@ __global__ __launch_bounds__(256, (S >= 32 ? 1 : 2)) void k_freq_fwd(DevSig s, i
   int ulo = Kal, uhi = 0;
 #pragma unroll
   for (int i = 0; i < RW; ++i) {
-    const int lo = s.rt_nrange[2 * (rt0 + i)];
-    const int hi = min(s.rt_nrange[2 * (rt0 + i) + 1], Kal);
+    const int lo = load_table(s.rt_nrange, 2 * (rt0 + i));
+    const int hi = min(load_table(s.rt_nrange, 2 * (rt0 + i) + 1), Kal);
     qa[i] = lo;
     qb[i] = hi;
     if (hi > lo) {
@@ -317,24 +336,45 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
         }
       }
     }
-    const int nlo = s.rt_nrange[2 * rt];
-    const int nhi = min(s.rt_nrange[2 * rt + 1], Kal);
+    const int nlo = load_table(s.rt_nrange, 2 * rt);
+    const int nhi = min(load_table(s.rt_nrange, 2 * rt + 1), Kal);
     const c32* w = wt[buf];
     f4 pacc[FT];
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft) pacc[ft] = f4{0.f, 0.f, 0.f, 0.f};
     if (nhi > nlo) {
+      // with few k-steps, the row tile's W operands are read once (one LDS wait) for all
+      // MT time tiles
+      constexpr bool PRE = MAXS <= 8;
+      c32 av[PRE ? MAXS : 1];
+      if constexpr (PRE) {
+#pragma unroll
+        for (int q = 0; q < MAXS; ++q) av[q] = w[li * WSP + 4 * q + lk];
+#pragma unroll
+        for (int q = 0; q < MAXS; ++q) {
+          materialize(av[q].x);
+          materialize(av[q].y);
+        }
+      }
 #pragma unroll
       for (int j = 0; j < MT; ++j) {
         if (act[j]) {
+          // otherwise each k-step's operand is read one step ahead, its wait placed after
+          // the products of the step before
+          c32 an = PRE ? c32{0.f, 0.f} : w[li * WSP + lk];
           f4 k1 = {0.f, 0.f, 0.f, 0.f}, k2 = {0.f, 0.f, 0.f, 0.f}, k3 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int q = 0; q < MAXS; ++q) {
+            const c32 a = PRE ? av[PRE ? q : 0] : an;
+            if (!PRE && q + 1 < MAXS) an = w[li * WSP + 4 * (q + 1) + lk];
             if (4 * q >= nlo && 4 * q < nhi) {
-              const c32 a = w[li * WSP + 4 * q + lk];
               k1 = mfma(yre[j][q], a.x + a.y, k1);
               k2 = mfma(ydf[j][q], a.x, k2);
               k3 = mfma(ysm[j][q], a.y, k3);
+            }
+            if (!PRE && q + 1 < MAXS) {
+              materialize(an.x);
+              materialize(an.y);
             }
           }
           float u[4];
@@ -646,7 +686,7 @@ __global__ __launch_bounds__(256) void k_freq_dP(DevSig s) {
 // buffered: the next live tile's global loads are in flight while the current one is
 // used, and one barrier per tile separates the buffers.
 __device__ inline int next_live_tile(const DevSig& s, int rt, int rt_hi, int Kal) {
-  while (rt < rt_hi && min(s.rt_nrange[2 * rt + 1], Kal) <= s.rt_nrange[2 * rt]) ++rt;
+  while (rt < rt_hi && min(load_table(s.rt_nrange, 2 * rt + 1), Kal) <= load_table(s.rt_nrange, 2 * rt)) ++rt;
   return rt;
 }
 
@@ -756,16 +796,33 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
       }
       if (dp_thread) dreg = dPg[static_cast<int64_t>(nxt) * 16 * nF + threadIdx.x];
     }
-    const int nlo = s.rt_nrange[2 * rt];
-    const int nhi = min(s.rt_nrange[2 * rt + 1], Kal);
+    const int nlo = load_table(s.rt_nrange, 2 * rt);
+    const int nhi = min(load_table(s.rt_nrange, 2 * rt + 1), Kal);
     const int r0 = rt * 16;
     const c32* w = wt[buf];
     if (active) {
+      // With few k-steps, all of the tile's W operands are read at once (one LDS wait)
+      // before the in-band products.
+      constexpr bool PRE = MAXS <= 8;
+      c32 av[PRE ? MAXS : 1];
+      if constexpr (PRE) {
+#pragma unroll
+        for (int q = 0; q < MAXS; ++q) av[q] = w[li * WSP + 4 * q + lk];
+#pragma unroll
+        for (int q = 0; q < MAXS; ++q) {
+          materialize(av[q].x);
+          materialize(av[q].y);
+        }
+      }
+      // otherwise each k-step's operand is read one step ahead, its wait placed after
+      // the products of the step before
+      c32 an = PRE ? c32{0.f, 0.f} : w[li * WSP + lk];
       f4 k1 = {0.f, 0.f, 0.f, 0.f}, k2 = {0.f, 0.f, 0.f, 0.f}, k3 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int q = 0; q < MAXS; ++q) {
+        const c32 a = PRE ? av[PRE ? q : 0] : an;
+        if (!PRE && q + 1 < MAXS) an = w[li * WSP + 4 * (q + 1) + lk];
         if (4 * q >= nlo && 4 * q < nhi) {
-          const c32 a = w[li * WSP + 4 * q + lk];
           if constexpr (G3) {
             k1 = mfma(a.x + a.y, yre[q], k1);
             k2 = mfma(a.x, ydf[q], k2);
@@ -777,6 +834,10 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
             k2 = mfma(a.y, yre[q], k2);
           }
         }
+        if (!PRE && q + 1 < MAXS) {
+          materialize(an.x);
+          materialize(an.y);
+        }
       }
       f4 vr, vi;
 #pragma unroll
@@ -786,13 +847,17 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
       }
       f4 du = {0.f, 0.f, 0.f, 0.f};
       if (hoist) {
+        // li nF + f <= 15 * 16 + 15 stays inside the staged rows: read all four operands
+        // at once, then drop the frames beyond nF
         const float* dp = dpt(buf) + li * nF;
+        float dv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dv[q] = dp[4 * q + lk];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) materialize(dv[q]);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          if (q < nFq) {
-            const int f = 4 * q + lk;
-            du = mfma(f < nF ? dp[f] : 0.f, bph[q], du);
-          }
+          if (q < nFq) du = mfma(4 * q + lk < nF ? dv[q] : 0.f, bph[q], du);
         }
       } else if (nsl < nF) {
         // only the frames whose centres lie within the phi_T support of the wave's times
@@ -824,19 +889,36 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
       float dvr[4], ddf[4], dsm[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const float m = hw_sqrt(vr[v] * vr[v] + vi[v] * vi[v]);
-        const float sc = m > 0.f ? du[v] / m : 0.f;
+        const float sc = du[v] * inv_modulus(vr[v] * vr[v] + vi[v] * vi[v]);
         const float r = vr[v] * sc, i = vi[v] * sc;
         dvr[v] = r;
         ddf[v] = i - r;
         dsm[v] = r + i;
       }
+      c32 bv[PRE ? 4 * MAXNT : 1];
+      if constexpr (PRE) {
+#pragma unroll
+        for (int nt = 0; nt < MAXNT; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) bv[4 * nt + v] = w[(4 * lk + v) * WSP + nt * 16 + li];
+#pragma unroll
+        for (int e = 0; e < 4 * MAXNT; ++e) {
+          materialize(bv[e].x);
+          materialize(bv[e].y);
+        }
+      }
 #pragma unroll
       for (int nt = 0; nt < MAXNT; ++nt) {
         if (nt < NT && nt * 16 < nhi && nt * 16 + 16 > nlo) {
+          // (without the preload: the column tile's four operands are read together)
+          c32 bq[4];
+          if constexpr (!PRE) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) bq[v] = w[(4 * lk + v) * WSP + nt * 16 + li];
+          }
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const c32 a = w[(4 * lk + v) * WSP + nt * 16 + li];
+            const c32 a = PRE ? bv[PRE ? 4 * nt + v : 0] : bq[v];
             if constexpr (G3) {
               dk1[nt] = mfma(a.x - a.y, dvr[v], dk1[nt]);
               dk2[nt] = mfma(a.x, ddf[v], dk2[nt]);
