@@ -690,15 +690,19 @@ __device__ inline int next_live_tile(const DevSig& s, int rt, int rt_hi, int Kal
   return rt;
 }
 
-template <int MAXS, int MAXNT>
+// H: the pooled-gradient rows of each row tile travel with its W tile through LDS and the
+// Phi_T fragments are loaded once (at most 16 frames, MAXS <= 16); a separate
+// instantiation, so that the other paths' global loads do not make the compiler wait for
+// the W prefetch before the pooling products.
+template <int MAXS, int MAXNT, bool H>
 __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
   constexpr int WS = 4 * MAXS;               // W tile columns
   // LDS row pitch (see the forward); the widest variant stays unpadded within 64 KiB
   constexpr int WSP = MAXS >= 64 ? WS : WS + 2;
   constexpr int PER = (16 * WS + 255) / 256;  // W elements staged per thread
-  constexpr bool HOIST = MAXS <= 16;
-  // per buffer: the W tile, then (HOIST) 256 floats of pooled-gradient rows
-  __shared__ c32 wt[2][16 * WSP + (HOIST ? 128 : 0)];
+  static_assert(!H || MAXS <= 16, "hoisted pooled gradients need MAXS <= 16");
+  // per buffer: the W tile, then (H) 256 floats of pooled-gradient rows
+  __shared__ c32 wt[2][16 * WSP + (H ? 128 : 0)];
   const BwdItem it = s.bwd_items[item0 + blockIdx.x];
   const FreqGroup fg = s.fgroups[it.grp];
   const int wave = wave_id();
@@ -757,7 +761,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
   // times are loaded once, and each row tile's pooled gradients travel with its W tile
   // through LDS instead of being loaded inside the loop.
   auto dpt = [&](int b) { return reinterpret_cast<float*>(wt[b] + 16 * WSP); };
-  const bool hoist = HOIST && nF <= 16;
+  constexpr bool hoist = H;
   const float* dPg = s.dP + fg.dP;
   float bph[4];
 #pragma unroll
@@ -765,6 +769,10 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
     const int f = 4 * q + lk;
     bph[q] = (hoist && active && f < nF) ? phi[(((s.f_lo + f) << fg.s_t) - (t0 + li)) & (L2 - 1)] : 0.f;
   }
+  // complete these loads here: left pending into the loop, they make every pooling
+  // product wait for all outstanding loads, the next W tile's prefetch included
+#pragma unroll
+  for (int q = 0; q < 4; ++q) materialize(bph[q]);
   const bool dp_thread = hoist && static_cast<int>(threadIdx.x) < 16 * nF;
   // frame slots within the phi_T support of this wave's 16 times
   const int sl0 = -floor_div(fg.halo - t0, 1 << fg.s_t);
@@ -846,7 +854,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
         vi[v] = G3 ? k1[v] + k2[v] : k2[v];
       }
       f4 du = {0.f, 0.f, 0.f, 0.f};
-      if (hoist) {
+      if constexpr (hoist) {
         // li nF + f <= 15 * 16 + 15 stays inside the staged rows: read all four operands
         // at once, then drop the frames beyond nF
         const float* dp = dpt(buf) + li * nF;
@@ -859,7 +867,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
         for (int q = 0; q < 4; ++q) {
           if (q < nFq) du = mfma(4 * q + lk < nF ? dv[q] : 0.f, bph[q], du);
         }
-      } else if (nsl < nF) {
+      } else if (nsl < nF) {   // (not H)
         // only the frames whose centres lie within the phi_T support of the wave's times
         const float* dPr = dPg + static_cast<int64_t>(r0 + li) * nF;
         const int nslot = L2 >> fg.s_t;
@@ -1066,14 +1074,24 @@ hipError_t run_freq_dP(const DevSig& s, const SigPlan& p, hipStream_t st) {
 }
 
 hipError_t run_freq_bwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  const bool few_frames = p.n_frames <= 16;
   for (const SigPlan::BwdLaunch& l : p.bwd_launches) {
     const dim3 grid(l.nitems);
     switch (l.S) {
-      case 4: hipLaunchKernelGGL((k_freq_bwd<4, 1>), grid, dim3(256), 0, st, s, l.item0); break;
-      case 8: hipLaunchKernelGGL((k_freq_bwd<8, 2>), grid, dim3(256), 0, st, s, l.item0); break;
-      case 16: hipLaunchKernelGGL((k_freq_bwd<16, 4>), grid, dim3(256), 0, st, s, l.item0); break;
-      case 32: hipLaunchKernelGGL((k_freq_bwd<32, 8>), grid, dim3(256), 0, st, s, l.item0); break;
-      default: hipLaunchKernelGGL((k_freq_bwd<64, 16>), grid, dim3(256), 0, st, s, l.item0); break;
+      case 4:
+        if (few_frames) hipLaunchKernelGGL((k_freq_bwd<4, 1, true>), grid, dim3(256), 0, st, s, l.item0);
+        else hipLaunchKernelGGL((k_freq_bwd<4, 1, false>), grid, dim3(256), 0, st, s, l.item0);
+        break;
+      case 8:
+        if (few_frames) hipLaunchKernelGGL((k_freq_bwd<8, 2, true>), grid, dim3(256), 0, st, s, l.item0);
+        else hipLaunchKernelGGL((k_freq_bwd<8, 2, false>), grid, dim3(256), 0, st, s, l.item0);
+        break;
+      case 16:
+        if (few_frames) hipLaunchKernelGGL((k_freq_bwd<16, 4, true>), grid, dim3(256), 0, st, s, l.item0);
+        else hipLaunchKernelGGL((k_freq_bwd<16, 4, false>), grid, dim3(256), 0, st, s, l.item0);
+        break;
+      case 32: hipLaunchKernelGGL((k_freq_bwd<32, 8, false>), grid, dim3(256), 0, st, s, l.item0); break;
+      default: hipLaunchKernelGGL((k_freq_bwd<64, 16, false>), grid, dim3(256), 0, st, s, l.item0); break;
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
