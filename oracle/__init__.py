@@ -20,6 +20,9 @@ brute       "O1": the same transform by direct circular convolutions with
             time-domain filters and index-stride decimation (tiny sizes only).
 descent     Loss, relative loss and the metamer updates (Sec. 2.3): gradient
             descent, Adam, and momentum with the bold-driver learning rate.
+init        The paper's descent start (Sec. 2.3): Gaussian noise whose power spectral
+            density matches S1 x (band levels, Rayleigh factor, the interpolated
+            spectrum and the shaping of given standard normal draws).
 decoder     The learned warm start (an addition to the method, not in the paper): a
             1-D transposed-convolution decoder from coefficients to a waveform, its
             exact adjoint with the device's bfloat16 storage points, and Adam.
