@@ -86,13 +86,16 @@ def cpu_baseline() -> dict:
 
 def config4_part(n_signals: int) -> dict:
     """Second half of the metric: time to relative loss 1e-2 from the learned start versus
-    white noise (held-out seeds 0..n-1, N = 2^16, Adam lr 0.1; see runs.config4)."""
+    white noise (held-out seeds 0..n-1, N = 2^16, Adam lr 0.1; see runs.config4), with the
+    paper's coloured-noise start beside them (at most 600 descent steps)."""
     from paper_2602_11896_amd import runs
     r = runs.config4(n_signals=n_signals, learned_steps=100, plain_max_steps=5000, extra_target=1e-3,
-                     extra_cap=300)
+                     extra_cap=300, colored_max_steps=600)
     keep = ("n_signals", "median_rel_loss_decoder", "learned_reached_0.01", "plain_reached_0.01",
             "learned_median_seconds_0.01", "plain_median_seconds_0.01", "learned_median_steps_0.01",
             "plain_median_steps_0.01", "learned_median_seconds_0.001", "plain_median_seconds_0.001",
+            "colored_reached_0.01", "colored_median_seconds_0.01", "colored_median_steps_0.01",
+            "colored_bold_reached_0.01", "colored_bold_median_seconds_0.01", "colored_bold_median_steps_0.01",
             "plain_seconds_per_step")
     out = {k: r[k] for k in keep}
     a, b = r["learned_median_seconds_0.01"], r["plain_median_seconds_0.01"]

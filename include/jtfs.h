@@ -208,6 +208,24 @@ jtfs_status jtfs_metamer_step(jtfs_plan_t plan, float* y, const float* S_target,
                               float* loss, void* ws, size_t ws_bytes, jtfs_stream_t stream);
 
 /*
+ * jtfs_colored_noise - the descent start of Sec. 2.3: Gaussian noise whose power spectral
+ * density matches the first-order coefficients S1 x. The paper names the start, not its
+ * construction; this reading is computed per signal:
+ *   m_l   = mean of S1 x(t, l) over the kept frames (U1 x averaged by phi_T, Eq. 3)
+ *   c_l   = (4 / pi) m_l^2 / E_l, E_l = (1 / N_pad) sum_k |psi1_l^(k)|^2 (a circular Gaussian
+ *           with E|z|^2 = P has E|z| = sqrt(pi P) / 2)
+ *   H_k^2 = sum_l c_l |psi1_l^(k')|^2 / (sum_l |psi1_l^(k')|^2 + 1e-12 max_k sum_l |psi1_l^(k)|^2),
+ *           k' = min(k, N_pad - k), on the padded DFT grid
+ *   y0    = unpad(IDFT(H . DFT(pad(w))))
+ * x: the targets (n_samples_total device floats); w: as many independent standard normal
+ * draws (the caller's generator; the library draws no random numbers); y0: output, may
+ * not alias x or w. ws: at least ws_backward bytes (its contents are overwritten).
+ * Enqueued on `stream`; deterministic for given x and w.
+ */
+jtfs_status jtfs_colored_noise(jtfs_plan_t plan, const float* x, const float* w, float* y0, void* ws,
+                               size_t ws_bytes, jtfs_stream_t stream);
+
+/*
  * jtfs_loss - per-signal metamer loss and its gradient with respect to S (Sec. 2.3):
  * loss[s] = scale ||S_s - T_s||^2 / N_s and dS_s = 2 scale (S_s - T_s) / N_s, where
  * N_s = ||T_s||^2 if `relative` (the relative loss; N_s = 1 when T_s = 0) and 1 otherwise.

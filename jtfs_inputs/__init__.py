@@ -105,6 +105,11 @@ def concatenated_signal(seed: int, n_segments: int = 16, seg_len: int = 65536,
     return _unit_rms(np.concatenate(parts))
 
 
+def standard_normal(n: int, seed: int) -> np.ndarray:
+    """n independent standard normal draws (the noise the coloured-noise start shapes)."""
+    return np.random.default_rng(seed).standard_normal(n)
+
+
 def white_noise_like(x: np.ndarray, seed: int) -> np.ndarray:
     """Initial guess of a metamer descent: white Gaussian noise with the RMS of x."""
     rng = np.random.default_rng(seed)

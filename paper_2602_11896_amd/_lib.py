@@ -85,6 +85,7 @@ SIGNATURES = [
     ("jtfs_opt_state_floats", c_int64, [c_void_p, c_int32]),
     ("jtfs_forward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("jtfs_forward_ex", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_uint32, c_void_p]),
+    ("jtfs_colored_noise", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("jtfs_backward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_uint32, c_void_p]),
     ("jtfs_metamer_step", c_int32, [c_void_p, c_void_p, c_void_p, POINTER(jtfs_opt), c_void_p, c_void_p, c_size_t,
                                     c_void_p]),

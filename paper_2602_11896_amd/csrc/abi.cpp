@@ -45,6 +45,7 @@ struct SigTables {
   const int32_t* segterms;
   const jtfs::SplitTask* stasks;
   const int64_t* s_off;
+  const int32_t* band_psi1;   // per first-order filter: its band (level 0, N_pad grid)
 };
 
 struct DeviceArena {
@@ -137,6 +138,7 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     append_bytes(buf, o, sp.segs);
     append_bytes(buf, o, sp.segterms);
     append_bytes(buf, o, sp.stasks);
+    append_bytes(buf, o, sp.band_psi1);
   }
   DeviceArena a;
   if (hipMalloc(&a.base, buf.size() + 256) != hipSuccess) return fail(JTFS_ERR_NOMEM, "hipMalloc of plan tables failed");
@@ -165,6 +167,7 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     t.segs = reinterpret_cast<const int32_t*>(b + o[14]);
     t.segterms = reinterpret_cast<const int32_t*>(b + o[15]);
     t.stasks = reinterpret_cast<const jtfs::SplitTask*>(b + o[16]);
+    t.band_psi1 = reinterpret_cast<const int32_t*>(b + o[17]);
     a.sig.push_back(t);
   }
   if (p->sig.size() > 1) {
@@ -581,6 +584,34 @@ jtfs_status jtfs_metamer_step(jtfs_plan_t plan, float* y, const float* S_target,
     float* v1 = nv > 1 ? opt->state + Nt + plan->x_off[s] : nullptr;
     float* v2 = nv > 2 ? opt->state + 2 * Nt + plan->x_off[s] : nullptr;
     STAGE(17, jtfs::run_update(*opt, ys, grad, loss + s, v0, v1, v2, scal_base + 4 * s, sp.N, st));
+    return JTFS_OK;
+  });
+}
+
+jtfs_status jtfs_colored_noise(jtfs_plan_t plan, const float* x, const float* w, float* y0, void* ws, size_t ws_bytes,
+                               jtfs_stream_t stream) {
+  if (!plan || !x || !w || !y0 || !ws) return fail(JTFS_ERR_ARG, "NULL argument");
+  if (y0 == x || y0 == w) return fail(JTFS_ERR_ARG, "y0 may not alias x or w");
+  if (ws_bytes < plan->ws_bwd) return fail(JTFS_ERR_WORKSPACE, "workspace smaller than ws_backward");
+  const DeviceArena* a = nullptr;
+  jtfs_status r = device_tables(plan, &a);
+  if (r != JTFS_OK) return r;
+  return for_each_signal(plan, a, static_cast<hipStream_t>(stream), [&](size_t s, hipStream_t st) -> jtfs_status {
+    const jtfs::SigPlan& sp = plan->sig[s];
+    jtfs::DevSig d = make_devsig(plan, s, a->sig[s], ws);
+    // first layer of x up to S1 (the levels go to the dU1 region: z1_total >= N1 floats)
+    d.x = x + plan->x_off[s];
+    HIPCHK(jtfs::run_time_stage(jtfs::ST_XHAT, d, sp, st));
+    HIPCHK(jtfs::run_time_stage(jtfs::ST_L1Z, d, sp, st));
+    HIPCHK(jtfs::run_time_stage(jtfs::ST_L1UH, d, sp, st));
+    HIPCHK(jtfs::run_s1(d, sp, st));
+    HIPCHK(jtfs::run_cn_levels(d, sp, a->sig[s].band_psi1, d.dU1, st));
+    // DFT of the padded draws, shaped into dXh, inverse DFT and unpad into y0
+    d.x = w + plan->x_off[s];
+    HIPCHK(jtfs::run_time_stage(jtfs::ST_XHAT, d, sp, st));
+    HIPCHK(jtfs::run_cn_shape(d, sp, a->sig[s].band_psi1, d.dU1, st));
+    d.dx = y0 + plan->x_off[s];
+    HIPCHK(jtfs::run_signal_idft(d, sp, st));
     return JTFS_OK;
   });
 }

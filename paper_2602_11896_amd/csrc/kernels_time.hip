@@ -318,9 +318,9 @@ __global__ __launch_bounds__(256) void k_ds1h(DevSig s) {
   }
 }
 
-template <int ST>
+template <int ST, bool GATHER = true>
 hipError_t run_stage_t(const DevSig& s, const SigPlan& p, hipStream_t st) {
-  if (ST == ST_BX) {
+  if (ST == ST_BX && GATHER) {
     hipLaunchKernelGGL(k_bx_gather, dim3((p.N_pad + 255) / 256), dim3(256), 0, st, s, p.bx_job);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -352,6 +352,10 @@ hipError_t run_time_stage(int stage, const DevSig& s, const SigPlan& p, hipStrea
     case ST_BX: return run_stage_t<ST_BX>(s, p, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t run_signal_idft(const DevSig& s, const SigPlan& p, hipStream_t st) {
+  return run_stage_t<ST_BX, false>(s, p, st);
 }
 
 hipError_t run_s1(const DevSig& s, const SigPlan& p, hipStream_t st) {

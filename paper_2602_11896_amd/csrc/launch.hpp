@@ -11,6 +11,18 @@ namespace jtfs {
 hipError_t run_time_stage(int stage, const DevSig& s, const SigPlan& p, hipStream_t st);
 hipError_t run_s1(const DevSig& s, const SigPlan& p, hipStream_t st);
 hipError_t run_ds1h(const DevSig& s, const SigPlan& p, hipStream_t st);
+// dx = unpad(Re((1 / N_pad) sum_k dXh[k] e^{+2 pi i k n / N_pad})): the inverse DFT of
+// stage BX applied to a spectrum already in dXh (without BX's first-order gather).
+hipError_t run_signal_idft(const DevSig& s, const SigPlan& p, hipStream_t st);
+
+// kernels_init.hip (coloured-noise descent start)
+// c[n1] = (4 / pi) m_n1^2 / E_n1: m_n1 the mean of S1 over the kept frames, E_n1 the
+// energy per sample of filter n1 on the N_pad grid.
+hipError_t run_cn_levels(const DevSig& s, const SigPlan& p, const int32_t* band_psi1, float* c, hipStream_t st);
+// dXh[k] = Xh[k] H_k with H_k^2 = sum c |psi1^(k')|^2 / (sum |psi1^(k')|^2 + 1e-12 emax),
+// k' = min(k, N_pad - k).
+hipError_t run_cn_shape(const DevSig& s, const SigPlan& p, const int32_t* band_psi1, const float* c,
+                        hipStream_t st);
 
 // kernels_freq.hip
 hipError_t run_order1_fwd(const DevSig& s, const SigPlan& p, hipStream_t st);

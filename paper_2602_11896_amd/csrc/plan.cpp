@@ -344,6 +344,22 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
 
   // ---- band tables
   for (const Filt& f : p.psi1) p.band_psi1.push_back(add_morlet_band(p, p.N_pad, f.xi, f.sigma, 0));
+  {
+    // summed squared response of the first-order bank on the non-negative frequencies
+    // (the coloured-noise start normalises by it)
+    std::vector<double> e(static_cast<size_t>(p.N_pad / 2 + 1), 0.0);
+    for (int32_t bi : p.band_psi1) {
+      const Band& b = p.bands[bi];
+      for (int32_t d = 0; d < b.len; ++d) {
+        const int64_t k = (static_cast<int64_t>(b.lo) + d) % b.L;
+        if (k <= p.N_pad / 2) {
+          const double h = p.bandvals[static_cast<size_t>(b.off + d)];
+          e[static_cast<size_t>(k)] += h * h;
+        }
+      }
+    }
+    p.psi1_energy_max = static_cast<float>(*std::max_element(e.begin(), e.end()));
+  }
   p.band_phiT.assign(static_cast<size_t>(p.log2T + 1), -1);
   for (const Filt& f : p.psi1) {
     if (p.band_phiT[f.k] < 0) p.band_phiT[f.k] = add_lowpass_band(p, p.N_pad >> f.k, p.sigmaT, f.k);

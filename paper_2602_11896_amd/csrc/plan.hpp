@@ -70,6 +70,7 @@ struct SigPlan {
   std::vector<float> bandvals;
   std::vector<Band> bands;
   std::vector<int32_t> band_psi1;        // per n1, level 0 on the N_pad grid
+  float psi1_energy_max = 0.f;           // max over bins k <= N_pad / 2 of sum_n1 |psi1_n1^(k)|^2
   std::map<std::pair<int, int>, int32_t> band_psi2;   // (n2, level) -> band
   std::vector<int32_t> band_phiT;        // per level (0..log2T), -1 if unused
   std::vector<float> tables;             // time-domain phi_T (per group) and phi_F (per g)

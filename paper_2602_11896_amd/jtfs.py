@@ -219,6 +219,21 @@ class Plan:
                                       _stream(x.device)), "jtfs_backward")
         return dx
 
+    def colored_noise(self, x: torch.Tensor, w: torch.Tensor, y0: torch.Tensor = None,
+                      ws: torch.Tensor = None) -> torch.Tensor:
+        """The descent start of Sec. 2.3 (jtfs_colored_noise): the standard normal draws w
+        shaped to the power spectral density that S1 x describes."""
+        _require(x, self.n_samples, "x")
+        _require(w, self.n_samples, "w")
+        if y0 is None:
+            y0 = torch.empty(self.n_samples, dtype=torch.float32, device=x.device)
+        _require(y0, self.n_samples, "y0")
+        if ws is None:
+            ws = self.workspace(x.device)
+        L.check(L.lib().jtfs_colored_noise(self._h, _ptr(x), _ptr(w), _ptr(y0), _ptr(ws), ws.numel(),
+                                           _stream(x.device)), "jtfs_colored_noise")
+        return y0
+
     def metamer_step(self, y: torch.Tensor, S_target: torch.Tensor, opt: "Optimizer", loss: torch.Tensor,
                      ws: torch.Tensor) -> None:
         _require(y, self.n_samples, "y")

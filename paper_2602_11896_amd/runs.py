@@ -95,13 +95,16 @@ def config2(max_steps: int = 500) -> dict:
 
 
 def config4(n_signals: int = 32, learned_steps: int = 100, plain_max_steps: int = 5000, weights: str = None,
-            target: float = 1e-2, extra_target: float = 1e-3, extra_cap: int = 1000) -> dict:
+            target: float = 1e-2, extra_target: float = 1e-3, extra_cap: int = 1000,
+            colored_max_steps: int = None) -> dict:
     """Time to relative loss 1e-2 from the learned start (decoder, then at most ``learned_steps``
-    Adam steps) and from white noise (Adam, at most ``plain_max_steps`` steps), on held-out
-    seeds 0 .. n_signals-1 of the config-1 generator at N = 2^16, 8 kHz; Adam lr 0.1 in both.
-    The learned time counts the decoder and the evaluation of S at its output. The time to
-    ``extra_target`` is reported too where it is reached within ``learned_steps`` (learned)
-    or ``extra_cap`` steps (plain)."""
+    Adam steps), from white noise (Adam, at most ``plain_max_steps`` steps) and from the
+    paper's coloured-noise start (Adam, and the paper's momentum + bold-driver update with
+    mu0 = 0.1; at most ``colored_max_steps`` steps, default ``plain_max_steps``), on held-out
+    seeds 0 .. n_signals-1 of the config-1 generator at N = 2^16, 8 kHz; Adam lr 0.1. The
+    learned time counts the decoder and the evaluation of S at its output, the coloured
+    time the construction of the start. The time to ``extra_target`` is reported too where
+    it is reached within ``learned_steps`` (learned) or ``extra_cap`` steps (the others)."""
     from .decoder import Decoder, DecoderConfig
     from .train_decoder import CFG4, WEIGHTS, load_params
     cfg = DecoderConfig()
@@ -134,32 +137,31 @@ def config4(n_signals: int = 32, learned_steps: int = 100, plain_max_steps: int 
             else:
                 lr_[tag] = {"reached": False, "steps": None, "seconds": None}
         y = _dev(ji.white_noise_like(x, 10 ** 5 + max(seed, 0)))
-        opt = Optimizer(plan, "adam", lr=0.1)
-        pl = descend_until(plan, S_t, y, opt, extra_target, min(extra_cap, plain_max_steps), check_every=10,
-                           extra_targets=(target,))
-        if not pl[f"reached_{target:g}"] and plain_max_steps > extra_cap:
-            # continue the same descent up to the plain cap for the main target only
-            more = descend_until(plan, S_t, y, opt, target, plain_max_steps - extra_cap, check_every=10)
-            pl[f"reached_{target:g}"] = more["reached"]
-            pl[f"steps_{target:g}"] = extra_cap + more["steps"] if more["reached"] else None
-            pl[f"seconds_{target:g}"] = pl["seconds_run"] + more["seconds"] if more["reached"] else None
-            pl["steps_run"] += more["steps_run"]
-            pl["seconds_run"] += more["seconds_run"]
-        plain = {}
-        for tag, tgt in (("target", target), ("extra", extra_target)):
-            name = "" if tgt == extra_target else f"_{tgt:g}"
-            plain[tag] = {"reached": pl["reached" + name], "steps": pl["steps" + name], "seconds": pl["seconds" + name]}
-        plain["seconds_per_step"] = pl["seconds_run"] / pl["steps_run"]
+        plain = _two_targets(plan, S_t, y, Optimizer(plan, "adam", lr=0.1), target, extra_target, extra_cap,
+                             plain_max_steps)
+        # the paper's start (Sec. 2.3): noise coloured to S1 x, with Adam and with the
+        # paper's momentum + bold-driver update; its time counts the start's construction
+        xd, wd = _dev(x), _dev(ji.standard_normal(len(x), 2 * 10 ** 5 + max(seed, 0)))
+        col = {}
+        for name, kind in (("colored", "adam"), ("colored_bold", "momentum")):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            y = plan.colored_noise(xd, wd, ws=ws)
+            torch.cuda.synchronize()
+            t_init = time.perf_counter() - t0
+            col[name] = _two_targets(plan, S_t, y, Optimizer(plan, kind, lr=0.1), target, extra_target, extra_cap,
+                                     colored_max_steps or plain_max_steps, t_init)
         if seed < 0:
             continue
-        rows.append({"seed": seed, "learned": lr_, "plain": plain})
+        rows.append({"seed": seed, "learned": lr_, "plain": plain, **col})
         print(json.dumps(rows[-1]), flush=True)
 
     def med(which, tag, key):
         v = [r[which][tag][key] for r in rows if r[which][tag]["reached"]]
         return float(np.median(v)) if v else None
 
-    out = {"workload": f"config4: held-out seeds 0-{n_signals - 1}, learned start vs white noise, Adam lr 0.1",
+    out = {"workload": f"config4: held-out seeds 0-{n_signals - 1}, learned start vs white noise vs the "
+                       f"coloured-noise start (Adam lr 0.1; coloured also with momentum + bold driver, mu0 0.1)",
            "n_signals": n_signals, "median_rel_loss_decoder": float(np.median([r["learned"]["rel_loss_decoder"]
                                                                                for r in rows]))}
     for tag, tgt in (("target", target), ("extra", extra_target)):
@@ -170,8 +172,36 @@ def config4(n_signals: int = 32, learned_steps: int = 100, plain_max_steps: int 
         out[f"plain_median_seconds_{k}"] = med("plain", tag, "seconds")
         out[f"learned_median_steps_{k}"] = med("learned", tag, "steps")
         out[f"plain_median_steps_{k}"] = med("plain", tag, "steps")
+        for name in ("colored", "colored_bold"):
+            out[f"{name}_reached_{k}"] = sum(r[name][tag]["reached"] for r in rows)
+            out[f"{name}_median_seconds_{k}"] = med(name, tag, "seconds")
+            out[f"{name}_median_steps_{k}"] = med(name, tag, "steps")
     out["plain_seconds_per_step"] = float(np.median([r["plain"]["seconds_per_step"] for r in rows]))
     return out
+
+
+def _two_targets(plan: Plan, S_t: torch.Tensor, y: torch.Tensor, opt: Optimizer, target: float, extra_target: float,
+                 extra_cap: int, max_steps: int, t_init: float = 0.0) -> dict:
+    """Descent from y to ``extra_target`` (at most ``extra_cap`` steps), continued to
+    ``target`` alone up to ``max_steps``; per target: reached, steps, seconds (plus t_init)."""
+    pl = descend_until(plan, S_t, y, opt, extra_target, min(extra_cap, max_steps), check_every=10,
+                       extra_targets=(target,))
+    if not pl[f"reached_{target:g}"] and max_steps > extra_cap:
+        # continue the same descent up to the cap for the main target only
+        more = descend_until(plan, S_t, y, opt, target, max_steps - extra_cap, check_every=10)
+        pl[f"reached_{target:g}"] = more["reached"]
+        pl[f"steps_{target:g}"] = extra_cap + more["steps"] if more["reached"] else None
+        pl[f"seconds_{target:g}"] = pl["seconds_run"] + more["seconds"] if more["reached"] else None
+        pl["steps_run"] += more["steps_run"]
+        pl["seconds_run"] += more["seconds_run"]
+    res = {}
+    for tag, tgt in (("target", target), ("extra", extra_target)):
+        name = "" if tgt == extra_target else f"_{tgt:g}"
+        sec = pl["seconds" + name]
+        res[tag] = {"reached": pl["reached" + name], "steps": pl["steps" + name],
+                    "seconds": None if sec is None else t_init + sec}
+    res["seconds_per_step"] = pl["seconds_run"] / pl["steps_run"]
+    return res
 
 
 def config3(n_signals: int = 64, iters: int = 10) -> dict:

@@ -100,6 +100,16 @@ def test_host_side_argument_errors():
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_colored_noise_host_argument_errors():
+    lib = L.lib()
+    p = J.Plan(J.Params(*CONFIGS["tiny"]))
+    a, b, c = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    assert lib.jtfs_colored_noise(p._h, None, b, c, a, p.ws_backward, None) == L.JTFS_ERR_ARG
+    assert lib.jtfs_colored_noise(p._h, a, b, a, c, p.ws_backward, None) == L.JTFS_ERR_ARG     # y0 aliases x
+    assert lib.jtfs_colored_noise(p._h, a, b, b, c, p.ws_backward, None) == L.JTFS_ERR_ARG     # y0 aliases w
+    assert lib.jtfs_colored_noise(p._h, a, b, c, a, p.ws_backward - 1, None) == L.JTFS_ERR_WORKSPACE
+
+
 def test_shared_workspace_sizes_and_flags():
     """JTFS_SHARED_WORKSPACE: the batch needs the largest signal's segment, not the sum,
     and a shared forward cannot be reused by a batched backward."""
