@@ -315,6 +315,31 @@ def test_autotune_returns_a_working_schedule():
     assert rel(S, fftroute.forward(op, x)) <= TOL_S
 
 
+WIDE = (8192, 7, 40, 2, 4, 2, 7, 16)
+
+
+def test_wide_groups_parity():
+    """Second-order groups of more than 128 stacked rows (the 64-k-step bucket: the
+    register-W forward contraction and the widest backward, as at config 5) with 64
+    frames: S and the gradient at full size against the oracle."""
+    say("[parity] wide groups (K up to 145, 64 frames)")
+    op = make_plan(*WIDE)
+    assert max(g.K for g in op.groups) > 128
+    x = ji.config1_signal(8, n=op.N)
+    S_ref = fftroute.forward(op, x)
+    say("[parity] wide groups: oracle forward done")
+    plan, ws, S = run_forward(WIDE, x)
+    err_s = rel(host(S), S_ref)
+    say(f"[parity] wide groups forward: rel L2 {err_s:.3e}")
+    assert err_s <= TOL_S
+    dS = np.random.default_rng(6).standard_normal(op.n_coeff)
+    dx = plan.backward(dev(x), dev(dS), ws=ws, reuse_forward=True)
+    g_ref = fftroute.backward(op, x, dS)
+    err_g = rel(host(dx), g_ref)
+    say(f"[parity] wide groups backward: rel L2 {err_g:.3e}")
+    assert err_g <= TOL_GRAD
+
+
 CFG4 = (65536, 6, 8, 1, 3, 1, 9, 4)
 
 
