@@ -252,6 +252,11 @@ jtfs_status jtfs_loss(jtfs_plan_t plan, const float* S, const float* S_target, f
  */
 #define JTFS_N_STAGES 19
 jtfs_status jtfs_timing_enable(jtfs_plan_t plan, int32_t on);
+/* Brackets only the stages whose bit is set in `mask` (bit i: stage id i; 0 disables
+ * timing; bits at or above JTFS_N_STAGES are JTFS_ERR_ARG). Each bracket records two
+ * events, which cost a few microseconds of GPU time: timing one stage perturbs a step
+ * far less than timing all of them. */
+jtfs_status jtfs_timing_stages(jtfs_plan_t plan, uint32_t mask);
 jtfs_status jtfs_timing_read(jtfs_plan_t plan, double* ms, int64_t* counts, int32_t cap);
 
 /* Release a plan and its device tables. NULL is ignored. */

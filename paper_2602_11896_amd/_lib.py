@@ -91,6 +91,7 @@ SIGNATURES = [
                                     c_void_p]),
     ("jtfs_loss", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, ctypes.c_float, c_void_p]),
     ("jtfs_timing_enable", c_int32, [c_void_p, c_int32]),
+    ("jtfs_timing_stages", c_int32, [c_void_p, c_uint32]),
     ("jtfs_timing_read", c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64), c_int32]),
     ("jtfs_plan_destroy", None, [c_void_p]),
     ("jtfs_dec_create", c_int32, [POINTER(jtfs_dec_config), c_int32, POINTER(c_void_p)]),

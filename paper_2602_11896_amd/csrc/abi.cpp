@@ -72,7 +72,7 @@ struct jtfs_plan_s {
   std::mutex mu;
   std::map<int, DeviceArena> dev;
   // stage timing: (stage, start, stop) event triples recorded since the last read
-  bool timing = false;
+  uint32_t timing = 0;   // bit i: bracket stage i
   struct Mark {
     int stage;
     hipEvent_t a, b;
@@ -285,7 +285,7 @@ jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void
 // with two events on `st`.
 template <class F>
 hipError_t timed(jtfs_plan_t p, int stage, hipStream_t st, F launch) {
-  if (!p->timing) return launch();
+  if (!((p->timing >> stage) & 1u)) return launch();
   jtfs_plan_s::Mark m{stage, nullptr, nullptr};
   hipError_t e = hipEventCreate(&m.a);
   if (e != hipSuccess) return e;
@@ -631,7 +631,14 @@ jtfs_status jtfs_loss(jtfs_plan_t plan, const float* S, const float* S_target, f
 
 jtfs_status jtfs_timing_enable(jtfs_plan_t plan, int32_t on) {
   if (!plan) return fail(JTFS_ERR_ARG, "NULL plan");
-  plan->timing = on != 0;
+  plan->timing = on != 0 ? (1u << JTFS_N_STAGES) - 1u : 0u;
+  return JTFS_OK;
+}
+
+jtfs_status jtfs_timing_stages(jtfs_plan_t plan, uint32_t mask) {
+  if (!plan) return fail(JTFS_ERR_ARG, "NULL plan");
+  if (mask >> JTFS_N_STAGES) return fail(JTFS_ERR_ARG, "stage mask has bits beyond JTFS_N_STAGES");
+  plan->timing = mask;
   return JTFS_OK;
 }
 

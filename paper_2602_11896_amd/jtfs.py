@@ -160,9 +160,16 @@ class Plan:
         L.check(L.lib().jtfs_plan_cost(self._h, signal, out), "jtfs_plan_cost")
         return dict(zip(["mac_dense", "mac_banded", "mac_exec", "mac_pool"], list(out)))
 
-    def timing(self, on: bool) -> None:
-        """Bracket every kernel stage with HIP events on the caller's stream (see jtfs.h)."""
-        L.check(L.lib().jtfs_timing_enable(self._h, 1 if on else 0), "jtfs_timing_enable")
+    def timing(self, on: bool, stages: Sequence[str] = None) -> None:
+        """Bracket every kernel stage (or only the named ones) with HIP events on the
+        caller's stream (see jtfs.h)."""
+        if stages is None:
+            L.check(L.lib().jtfs_timing_enable(self._h, 1 if on else 0), "jtfs_timing_enable")
+            return
+        mask = 0
+        for name in stages:
+            mask |= 1 << L.STAGE_NAMES.index(name)
+        L.check(L.lib().jtfs_timing_stages(self._h, mask if on else 0), "jtfs_timing_stages")
 
     def timing_read(self) -> dict:
         """{stage name: (total ms, launches)} since the previous read (waits for the events)."""

@@ -100,6 +100,17 @@ def test_host_side_argument_errors():
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_timing_stage_mask():
+    lib = L.lib()
+    p = J.Plan(J.Params(*CONFIGS["tiny"]))
+    assert lib.jtfs_timing_stages(p._h, (1 << 6) | (1 << 9)) == L.JTFS_OK
+    assert lib.jtfs_timing_stages(p._h, 1 << L.JTFS_N_STAGES) == L.JTFS_ERR_ARG
+    assert lib.jtfs_timing_stages(None, 1) == L.JTFS_ERR_ARG
+    p.timing(True, stages=("freq_fwd", "freq_bwd"))
+    p.timing(False)
+    assert p.timing_read() == {}
+
+
 def test_colored_noise_host_argument_errors():
     lib = L.lib()
     p = J.Plan(J.Params(*CONFIGS["tiny"]))
