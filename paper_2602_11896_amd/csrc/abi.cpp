@@ -251,6 +251,7 @@ jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void
   d.S1 = reinterpret_cast<float*>(base + w.S1);
   d.Y2 = reinterpret_cast<jtfs::c32*>(base + w.Y2);
   d.part = reinterpret_cast<float*>(base + w.part);
+  d.psum = reinterpret_cast<float*>(base + w.psum);
   d.scr = reinterpret_cast<jtfs::c32*>(base + w.scr);
   d.dP = reinterpret_cast<float*>(base + w.dP);
   d.dYpart = reinterpret_cast<jtfs::c32*>(base + w.dYpart);

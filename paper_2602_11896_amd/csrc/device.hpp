@@ -39,6 +39,7 @@ struct DevSig {
   float* S1;
   c32* Y2;
   float* part;
+  float* psum;              // per non-windowed group: partials summed over time chunks (R_pad x nF)
   c32* scr;
   float* dP;
   c32* dYpart;

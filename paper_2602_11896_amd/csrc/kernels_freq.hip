@@ -424,8 +424,29 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
   }
 }
 
-// Sum of the time-chunk partials, phi_F averaging along log-frequency (band-pass g) or
-// nothing more (g = phi_F), log-frequency unpadding, store into S.
+// Sum over the time chunks of a non-windowed group's pooled partials, one thread per
+// (row, kept frame) cell: eight independent partial sums (eight loads in flight),
+// combined in a fixed order.
+__global__ __launch_bounds__(256) void k_freq_psum(DevSig s) {
+  const FreqGroup fg = s.fgroups[blockIdx.y];
+  if (fg.psum < 0) return;
+  const int64_t cells = static_cast<int64_t>(s.R_pad) * s.nF;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= cells) return;
+  const float* src = s.part + fg.part + e;
+  float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int tc = 0;
+  for (; tc + 8 <= fg.n_tc; tc += 8) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] += src[(tc + j) * cells];
+  }
+  for (int j = 0; tc < fg.n_tc; ++tc, ++j) a[j] += src[tc * cells];
+  s.psum[fg.psum + e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// Sum of the time-chunk partials (read from k_freq_psum, or summed here for windowed
+// groups), phi_F averaging along log-frequency (band-pass g) or nothing more (g = phi_F),
+// log-frequency unpadding, store into S.
 constexpr int kPoolFrames = 8;   // frames per pooling workgroup
 
 __global__ __launch_bounds__(256) void k_freq_pool(DevSig s) {
@@ -467,15 +488,8 @@ __global__ __launch_bounds__(256) void k_freq_pool(DevSig s) {
           if (o < fg.fw) a[(t - t_lo) & 7] += src[tc * stride + o];
         }
       } else {
-        // eight independent partial sums (eight loads in flight), combined in a fixed order
-        const float* src = s.part + fg.part + static_cast<int64_t>(ff.row0 + r) * nF + f0 + fl;
-        const int64_t stride = static_cast<int64_t>(s.R_pad) * nF;
-        int tc = 0;
-        for (; tc + 8 <= fg.n_tc; tc += 8) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) a[j] += src[(tc + j) * stride];
-        }
-        for (int j = 0; tc < fg.n_tc; ++tc, ++j) a[j] += src[tc * stride];
+        // summed over the time chunks by k_freq_psum
+        a[0] = s.psum[fg.psum + static_cast<int64_t>(ff.row0 + r) * nF + f0 + fl];
       }
       P[r * fc + fl] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
@@ -597,34 +611,34 @@ __global__ __launch_bounds__(64) void k_o1_dv(DevSig s) {
 
 // Step 2: dS1 contribution of filter g, Re(W_g^H dV), on every padded frame (zero
 // outside the kept ones); summed over g in a fixed order later.
-__global__ __launch_bounds__(64) void k_o1_ds1(DevSig s) {
+__global__ __launch_bounds__(256) void k_o1_ds1(DevSig s) {
+  // 64 cells per block; the four waves take interleaved quarters of the rows and their
+  // sums are combined through LDS in a fixed order
+  __shared__ float red[4][64];
   const int g = blockIdx.y;
   const FrFilter ff = s.frf[g];
-  const int e = blockIdx.x * 64 + threadIdx.x;
-  if (e >= s.N1 * s.nf_pad) return;
-  const int n = e / s.nf_pad, f = e - n * s.nf_pad;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
-  const int fl = f - s.f_lo;
-  if (fl >= 0 && fl < s.nF) {
-    const int nb = (s.N1 + (1 << s.sF) - 1) >> s.sF;
-    const int rows = ff.lowpass ? nb : ff.M;
-    // four independent partial sums (loads in flight), combined in a fixed order
-    int r = 0;
-    for (; r + 4 <= rows; r += 4) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const c32 w = s.W[static_cast<int64_t>(ff.row0 + r + j) * s.NW + n];
-        const c32 d = s.o1[(ff.row0 + r + j) * s.nF + fl];
+  if (e < s.N1 * s.nf_pad) {
+    const int n = e / s.nf_pad, f = e - n * s.nf_pad;
+    const int fl = f - s.f_lo;
+    if (fl >= 0 && fl < s.nF) {
+      const int nb = (s.N1 + (1 << s.sF) - 1) >> s.sF;
+      const int rows = ff.lowpass ? nb : ff.M;
+      // rows wave, wave + 4, ...: four independent partial sums per thread
+      int r = wave, j = 0;
+      for (; r < rows; r += 4, j = (j + 1) & 3) {
+        const c32 w = s.W[static_cast<int64_t>(ff.row0 + r) * s.NW + n];
+        const c32 d = s.o1[(ff.row0 + r) * s.nF + fl];
         acc[j] += w.x * d.x + w.y * d.y;
       }
     }
-    for (int j = 0; r < rows; ++r, ++j) {
-      const c32 w = s.W[static_cast<int64_t>(ff.row0 + r) * s.NW + n];
-      const c32 d = s.o1[(ff.row0 + r) * s.nF + fl];
-      acc[j] += w.x * d.x + w.y * d.y;
-    }
   }
-  s.dS1p[static_cast<int64_t>(g) * s.N1 * s.nf_pad + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  red[wave][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (wave == 0 && e < s.N1 * s.nf_pad)
+    s.dS1p[static_cast<int64_t>(g) * s.N1 * s.nf_pad + e] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 // Sum of the row-split partials of dY2 into split 0 (fixed order), groups with RS > 1.
@@ -987,7 +1001,7 @@ hipError_t run_order1_bwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
   const int rows = (p.R_pad * p.n_frames + 63) / 64;
   hipLaunchKernelGGL(k_o1_dv, dim3(rows), dim3(64), 0, st, s);
   const int cells = (static_cast<int>(p.psi1.size()) * p.nf_pad + 63) / 64;
-  hipLaunchKernelGGL(k_o1_ds1, dim3(cells, p.fr_real.size()), dim3(64), 0, st, s);
+  hipLaunchKernelGGL(k_o1_ds1, dim3(cells, p.fr_real.size()), dim3(256), 0, st, s);
   return hipGetLastError();
 }
 
@@ -1061,6 +1075,12 @@ hipError_t run_freq_fwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
 
 hipError_t run_freq_pool(const DevSig& s, const SigPlan& p, hipStream_t st) {
   if (p.groups.empty()) return hipSuccess;
+  if (p.psum_total > 0) {
+    const int blocks = static_cast<int>((static_cast<int64_t>(p.R_pad) * p.n_frames + 255) / 256);
+    hipLaunchKernelGGL(k_freq_psum, dim3(blocks, p.groups.size()), dim3(256), 0, st, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_freq_pool, dim3(p.groups.size() * p.fr.size(), (p.n_frames + kPoolFrames - 1) / kPoolFrames),
                      dim3(256), 0, st, s);
   return hipGetLastError();

@@ -546,6 +546,8 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     }
     fg.part = p.part_total;
     p.part_total += static_cast<int64_t>(fg.n_tc) * p.R_pad * (fg.fw > 0 ? fg.fw : nF);
+    fg.psum = fg.fw > 0 ? -1 : p.psum_total;
+    if (fg.fw == 0) p.psum_total += static_cast<int64_t>(p.R_pad) * nF;
     fg.dP = p.dP_total;
     p.dP_total += static_cast<int64_t>(p.R_pad) * nF;
     fg.n_tb = static_cast<int32_t>((grp.L2 + 63) / 64);
@@ -806,6 +808,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   // layer-2 adjoint DFT. No stage uses both, so they share one region.
   w.part = take(std::max(sizeof(float) * std::max<int64_t>(p.part_total, 1),
                          sizeof(cfloat) * std::max<int64_t>(p.dYpart_total, 1)));
+  w.psum = take(sizeof(float) * std::max<int64_t>(p.psum_total, 1));
   w.scr = take(sizeof(cfloat) * std::max<int64_t>(p.scr_elems, 1));
   w.S = take(sizeof(float) * p.n_coeff);
   w.dS = take(sizeof(float) * p.n_coeff);

@@ -47,7 +47,7 @@ struct Launch {
 // Byte offsets of workspace regions for one signal (relative to the signal's segment).
 // part and dYpart are one region (never live at the same time).
 struct WsLayout {
-  size_t Xh, Z1, U1h, S1, Y2, part, scr, S, dS, o1;   // forward (+ loss scratch)
+  size_t Xh, Z1, U1h, S1, Y2, part, psum, scr, S, dS, o1;   // forward (+ loss scratch)
   size_t fwd_end;
   size_t dP, dYpart, dYh, dS1p, dU1, dZh, dXh, grad;
   size_t bwd_end;
@@ -117,7 +117,7 @@ struct SigPlan {
 
   // ---- workspace
   std::vector<int64_t> z1_off;           // complex offset of row n1 in Z1 / U1h / dZh (float offset in dU1)
-  int64_t z1_total = 0, y2_total = 0, part_total = 0, dP_total = 0, dYpart_total = 0;
+  int64_t z1_total = 0, y2_total = 0, part_total = 0, psum_total = 0, dP_total = 0, dYpart_total = 0;
   int64_t scr_elems = 0;
   WsLayout ws{};
 };

@@ -59,6 +59,8 @@ struct FreqGroup {
   int64_t part;     // float offset of this group's pooled partial sums
   int64_t dP;       // float offset of this group's pooled-gradient rows
   int64_t dYpart;   // complex offset of this group's dY2 partials (RS x K x L2)
+  int64_t psum;     // float offset of the chunk sums (R_pad x nF) in the psum region, or -1
+                    // (windowed groups: the pooling kernel sums their partials itself)
   int32_t K, L2, j2, s_t;   // s_t = log2 T - j2 (time pooling stride exponent)
   int32_t TC, n_tc;         // t-chunk length of the forward and number of chunks
   int32_t RS, rt_per_split; // backward row splits and row tiles per split
