@@ -188,7 +188,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-config4", action="store_true", help="skip the learned-start and decoder measurements")
-    ap.add_argument("--no-autotune", action="store_true", help="plan with the default tile schedules")
+    ap.add_argument("--autotune", action="store_true",
+                    help="measure the tile schedules on this device before planning (jtfs_autotune) instead of "
+                         "using the library defaults; at config 2 its choices are within run-to-run noise of the "
+                         "defaults, and the HBM counter record only applies to the schedules it was taken with")
     ap.add_argument("--tuning", default=None, metavar="FWD_ROWS,FWD_MT,BWD_ROWS,SPLIT_BIAS[,F4..F64,B4..B64]",
                     help="plan with these tile schedules instead of measuring them (e.g. to profile the "
                          "launch configuration an earlier run chose): the four global fields, optionally "
@@ -225,7 +228,7 @@ def main() -> int:
             sys.exit("--tuning takes 4 integers (fwd_rows,fwd_mt,bwd_rows,split_bias) or 14 (then the "
                      "five forward and five backward per-bucket row targets)")
         tuning = J.Tuning(*f[:4]) if len(f) == 4 else J.Tuning(*f[:4], tuple(f[4:9]), tuple(f[9:14]))
-    elif not args.no_autotune:
+    elif args.autotune:
         # plan-time: tile schedules measured on this device (not part of the timed region)
         tuning, tune_ms = J.autotune(J.Params(**CFG2), device=dev)
     plan = J.Plan(J.Params(**CFG2), tuning=tuning)
