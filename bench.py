@@ -149,10 +149,10 @@ def decoder_part(batch: int = 16, reps: int = 10) -> dict:
 
 def effective_tuning(t) -> dict:
     """The schedules a plan runs with: a zero field of jtfs_tuning selects the library
-    default (256, 32, 256, 0), a zero per-bucket target the global one."""
+    default (256, 32, 128, 0), a zero per-bucket target the global one."""
     import paper_2602_11896_amd as J
     t = t if t is not None else J.Tuning()
-    fr, br = t.fwd_rows or 256, t.bwd_rows or 256
+    fr, br = t.fwd_rows or 256, t.bwd_rows or 128
     return {"fwd_rows": fr, "fwd_mt": t.fwd_mt or 32, "bwd_rows": br, "split_bias": t.split_bias,
             "fwd_rows_k": [v or fr for v in t.fwd_rows_k], "bwd_rows_k": [v or br for v in t.bwd_rows_k]}
 

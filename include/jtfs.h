@@ -268,7 +268,7 @@ void jtfs_plan_destroy(jtfs_plan_t plan);
  *   fwd_rows   workgroups per second-order group targeted by the forward contraction's row
  *              splits (default 256; 16 .. 8192)
  *   fwd_mt     forward time tiles per wave times the group's k-steps: 16 or 32 (default 32)
- *   bwd_rows   workgroups per group targeted by the backward's row splits (default 256)
+ *   bwd_rows   workgroups per group targeted by the backward's row splits (default 128)
  *   split_bias shift of the split point of transforms longer than 4096 points, n = A B with
  *              log2 A = floor(log2 n / 2) + split_bias, clamped so that A, B <= 4096 (-2 .. 2)
  *   fwd_rows_k, bwd_rows_k

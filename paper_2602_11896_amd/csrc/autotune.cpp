@@ -121,7 +121,7 @@ extern "C" jtfs_status jtfs_autotune(const jtfs_params* signals, int32_t batch, 
   Bench b{signals, batch, static_cast<hipStream_t>(stream), {}, {}, {}, {}, {}, {}};
   if (hipEventCreate(&b.ev.a) != hipSuccess || hipEventCreate(&b.ev.b) != hipSuccess)
     return jtfs::report(JTFS_ERR_HIP, "autotune: event creation failed");
-  jtfs_tuning cur{256, 32, 256, 0, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+  jtfs_tuning cur{256, 32, 128, 0, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
   double best = 0.0;
   jtfs_status r = b.time(cur, best);
   if (r != JTFS_OK) return r;

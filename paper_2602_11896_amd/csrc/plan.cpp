@@ -169,7 +169,7 @@ int32_t subsampling_scale(double xi, double sigma) {
 }
 
 bool resolve_tuning(const jtfs_tuning* in, jtfs_tuning& t) {
-  t = jtfs_tuning{256, 32, 256, 0, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+  t = jtfs_tuning{256, 32, 128, 0, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
   if (in) {
     if (in->fwd_rows) t.fwd_rows = in->fwd_rows;
     if (in->fwd_mt) t.fwd_mt = in->fwd_mt;
