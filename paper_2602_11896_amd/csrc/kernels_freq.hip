@@ -714,7 +714,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
   // LDS row pitch (see the forward); the widest variant stays unpadded within 64 KiB
   constexpr int WSP = MAXS >= 64 ? WS : WS + 2;
   constexpr int PER = (16 * WS + 255) / 256;  // W elements staged per thread
-  static_assert(!H || MAXS <= 16, "hoisted pooled gradients need MAXS <= 16");
+  static_assert(!H || MAXS <= 32, "hoisted pooled gradients need MAXS <= 32");
   // per buffer: the W tile, then (H) 256 floats of pooled-gradient rows
   __shared__ c32 wt[2][16 * WSP + (H ? 128 : 0)];
   const BwdItem it = s.bwd_items[item0 + blockIdx.x];
@@ -1110,7 +1110,10 @@ hipError_t run_freq_bwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
         if (few_frames) hipLaunchKernelGGL((k_freq_bwd<16, 4, true>), grid, dim3(256), 0, st, s, l.item0);
         else hipLaunchKernelGGL((k_freq_bwd<16, 4, false>), grid, dim3(256), 0, st, s, l.item0);
         break;
-      case 32: hipLaunchKernelGGL((k_freq_bwd<32, 8, false>), grid, dim3(256), 0, st, s, l.item0); break;
+      case 32:
+        if (few_frames) hipLaunchKernelGGL((k_freq_bwd<32, 8, true>), grid, dim3(256), 0, st, s, l.item0);
+        else hipLaunchKernelGGL((k_freq_bwd<32, 8, false>), grid, dim3(256), 0, st, s, l.item0);
+        break;
       default: hipLaunchKernelGGL((k_freq_bwd<64, 16, false>), grid, dim3(256), 0, st, s, l.item0); break;
     }
     const hipError_t e = hipGetLastError();
