@@ -472,26 +472,37 @@ __device__ inline void load24(const uint16_t* row, int t0, float v[24]) {
 
 __global__ __launch_bounds__(256) void k_out_fwd(const uint16_t* __restrict__ xct, int T, const float* __restrict__ wo,
                                                  const float* __restrict__ bias, float* __restrict__ y) {
+  // 64 threads x 8 samples per block; the four waves take 32 channels each and their sums
+  // are combined through LDS in a fixed order
+  __shared__ float red[4][64 * 8];
   const int b = blockIdx.y;
-  const int t0 = 8 * (blockIdx.x * 256 + threadIdx.x);
-  if (t0 >= T) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t0 = 8 * (blockIdx.x * 64 + lane);
   const int64_t row_len = T + 2 * kDecPad;
   float acc[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) acc[i] = bias[0];
-  for (int ci = 0; ci < kDecC; ++ci) {
-    float v[24];
-    load24(xct + (int64_t(b) * kDecC + ci) * row_len, t0, v);
+  for (int i = 0; i < 8; ++i) acc[i] = 0.f;
+  if (t0 < T) {
+    for (int ci = wave * (kDecC / 4); ci < (wave + 1) * (kDecC / 4); ++ci) {
+      float v[24];
+      load24(xct + (int64_t(b) * kDecC + ci) * row_len, t0, v);
 #pragma unroll
-    for (int k = 0; k < kDecK; ++k) {
-      const float wk = wo[ci * kDecK + k];
+      for (int k = 0; k < kDecK; ++k) {
+        const float wk = wo[ci * kDecK + k];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) acc[i] += wk * v[i + k + 4];
+        for (int i = 0; i < 8; ++i) acc[i] += wk * v[i + k + 4];
+      }
     }
   }
-  float* yo = y + int64_t(b) * T + t0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) yo[i] = acc[i];
+  for (int i = 0; i < 8; ++i) red[wave][lane * 8 + i] = acc[i];
+  __syncthreads();
+  if (wave == 0 && t0 < T) {
+    float* yo = y + int64_t(b) * T + t0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      yo[i] = bias[0] + ((red[0][lane * 8 + i] + red[1][lane * 8 + i]) + (red[2][lane * 8 + i] + red[3][lane * 8 + i]));
+  }
 }
 
 // dz of the last hidden layer: da[u, ci] = sum_k w[ci][k] dy[u - k + 4], masked.
@@ -564,12 +575,21 @@ __global__ __launch_bounds__(256) void k_out_wgrad(const float* __restrict__ dy,
     for (int k = 0; k < kDecK; ++k) part[(int64_t(chunk) * kDecC + ci) * kDecK + k] = acc[k];
 }
 
-__global__ void k_out_wgrad_reduce(const float* __restrict__ part, int n_chunks, float* __restrict__ grad) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kDecC * kDecK) return;
+// One block per output weight: the chunk partials are summed by 256 threads (fixed
+// strides) and a fixed-order tree.
+__global__ __launch_bounds__(256) void k_out_wgrad_reduce(const float* __restrict__ part, int n_chunks,
+                                                          float* __restrict__ grad) {
+  __shared__ float red[256];
+  const int i = blockIdx.x;
   float acc = 0.f;
-  for (int c = 0; c < n_chunks; ++c) acc += part[int64_t(c) * kDecC * kDecK + i];
-  grad[i] = acc;
+  for (int c = threadIdx.x; c < n_chunks; c += 256) acc += part[int64_t(c) * kDecC * kDecK + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (static_cast<int>(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad[i] = red[0];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -682,7 +702,7 @@ hipError_t run_dec_conv_fwd(int s, const uint16_t* x_tc, int cip, int t_in, int 
 
 hipError_t run_dec_out_fwd(const uint16_t* x_ct, int T, int batch, const float* wout, const float* bias, float* y,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_out_fwd, dim3(blocks_for(T / 8, 256), batch), dim3(256), 0, st, x_ct, T, wout, bias, y);
+  hipLaunchKernelGGL(k_out_fwd, dim3(blocks_for(T / 8, 64), batch), dim3(256), 0, st, x_ct, T, wout, bias, y);
   return hipGetLastError();
 }
 
@@ -702,8 +722,7 @@ hipError_t run_dec_out_bwd(const float* dy, int T, int batch, const float* wout,
   const int n_chunks = cpb * batch;
   hipLaunchKernelGGL(k_out_wgrad, dim3(n_chunks, kDecC / 16), dim3(256), 0, st, dy, T, a_ct, cpb, part);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_out_wgrad_reduce, dim3(blocks_for(kDecC * kDecK, 256)), dim3(256), 0, st, part, n_chunks,
-                     grad_w);
+  hipLaunchKernelGGL(k_out_wgrad_reduce, dim3(kDecC * kDecK), dim3(256), 0, st, part, n_chunks, grad_w);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // output bias: partial sums over 8192-sample rows of dy, then their sum (partials after the
   // weight partials in `part`)
