@@ -107,12 +107,21 @@ JTFS_HD inline void stockham_compute(const c32* col, int log2n, int log2p, int t
 #pragma unroll
     for (int r = 0; r < R; ++r) v[b * R + r] = col[i + r * stride];
     if (log2p > 0) {
+      // twiddles w^r, w = exp(-+2 pi i k / (R p)): the powers w^(2^q) come from the table
+      // (LR scattered loads instead of R - 1), the others are products of them in
+      // binary order (at most LR - 1 complex multiplications each)
+      c32 w[R];
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        c32 w = tw[(r * k) << tshift];
-        if (DIR > 0) w.y = -w.y;
-        v[b * R + r] = cmul(v[b * R + r], w);
+      for (int q = 0; q < LR; ++q) {
+        c32 t = tw[(k << q) << tshift];
+        if (DIR > 0) t.y = -t.y;
+        w[1 << q] = t;
       }
+#pragma unroll
+      for (int r = 3; r < R; ++r)
+        if (r & (r - 1)) w[r] = cmul(w[r & (r - 1)], w[r & -r]);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], w[r]);
     }
     dft_reg<LR, DIR>(v + b * R);
   }

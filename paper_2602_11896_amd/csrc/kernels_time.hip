@@ -30,17 +30,25 @@ namespace {
 __device__ inline float cabs(c32 z) { return sqrtf(z.x * z.x + z.y * z.y); }
 
 // Fourier subsampling by 2^shift of (src . band) onto an n-point grid, output bin q.
+// The plan guarantees that a band is not empty and spans at most two aliased blocks
+// (1 <= len <= 2 n), so both are read without a loop, at indices clamped into the band and with an absent second
+// term masked by value: the loads of several bins can be in flight together.
 __device__ inline c32 fold_gather(const c32* src, const Band& b, const float* vals, int n, int shift, int q) {
   const int nmask = n - 1;
-  int d = (q - (b.lo & nmask)) & nmask;
+  const int d0 = (q - (b.lo & nmask)) & nmask;
   c32 acc{0.f, 0.f};
-  for (; d < b.len; d += n) {
-    int m = b.lo + d;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int d = d0 + k * n;
+    const bool in = d < b.len;
+    const int dc = in ? d : 0;
+    int m = b.lo + dc;
     if (m >= b.L) m -= b.L;
-    const float h = vals[b.off + d];
+    const float h = vals[b.off + dc];
     const c32 v = src[m];
-    acc.x += v.x * h;
-    acc.y += v.y * h;
+    const float hm = in ? h : 0.f;
+    acc.x += v.x * hm;
+    acc.y += v.y * hm;
   }
   const float sc = ldexpf(1.0f, -shift);
   return c32{acc.x * sc, acc.y * sc};
@@ -73,7 +81,7 @@ struct Ops;
 template <>
 struct Ops<ST_XHAT> {
   static constexpr int DIR = -1;
-  __device__ static c32 load(const DevSig& s, const RowJob&, int idx) {
+  __device__ static c32 load(const DevSig& s, const RowJob&, const Band&, int idx) {
     const int j = idx - s.pad_left;
     return c32{(j >= 0 && j < s.N) ? s.x[j] : 0.f, 0.f};
   }
@@ -83,8 +91,8 @@ struct Ops<ST_XHAT> {
 template <>
 struct Ops<ST_L1Z> {
   static constexpr int DIR = +1;
-  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
-    return fold_gather(s.Xh, s.bands[j.band], s.bandvals, j.n, j.shift, idx);
+  __device__ static c32 load(const DevSig& s, const RowJob& j, const Band& b, int idx) {
+    return fold_gather(s.Xh, b, s.bandvals, j.n, j.shift, idx);
   }
   __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.Z1[j.dst + idx] = v; }
 };
@@ -92,7 +100,7 @@ struct Ops<ST_L1Z> {
 template <>
 struct Ops<ST_L1UH> {
   static constexpr int DIR = -1;
-  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
+  __device__ static c32 load(const DevSig& s, const RowJob& j, const Band&, int idx) {
     return c32{cabs(s.Z1[j.src + idx]), 0.f};
   }
   __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.U1h[j.dst + idx] = v; }
@@ -101,8 +109,8 @@ struct Ops<ST_L1UH> {
 template <>
 struct Ops<ST_L2Y> {
   static constexpr int DIR = +1;
-  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
-    return fold_gather(s.U1h + j.src, s.bands[j.band], s.bandvals, j.n, j.shift, idx);
+  __device__ static c32 load(const DevSig& s, const RowJob& j, const Band& b, int idx) {
+    return fold_gather(s.U1h + j.src, b, s.bandvals, j.n, j.shift, idx);
   }
   __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.Y2[j.dst + idx] = v; }
 };
@@ -110,14 +118,14 @@ struct Ops<ST_L2Y> {
 template <>
 struct Ops<ST_BYH> {
   static constexpr int DIR = -1;
-  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) { return s.dYpart[j.src + idx]; }
+  __device__ static c32 load(const DevSig& s, const RowJob& j, const Band&, int idx) { return s.dYpart[j.src + idx]; }
   __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.dYh[j.dst + idx] = v; }
 };
 
 template <>
 struct Ops<ST_BU> {
   static constexpr int DIR = +1;
-  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
+  __device__ static c32 load(const DevSig& s, const RowJob& j, const Band&, int idx) {
     return term_gather(s, s.dYh, j.t0, idx);
   }
   __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.dU1[j.dst + idx] = v.x; }
@@ -126,11 +134,14 @@ struct Ops<ST_BU> {
 template <>
 struct Ops<ST_BZH> {
   static constexpr int DIR = -1;
-  __device__ static c32 load(const DevSig& s, const RowJob& j, int idx) {
+  __device__ static c32 load(const DevSig& s, const RowJob& j, const Band&, int idx) {
+    // u times the phase z / |z| (rsq, within 1 ulp; subgradient 0 where |z| vanishes,
+    // below 1.1e-19 the square underflows anyway)
     const float u = s.dU1[j.src + idx];
     const c32 z = s.Z1[j.aux + idx];
-    const float a = cabs(z);
-    return a > 0.f ? c32{u * (z.x / a), u * (z.y / a)} : c32{0.f, 0.f};
+    const float m2 = z.x * z.x + z.y * z.y;
+    const float r = m2 >= 1.17549435e-38f ? u * __builtin_amdgcn_rsqf(m2) : 0.f;
+    return c32{z.x * r, z.y * r};
   }
   __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.dZh[j.dst + idx] = v; }
 };
@@ -139,7 +150,7 @@ template <>
 struct Ops<ST_BX> {
   static constexpr int DIR = +1;
   // the gather itself runs beforehand in k_bx_gather, over the whole spectrum at once
-  __device__ static c32 load(const DevSig& s, const RowJob&, int idx) { return s.dXh[idx]; }
+  __device__ static c32 load(const DevSig& s, const RowJob&, const Band&, int idx) { return s.dXh[idx]; }
   __device__ static void store(const DevSig& s, const RowJob&, int idx, c32 v) {
     const int k = idx - s.pad_left;
     if (k >= 0 && k < s.N) s.dx[k] = v.x;
@@ -185,27 +196,42 @@ __device__ void fft_tile(c32* lds, int log2n, const c32* tw, int log2tw) {
   }
 }
 
-// One workgroup per task: `count` rows of one length, all in one 4096-element tile.
+// One workgroup per task: `count` rows of one length, all in one 4096-element tile. The
+// rows' jobs and bands are staged in LDS first (count <= 4096 / 16), so that each element
+// reads only its data from global memory.
+constexpr int kMaxTileRows = 256;
+
 template <int ST>
-__device__ void rows_body(const DevSig& s, c32* lds, int task) {
+__device__ void rows_body(const DevSig& s, c32* lds, RowJob* tj, Band* tb, int task) {
   using O = Ops<ST>;
   const RowTask tk = s.tasks[task];
   const int log2n = tk.log2n;
   const int n = 1 << log2n;
-#pragma unroll 1
+  const int count = min(tk.count, kMaxTileRows);
+  for (int r = threadIdx.x; r < count; r += 256) {
+    const RowJob j = s.jobs[tk.job0 + r];
+    tj[r] = j;
+    tb[r] = j.band >= 0 ? s.bands[j.band] : Band{0, 0, 0, 0, 0};
+  }
+  __syncthreads();
+#pragma unroll 4
   for (int i = 0; i < 16; ++i) {
+    // (elements past the last row load from it and are zeroed by value: no branch, so
+    // the loads of consecutive elements can be in flight together)
     const int e = threadIdx.x + 256 * i;
     const int row = e >> log2n;
-    lds[e] = row < tk.count ? O::load(s, s.jobs[tk.job0 + row], e & (n - 1)) : c32{0.f, 0.f};
+    const int rc = min(row, count - 1);
+    const c32 v = O::load(s, tj[rc], tb[rc], e & (n - 1));
+    lds[e] = row < count ? v : c32{0.f, 0.f};
   }
   __syncthreads();
   fft_tile<O::DIR>(lds, log2n, s.tw, s.log2_Npad);
   const float sc = O::DIR > 0 ? 1.0f / n : 1.0f;
-#pragma unroll 1
+#pragma unroll 4
   for (int i = 0; i < 16; ++i) {
     const int e = threadIdx.x + 256 * i;
     const int row = e >> log2n;
-    if (row < tk.count) O::store(s, s.jobs[tk.job0 + row], e & (n - 1), cscale(lds[e], sc));
+    if (row < count) O::store(s, tj[row], e & (n - 1), cscale(lds[e], sc));
   }
 }
 
@@ -218,11 +244,13 @@ __device__ void split1_body(const DevSig& s, c32* lds, int task) {
   const int log2n = tk.log2n;
   const SplitGeom g = split_geom(log2n, tk.log2A);
   const RowJob job = s.jobs[tk.job];
+  const Band band = job.band >= 0 ? s.bands[job.band] : Band{0, 0, 0, 0, 0};
   const int n1_0 = tk.blk << g.log2C1;
+#pragma unroll 4
   for (int i = 0; i < 16; ++i) {
     int idx, slot;
     split_p1_load(g, n1_0, threadIdx.x + 256 * i, idx, slot);
-    lds[slot] = O::load(s, job, idx);
+    lds[slot] = O::load(s, job, band, idx);
   }
   __syncthreads();
   fft_tile<O::DIR>(lds, g.log2B, s.tw, s.log2_Npad);
@@ -242,8 +270,10 @@ __device__ void split1_body(const DevSig& s, c32* lds, int task) {
 template <int ST>
 __global__ __launch_bounds__(256) void k_fft_stage1(DevSig s, int task0, int ntask, int split0) {
   __shared__ c32 lds[4096];
+  __shared__ RowJob tj[kMaxTileRows];
+  __shared__ Band tb[kMaxTileRows];
   if (static_cast<int>(blockIdx.x) < ntask)
-    rows_body<ST>(s, lds, task0 + blockIdx.x);
+    rows_body<ST>(s, lds, tj, tb, task0 + blockIdx.x);
   else
     split1_body<ST>(s, lds, split0 + blockIdx.x - ntask);
 }

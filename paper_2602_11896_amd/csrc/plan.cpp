@@ -790,6 +790,18 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     p.jobs.push_back(job(p.z1_off[n1], int64_t(n1) * p.nf_pad, 0, p.band_phiT[k1], Np >> k1, p.Lf, p.log2T - k1));
   }
 
+  // The Fourier-subsampling gathers read, per output bin, one or two aliased blocks of a
+  // non-empty band (the subsampling rule keeps a filter's band within two periods of the
+  // coarser grid).
+  for (const RowJob& j : p.jobs) {
+    if (j.band < 0 || j.n <= 0) continue;
+    const int32_t len = p.bands[static_cast<size_t>(j.band)].len;
+    if (len < 1 || len > 2 * j.n) {
+      err = "a filter band is empty or spans more than two periods of its subsampled grid";
+      return JTFS_ERR_UNSUPPORTED;
+    }
+  }
+
   // ---- workspace layout (bytes, 256-aligned regions)
   size_t o = 0;
   auto take = [&](size_t bytes) {
