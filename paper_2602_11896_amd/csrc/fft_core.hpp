@@ -182,6 +182,31 @@ JTFS_HD inline void split_p1_store(const SplitGeom& g, int n1_0, int e, int& slo
   twexp = (n1_0 + c) * k2;
 }
 
+// Pass-1 twiddles of thread t, w_n^(n1 k2) for its 16 elements e = t + 256 i: since
+// C1 <= 256 (B >= 16), they share the column n1 = n1_0 + (t mod C1) and take
+// k2 = k2_0 + i s with s = 256 / C1. Five table reads, w^(n1 k2_0) and w^(n1 s 2^q),
+// q < 4, and the rest as products in binary order (at most four complex
+// multiplications each) instead of sixteen scattered reads. tw: exp(-2 pi i q / 2^log2tw);
+// DIR > 0 conjugates.
+template <int DIR>
+JTFS_HD inline void split_p1_twiddles(const SplitGeom& g, int n1_0, int t, const c32* tw, int tshift, c32* w16) {
+  const int c = t & ((1 << g.log2C1) - 1), k2_0 = t >> g.log2C1;
+  const int n1 = n1_0 + c;
+  const int step = 256 >> g.log2C1;
+  c32 p[4];
+  for (int q = 0; q < 4; ++q) {
+    p[q] = tw[((n1 * step) << q) << tshift];
+    if (DIR > 0) p[q].y = -p[q].y;
+  }
+  w16[0] = tw[(n1 * k2_0) << tshift];
+  if (DIR > 0) w16[0].y = -w16[0].y;
+  for (int i = 1; i < 16; ++i) {
+    const int low = i & -i;
+    const int q = low == 1 ? 0 : low == 2 ? 1 : low == 4 ? 2 : 3;
+    w16[i] = cmul(w16[i - low], p[q]);
+  }
+}
+
 // pass 2 load: scratch index of element e (row base k2_0); the tile slot is e itself
 JTFS_HD inline int split_p2_load(const SplitGeom& g, int k2_0, int e) {
   const int c = e >> g.log2A, n1 = e & ((1 << g.log2A) - 1);

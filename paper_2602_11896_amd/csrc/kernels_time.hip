@@ -256,12 +256,13 @@ __device__ void split1_body(const DevSig& s, c32* lds, int task) {
   fft_tile<O::DIR>(lds, g.log2B, s.tw, s.log2_Npad);
   c32* scr = s.scr + tk.scr;
   const int tshift = s.log2_Npad - log2n;
+  c32 w16[16];
+  split_p1_twiddles<O::DIR>(g, n1_0, threadIdx.x, s.tw, tshift, w16);
+#pragma unroll
   for (int i = 0; i < 16; ++i) {
     int slot, sidx, te;
     split_p1_store(g, n1_0, threadIdx.x + 256 * i, slot, sidx, te);
-    c32 w = s.tw[te << tshift];
-    if (O::DIR > 0) w.y = -w.y;
-    scr[sidx] = cmul(lds[slot], w);
+    scr[sidx] = cmul(lds[slot], w16[i]);
   }
 }
 

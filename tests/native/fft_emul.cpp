@@ -4,6 +4,7 @@
 // and the two-pass split used for longer transforms.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "../../paper_2602_11896_amd/csrc/fft_core.hpp"
@@ -112,11 +113,22 @@ static double check_split(int log2n, int log2A, int dir, const std::vector<c32>&
   for (int n1_0 = 0; n1_0 < A; n1_0 += 1 << g.log2C1) {
     for (int e = 0; e < 4096; ++e) { int idx, slot; split_p1_load(g, n1_0, e, idx, slot); lds[slot] = x[idx]; }
     if (dir < 0) tile_fft<-1>(lds, g.log2B, tw, log2tw); else tile_fft<+1>(lds, g.log2B, tw, log2tw);
-    for (int e = 0; e < 4096; ++e) {
-      int slot, sidx, te; split_p1_store(g, n1_0, e, slot, sidx, te);
-      c32 w = tw[(size_t)te << (log2tw - log2n)];
-      if (dir > 0) w.y = -w.y;
-      scr[sidx] = cmul(lds[slot], w);
+    // per thread t: its 16 elements e = t + 256 i take the composed twiddles of
+    // split_p1_twiddles, whose exponents must be the n1 k2 of split_p1_store
+    for (int t = 0; t < 256; ++t) {
+      c32 w16[16];
+      if (dir < 0) split_p1_twiddles<-1>(g, n1_0, t, tw.data(), log2tw - log2n, w16);
+      else split_p1_twiddles<+1>(g, n1_0, t, tw.data(), log2tw - log2n, w16);
+      for (int i = 0; i < 16; ++i) {
+        int slot, sidx, te; split_p1_store(g, n1_0, t + 256 * i, slot, sidx, te);
+        c32 wr = tw[(size_t)te << (log2tw - log2n)];
+        if (dir > 0) wr.y = -wr.y;
+        if (std::fabs(wr.x - w16[i].x) > 1e-6f || std::fabs(wr.y - w16[i].y) > 1e-6f) {
+          std::printf("twiddle mismatch log2n=%d log2A=%d t=%d i=%d\n", log2n, log2A, t, i);
+          std::exit(1);
+        }
+        scr[sidx] = cmul(lds[slot], w16[i]);
+      }
     }
   }
   for (int k2_0 = 0; k2_0 < B; k2_0 += 1 << g.log2C2) {
