@@ -40,9 +40,8 @@ struct SigTables {
   const jtfs::BwdItem* bwd_items;
   const jtfs::RowJob* jobs;
   const jtfs::RowTask* tasks;
-  const jtfs::GatherTerm* terms;
   const int32_t* segs;
-  const int32_t* segterms;
+  const jtfs::SegTerm* segterms;
   const jtfs::SplitTask* stasks;
   const int64_t* s_off;
   const int32_t* band_psi1;   // per first-order filter: its band (level 0, N_pad grid)
@@ -132,7 +131,6 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     append_bytes(buf, o, sp.fwd_items);
     append_bytes(buf, o, sp.bwd_items);
     append_bytes(buf, o, sp.jobs);
-    append_bytes(buf, o, sp.terms);
     append_bytes(buf, o, p->block_off[s]);
     append_bytes(buf, o, sp.tasks);
     append_bytes(buf, o, sp.segs);
@@ -161,13 +159,12 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     t.fwd_items = reinterpret_cast<const jtfs::FwdItem*>(b + o[8]);
     t.bwd_items = reinterpret_cast<const jtfs::BwdItem*>(b + o[9]);
     t.jobs = reinterpret_cast<const jtfs::RowJob*>(b + o[10]);
-    t.terms = reinterpret_cast<const jtfs::GatherTerm*>(b + o[11]);
-    t.s_off = reinterpret_cast<const int64_t*>(b + o[12]);
-    t.tasks = reinterpret_cast<const jtfs::RowTask*>(b + o[13]);
-    t.segs = reinterpret_cast<const int32_t*>(b + o[14]);
-    t.segterms = reinterpret_cast<const int32_t*>(b + o[15]);
-    t.stasks = reinterpret_cast<const jtfs::SplitTask*>(b + o[16]);
-    t.band_psi1 = reinterpret_cast<const int32_t*>(b + o[17]);
+    t.s_off = reinterpret_cast<const int64_t*>(b + o[11]);
+    t.tasks = reinterpret_cast<const jtfs::RowTask*>(b + o[12]);
+    t.segs = reinterpret_cast<const int32_t*>(b + o[13]);
+    t.segterms = reinterpret_cast<const jtfs::SegTerm*>(b + o[14]);
+    t.stasks = reinterpret_cast<const jtfs::SplitTask*>(b + o[15]);
+    t.band_psi1 = reinterpret_cast<const int32_t*>(b + o[16]);
     a.sig.push_back(t);
   }
   if (p->sig.size() > 1) {
@@ -240,7 +237,6 @@ jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void
   d.bwd_items = t.bwd_items;
   d.jobs = t.jobs;
   d.tasks = t.tasks;
-  d.terms = t.terms;
   d.segs = t.segs;
   d.segterms = t.segterms;
   d.stasks = t.stasks;

@@ -21,9 +21,8 @@ struct DevSig {
   const BwdItem* bwd_items;
   const RowJob* jobs;
   const RowTask* tasks;
-  const GatherTerm* terms;
   const int32_t* segs;      // per gather segment: first index into segterms, count
-  const int32_t* segterms;
+  const SegTerm* segterms;
   const SplitTask* stasks;  // two-pass transform workgroups
   const int64_t* s_off;     // output offset of block (group gi, filter g) at gi*n_g + g;
                             // order-1 blocks at n_groups*n_g + (index in the real list)

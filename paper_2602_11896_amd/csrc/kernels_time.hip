@@ -61,12 +61,11 @@ __device__ inline c32 term_gather(const DevSig& s, const c32* base, int seg0, in
   const int sg = seg0 + (m >> 9);
   const int first = s.segs[2 * sg], count = s.segs[2 * sg + 1];
   for (int i = 0; i < count; ++i) {
-    const GatherTerm g = s.terms[s.segterms[first + i]];
-    const Band b = s.bands[g.band];
-    int d = m - b.lo;
-    if (d < 0) d += b.L;
-    if (d < b.len) {
-      const float h = s.bandvals[b.off + d];
+    const SegTerm g = s.segterms[first + i];
+    int d = m - g.lo;
+    if (d < 0) d += g.L;
+    if (d < g.len) {
+      const float h = s.bandvals[g.off + d];
       const c32 v = base[g.src + (m & (g.src_len - 1))];
       acc.x += v.x * h;
       acc.y += v.y * h;

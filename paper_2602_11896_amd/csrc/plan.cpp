@@ -776,7 +776,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
         const Band& bd = p.bands[p.terms[t].band];
         const int64_t L = bd.L;
         const bool meets = L != j.n || bd.len >= L || ((a - bd.lo) % L + L) % L < bd.len || ((bd.lo - a) % L + L) % L < b - a;
-        if (meets) p.segterms.push_back(t);
+        if (meets) p.segterms.push_back(SegTerm{p.terms[t].src, bd.off, bd.lo, bd.len, bd.L, p.terms[t].src_len});
       }
       p.segs.push_back(first);
       p.segs.push_back(static_cast<int32_t>(p.segterms.size()) - first);

@@ -99,7 +99,9 @@ struct SigPlan {
   std::vector<GatherTerm> terms;
   // Adjoint gathers: per 512-bin segment of a gather row, the terms whose band meets it
   // (pairs: first index into segterms, count); the row's RowJob.t0 is its first segment.
-  std::vector<int32_t> segs, segterms;
+  // `terms` is only the planning list the segments are cut from.
+  std::vector<int32_t> segs;
+  std::vector<SegTerm> segterms;
   std::vector<Launch> launches[ST_COUNT];     // two-pass (n > 4096) launches
   std::vector<RowTask> tasks;                  // single-pass workgroup tasks of every stage
   int32_t task0[ST_COUNT] = {0}, ntask[ST_COUNT] = {0};

@@ -52,6 +52,15 @@ struct GatherTerm {
   int32_t src_len;
 };
 
+// One term of an adjoint-gather segment, self-contained (a gather reads it in one step):
+// the source row and its length, and the band's placement (first bin lo on a grid of L
+// bins, len values at offset off of the band values).
+struct SegTerm {
+  int64_t src;
+  int64_t off;
+  int32_t lo, len, L, src_len;
+};
+
 // A second-order group (one n2 with K >= 1 rows), frequential stage bookkeeping.
 struct FreqGroup {
   int64_t y2;       // complex offset of the K x L2 stack in the Y2 region
