@@ -8,8 +8,9 @@
 // takes the R-point DFT and writes output r to ((i - k)*R + k) + r*p. After the last
 // pass the column holds its DFT in natural order (self-sorting, no bit reversal).
 //
-// The per-thread steps are __host__ __device__ so that the same code can be driven by
-// a sequential host emulation of the barrier-separated phases.
+// Tile element e lives at LDS slot tile_slot(e) (below), a bank swizzle; every access
+// to the tile goes through it. The per-thread steps are __host__ __device__ so that the
+// same code can be driven by a sequential host emulation of the barrier-separated phases.
 #pragma once
 #include <cstdint>
 
@@ -40,6 +41,18 @@ constexpr float kSin16[16] = {0.0f, 0.38268343236508977f, 0.70710678118654752f, 
                               1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
                               0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
                               -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f};
+
+// LDS slot of tile element e (0 <= e < 4096): bits 0-3 of e are XORed with bits 4-7 and
+// 8-11, bit 4 with bit 8. The accesses of a wave move along strides that are powers of
+// two (1 in the loads and the reads of long columns, 16 in the first pass's writes, the
+// row length across the columns of short transforms, the column length in the
+// transposes of the two-pass split); in the natural layout most of those strides put
+// many lanes on one bank, and the swizzle spreads each of them over all the banks. It is
+// a bijection (each changed bit takes only higher bits) and linear over GF(2):
+// tile_slot(a + b) = tile_slot(a) ^ tile_slot(b) when a and b have no set bit in common,
+// which lets a thread swizzle its base once and add offsets shared by the workgroup
+// with a single XOR.
+JTFS_HD constexpr int tile_slot(int e) { return e ^ ((e >> 4) & 31) ^ ((e >> 8) & 15); }
 
 constexpr int bitrev(int v, int bits) {
   int r = 0;
@@ -89,12 +102,14 @@ JTFS_HD inline int fft_radices(int log2n, int* lr) {
   return np;
 }
 
-// Read phase of one radix-2^LR pass for thread t (of tpf threads on this column): loads,
-// twiddles and transforms the thread's 16 / R butterflies into v[0..16). `tw` holds
-// exp(-2 pi i q / 2^log2tw); log2p is log2 of the span p.
+// Read phase of one radix-2^LR pass for thread t (of tpf threads on the column whose
+// first element is tile element cbase): loads, twiddles and transforms the thread's
+// 16 / R butterflies into v[0..16). `tw` holds exp(-2 pi i q / 2^log2tw); log2p is log2
+// of the span p. cbase (a multiple of n), i < n / R and r * (n / R) share no bits, so
+// the slot of cbase + i + r * (n / R) is the XOR of their slots.
 template <int DIR, int LR>
-JTFS_HD inline void stockham_compute(const c32* col, int log2n, int log2p, int t, int tpf, const c32* tw,
-                                     int log2tw, c32* v) {
+JTFS_HD inline void stockham_compute(const c32* tile, int cbase, int log2n, int log2p, int t, int tpf,
+                                     const c32* tw, int log2tw, c32* v) {
   constexpr int R = 1 << LR;
   constexpr int NB = 16 >> LR;
   const int stride = (1 << log2n) >> LR;
@@ -104,8 +119,9 @@ JTFS_HD inline void stockham_compute(const c32* col, int log2n, int log2p, int t
   for (int b = 0; b < NB; ++b) {
     const int i = t + tpf * b;
     const int k = i & pmask;
+    const int sb = tile_slot(cbase + i);
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[b * R + r] = col[i + r * stride];
+    for (int r = 0; r < R; ++r) v[b * R + r] = tile[sb ^ tile_slot(r * stride)];
     if (log2p > 0) {
       // twiddles w^r, w = exp(-+2 pi i k / (R p)): the powers w^(2^q) come from the table
       // (LR scattered loads instead of R - 1), the others are products of them in
@@ -127,9 +143,11 @@ JTFS_HD inline void stockham_compute(const c32* col, int log2n, int log2p, int t
   }
 }
 
-// Write phase of the same pass: stores the 16 results of thread t.
+// Write phase of the same pass: stores the 16 results of thread t. The output index
+// j + r * p has j = (i - k) * R + k with k < p and (i - k) * R a multiple of p * R, so
+// j, r * p and cbase share no bits either.
 template <int LR>
-JTFS_HD inline void stockham_store(c32* col, int log2p, int t, int tpf, const c32* v) {
+JTFS_HD inline void stockham_store(c32* tile, int cbase, int log2p, int t, int tpf, const c32* v) {
   constexpr int R = 1 << LR;
   constexpr int NB = 16 >> LR;
   const int p = 1 << log2p;
@@ -137,9 +155,9 @@ JTFS_HD inline void stockham_store(c32* col, int log2p, int t, int tpf, const c3
   for (int b = 0; b < NB; ++b) {
     const int i = t + tpf * b;
     const int k = i & (p - 1);
-    const int j = ((i - k) << LR) + k;
+    const int sb = tile_slot(cbase + ((i - k) << LR) + k);
 #pragma unroll
-    for (int r = 0; r < R; ++r) col[j + r * p] = v[b * R + r];
+    for (int r = 0; r < R; ++r) tile[sb ^ tile_slot(r * p)] = v[b * R + r];
   }
 }
 
@@ -167,14 +185,15 @@ JTFS_HD inline SplitGeom split_geom(int log2n, int log2A) {
 }
 JTFS_HD inline SplitGeom split_geom(int log2n) { return split_geom(log2n, log2n / 2); }
 
-// pass 1 load: input index and tile slot of element e (column base n1_0)
+// pass 1 load: input index and tile element ("slot", stored at tile_slot(slot)) of
+// element e (column base n1_0)
 JTFS_HD inline void split_p1_load(const SplitGeom& g, int n1_0, int e, int& idx, int& slot) {
   const int c = e & ((1 << g.log2C1) - 1), n2 = e >> g.log2C1;
   idx = (n1_0 + c) + (n2 << g.log2A);
   slot = (c << g.log2B) + n2;
 }
 
-// pass 1 store: tile slot, scratch index and twiddle exponent n1*k2 of element e
+// pass 1 store: tile element, scratch index and twiddle exponent n1*k2 of element e
 JTFS_HD inline void split_p1_store(const SplitGeom& g, int n1_0, int e, int& slot, int& sidx, int& twexp) {
   const int c = e & ((1 << g.log2C1) - 1), k2 = e >> g.log2C1;
   slot = (c << g.log2B) + k2;
@@ -207,13 +226,13 @@ JTFS_HD inline void split_p1_twiddles(const SplitGeom& g, int n1_0, int t, const
   }
 }
 
-// pass 2 load: scratch index of element e (row base k2_0); the tile slot is e itself
+// pass 2 load: scratch index of element e (row base k2_0); the tile element is e itself
 JTFS_HD inline int split_p2_load(const SplitGeom& g, int k2_0, int e) {
   const int c = e >> g.log2A, n1 = e & ((1 << g.log2A) - 1);
   return ((k2_0 + c) << g.log2A) + n1;
 }
 
-// pass 2 store: tile slot and output index of element e
+// pass 2 store: tile element and output index of element e
 JTFS_HD inline void split_p2_store(const SplitGeom& g, int k2_0, int e, int& slot, int& oidx) {
   const int c = e & ((1 << g.log2C2) - 1), k1 = e >> g.log2C2;
   slot = (c << g.log2A) + k1;

@@ -167,29 +167,31 @@ __global__ __launch_bounds__(256) void k_bx_gather(DevSig s, int job) {
 
 // One radix-2^LR pass over the tile (two barriers: all reads before any write).
 template <int DIR, int LR>
-__device__ inline void tile_pass(c32* col, int log2n, int log2p, int t, int tpf, const c32* tw, int log2tw) {
+__device__ inline void tile_pass(c32* tile, int cbase, int log2n, int log2p, int t, int tpf, const c32* tw,
+                                 int log2tw) {
   c32 v[16];
-  stockham_compute<DIR, LR>(col, log2n, log2p, t, tpf, tw, log2tw, v);
+  stockham_compute<DIR, LR>(tile, cbase, log2n, log2p, t, tpf, tw, log2tw, v);
   __syncthreads();
-  stockham_store<LR>(col, log2p, t, tpf, v);
+  stockham_store<LR>(tile, cbase, log2p, t, tpf, v);
   __syncthreads();
 }
 
-// In-place FFT of the 4096 / n columns of the tile (natural order in and out).
+// In-place FFT of the 4096 / n columns of the tile (natural order in and out; element
+// e at LDS slot tile_slot(e)).
 template <int DIR>
 __device__ void fft_tile(c32* lds, int log2n, const c32* tw, int log2tw) {
   const int tpf = 1 << (log2n - 4);
   const int t = threadIdx.x & (tpf - 1);
-  c32* col = lds + (threadIdx.x >> (log2n - 4)) * (1 << log2n);
+  const int cbase = (threadIdx.x >> (log2n - 4)) << log2n;
   int lr[8];
   const int np = fft_radices(log2n, lr);
   int log2p = 0;
   for (int p = 0; p < np; ++p) {
     switch (lr[p]) {
-      case 1: tile_pass<DIR, 1>(col, log2n, log2p, t, tpf, tw, log2tw); break;
-      case 2: tile_pass<DIR, 2>(col, log2n, log2p, t, tpf, tw, log2tw); break;
-      case 3: tile_pass<DIR, 3>(col, log2n, log2p, t, tpf, tw, log2tw); break;
-      default: tile_pass<DIR, 4>(col, log2n, log2p, t, tpf, tw, log2tw); break;
+      case 1: tile_pass<DIR, 1>(lds, cbase, log2n, log2p, t, tpf, tw, log2tw); break;
+      case 2: tile_pass<DIR, 2>(lds, cbase, log2n, log2p, t, tpf, tw, log2tw); break;
+      case 3: tile_pass<DIR, 3>(lds, cbase, log2n, log2p, t, tpf, tw, log2tw); break;
+      default: tile_pass<DIR, 4>(lds, cbase, log2n, log2p, t, tpf, tw, log2tw); break;
     }
     log2p += lr[p];
   }
@@ -221,7 +223,7 @@ __device__ void rows_body(const DevSig& s, c32* lds, RowJob* tj, Band* tb, int t
     const int row = e >> log2n;
     const int rc = min(row, count - 1);
     const c32 v = O::load(s, tj[rc], tb[rc], e & (n - 1));
-    lds[e] = row < count ? v : c32{0.f, 0.f};
+    lds[tile_slot(e)] = row < count ? v : c32{0.f, 0.f};
   }
   __syncthreads();
   fft_tile<O::DIR>(lds, log2n, s.tw, s.log2_Npad);
@@ -230,7 +232,7 @@ __device__ void rows_body(const DevSig& s, c32* lds, RowJob* tj, Band* tb, int t
   for (int i = 0; i < 16; ++i) {
     const int e = threadIdx.x + 256 * i;
     const int row = e >> log2n;
-    if (row < count) O::store(s, tj[row], e & (n - 1), cscale(lds[e], sc));
+    if (row < count) O::store(s, tj[row], e & (n - 1), cscale(lds[tile_slot(e)], sc));
   }
 }
 
@@ -249,7 +251,7 @@ __device__ void split1_body(const DevSig& s, c32* lds, int task) {
   for (int i = 0; i < 16; ++i) {
     int idx, slot;
     split_p1_load(g, n1_0, threadIdx.x + 256 * i, idx, slot);
-    lds[slot] = O::load(s, job, band, idx);
+    lds[tile_slot(slot)] = O::load(s, job, band, idx);
   }
   __syncthreads();
   fft_tile<O::DIR>(lds, g.log2B, s.tw, s.log2_Npad);
@@ -261,7 +263,7 @@ __device__ void split1_body(const DevSig& s, c32* lds, int task) {
   for (int i = 0; i < 16; ++i) {
     int slot, sidx, te;
     split_p1_store(g, n1_0, threadIdx.x + 256 * i, slot, sidx, te);
-    scr[sidx] = cmul(lds[slot], w16[i]);
+    scr[sidx] = cmul(lds[tile_slot(slot)], w16[i]);
   }
 }
 
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(256) void k_fft_split2(DevSig s, int task0) {
   const c32* scr = s.scr + tk.scr;
   for (int i = 0; i < 16; ++i) {
     const int e = threadIdx.x + 256 * i;
-    lds[e] = scr[split_p2_load(g, k2_0, e)];
+    lds[tile_slot(e)] = scr[split_p2_load(g, k2_0, e)];
   }
   __syncthreads();
   fft_tile<O::DIR>(lds, g.log2A, s.tw, s.log2_Npad);
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(256) void k_fft_split2(DevSig s, int task0) {
   for (int i = 0; i < 16; ++i) {
     int slot, oidx;
     split_p2_store(g, k2_0, threadIdx.x + 256 * i, slot, oidx);
-    O::store(s, job, oidx, cscale(lds[slot], sc));
+    O::store(s, job, oidx, cscale(lds[tile_slot(slot)], sc));
   }
 }
 

@@ -26,10 +26,10 @@ static void one_pass(std::vector<c32>& lds, int log2n, int log2p, const std::vec
   const int n = 1 << log2n, tpf = n / 16;
   std::vector<c32> regs(256 * 16);
   for (int tid = 0; tid < 256; ++tid)
-    stockham_compute<DIR, LR>(lds.data() + (tid / tpf) * n, log2n, log2p, tid % tpf, tpf, tw.data(), log2tw,
+    stockham_compute<DIR, LR>(lds.data(), (tid / tpf) * n, log2n, log2p, tid % tpf, tpf, tw.data(), log2tw,
                               &regs[tid * 16]);
   for (int tid = 0; tid < 256; ++tid)
-    stockham_store<LR>(lds.data() + (tid / tpf) * n, log2p, tid % tpf, tpf, &regs[tid * 16]);
+    stockham_store<LR>(lds.data(), (tid / tpf) * n, log2p, tid % tpf, tpf, &regs[tid * 16]);
 }
 
 template <int DIR>
@@ -58,7 +58,7 @@ static double check(int log2n, int dir, const std::vector<c32>& tw, int log2tw) 
     xr[e] = ((s >> 8) & 0xffff) / 65536.0 - 0.5;
     s = s * 1664525u + 1013904223u;
     xi[e] = ((s >> 8) & 0xffff) / 65536.0 - 0.5;
-    lds[e] = c32{(float)xr[e], (float)xi[e]};
+    lds[tile_slot(e)] = c32{(float)xr[e], (float)xi[e]};
   }
   if (dir < 0) tile_fft<-1>(lds, log2n, tw, log2tw);
   else tile_fft<+1>(lds, log2n, tw, log2tw);
@@ -71,7 +71,8 @@ static double check(int log2n, int dir, const std::vector<c32>& tw, int log2tw) 
         sr += xr[c * n + j] * std::cos(a) - xi[c * n + j] * std::sin(a);
         si += xr[c * n + j] * std::sin(a) + xi[c * n + j] * std::cos(a);
       }
-      double dr = lds[c * n + k].x - sr, di = lds[c * n + k].y - si;
+      const c32 o = lds[tile_slot(c * n + k)];
+      double dr = o.x - sr, di = o.y - si;
       err += dr * dr + di * di;
       ref += sr * sr + si * si;
     }
@@ -111,7 +112,7 @@ static double check_split(int log2n, int log2A, int dir, const std::vector<c32>&
   std::vector<c32> lds(4096);
   const int A = 1 << g.log2A, B = 1 << g.log2B;
   for (int n1_0 = 0; n1_0 < A; n1_0 += 1 << g.log2C1) {
-    for (int e = 0; e < 4096; ++e) { int idx, slot; split_p1_load(g, n1_0, e, idx, slot); lds[slot] = x[idx]; }
+    for (int e = 0; e < 4096; ++e) { int idx, slot; split_p1_load(g, n1_0, e, idx, slot); lds[tile_slot(slot)] = x[idx]; }
     if (dir < 0) tile_fft<-1>(lds, g.log2B, tw, log2tw); else tile_fft<+1>(lds, g.log2B, tw, log2tw);
     // per thread t: its 16 elements e = t + 256 i take the composed twiddles of
     // split_p1_twiddles, whose exponents must be the n1 k2 of split_p1_store
@@ -127,14 +128,14 @@ static double check_split(int log2n, int log2A, int dir, const std::vector<c32>&
           std::printf("twiddle mismatch log2n=%d log2A=%d t=%d i=%d\n", log2n, log2A, t, i);
           std::exit(1);
         }
-        scr[sidx] = cmul(lds[slot], w16[i]);
+        scr[sidx] = cmul(lds[tile_slot(slot)], w16[i]);
       }
     }
   }
   for (int k2_0 = 0; k2_0 < B; k2_0 += 1 << g.log2C2) {
-    for (int e = 0; e < 4096; ++e) lds[e] = scr[split_p2_load(g, k2_0, e)];
+    for (int e = 0; e < 4096; ++e) lds[tile_slot(e)] = scr[split_p2_load(g, k2_0, e)];
     if (dir < 0) tile_fft<-1>(lds, g.log2A, tw, log2tw); else tile_fft<+1>(lds, g.log2A, tw, log2tw);
-    for (int e = 0; e < 4096; ++e) { int slot, oidx; split_p2_store(g, k2_0, e, slot, oidx); out[oidx] = lds[slot]; }
+    for (int e = 0; e < 4096; ++e) { int slot, oidx; split_p2_store(g, k2_0, e, slot, oidx); out[oidx] = lds[tile_slot(slot)]; }
   }
   ref_fft(xr, xi, dir);
   double err = 0, ref = 0;
@@ -149,6 +150,15 @@ int main() {
   const int log2tw = 17;
   auto tw = twiddles(log2tw);
   int bad = 0;
+  // the LDS swizzle must be a permutation of the tile
+  {
+    std::vector<int> seen(4096, 0);
+    for (int e = 0; e < 4096; ++e) {
+      const int q = tile_slot(e);
+      if (q < 0 || q >= 4096 || seen[q]++) bad = 1;
+    }
+    std::printf("tile_slot permutation %s\n", bad ? "BROKEN" : "ok");
+  }
   for (int log2n = 4; log2n <= 12; ++log2n)
     for (int dir : {-1, 1}) {
       double e = check(log2n, dir, tw, log2tw);
