@@ -55,21 +55,34 @@ __device__ inline c32 fold_gather(const c32* src, const Band& b, const float* va
 }
 
 // Adjoint gather: sum over terms of band[m] * src_t[m mod len_t], output bin m; only the
-// terms whose band meets m's 512-bin segment are visited (seg0 = the row's first segment).
+// terms whose band meets m's 512-bin segment are visited. Every band is non-empty, so a
+// term whose band misses m reads the band at a clamped index and is masked by value: no
+// branch, so the loads of several terms can be in flight together.
+__device__ inline void term_add(const DevSig& s, const c32* base, const SegTerm& g, int m, c32& acc) {
+  int d = m - g.lo;
+  if (d < 0) d += g.L;
+  const bool in = d < g.len;
+  const float h = s.bandvals[g.off + (in ? d : 0)];
+  const c32 v = base[g.src + (m & (g.src_len - 1))];
+  const float hm = in ? h : 0.f;
+  acc.x += v.x * hm;
+  acc.y += v.y * hm;
+}
+
+// seg0 = the row's first segment. When the whole wave's bins lie in one segment (rows of
+// 64 bins or more), its term list is read with scalar loads.
 __device__ inline c32 term_gather(const DevSig& s, const c32* base, int seg0, int m) {
   c32 acc{0.f, 0.f};
   const int sg = seg0 + (m >> 9);
-  const int first = s.segs[2 * sg], count = s.segs[2 * sg + 1];
-  for (int i = 0; i < count; ++i) {
-    const SegTerm g = s.segterms[first + i];
-    int d = m - g.lo;
-    if (d < 0) d += g.L;
-    if (d < g.len) {
-      const float h = s.bandvals[g.off + d];
-      const c32 v = base[g.src + (m & (g.src_len - 1))];
-      acc.x += v.x * h;
-      acc.y += v.y * h;
-    }
+  const int sgu = __builtin_amdgcn_readfirstlane(sg);
+  if (__all(sg == sgu)) {
+    const int first = s.segs[2 * sgu], count = s.segs[2 * sgu + 1];
+#pragma unroll 4
+    for (int i = 0; i < count; ++i) term_add(s, base, s.segterms[first + i], m, acc);
+  } else {
+    const int first = s.segs[2 * sg], count = s.segs[2 * sg + 1];
+#pragma unroll 4
+    for (int i = 0; i < count; ++i) term_add(s, base, s.segterms[first + i], m, acc);
   }
   return acc;
 }
