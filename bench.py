@@ -210,7 +210,7 @@ def main() -> int:
         print(json.dumps({"copy_bytes": src.numel() * 4, "repeats": 3}), flush=True)
         return 0
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
         return 2
 

@@ -1,7 +1,7 @@
 """Oracle plan: filterbanks, subsampling factors, path list and output layout.
 
 Derived from the paper (Sec. 3.1-3.5) independently of the C++ plan of the HIP path.
-Readings where the paper is silent (each listed with its reason in the design doc):
+Readings where the paper is silent, each with its reason:
 
 * phi_T is a Gaussian of width sigma0 / T, phi_F of width sigma0 / F (F in first-order
   filter bins); both have unit DC gain. Their subsampling scales are log2 T and
