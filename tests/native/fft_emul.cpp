@@ -146,6 +146,72 @@ static double check_split(int log2n, int log2A, int dir, const std::vector<c32>&
   return std::sqrt(err / ref);
 }
 
+// Bank spread of the swizzled tile: in every LDS write of a Stockham pass and in the
+// transposes of the two-pass split, each 16 consecutive lanes of a wave must reach 16
+// different slots modulo 16 (16 eight-byte elements fill one row of 32 four-byte banks).
+// The writes are recorded by running the pass's store phase with values that name the
+// writing lane and register.
+static int bank_spread_failures() {
+  int bad = 0;
+  auto distinct16 = [](const int* slot16) {
+    unsigned seen = 0;
+    for (int l = 0; l < 16; ++l) seen |= 1u << (slot16[l] & 15);
+    return seen == 0xffffu;
+  };
+  for (int log2n = 4; log2n <= 12; ++log2n) {
+    const int n = 1 << log2n, tpf = n / 16;
+    int lr[8];
+    const int np = fft_radices(log2n, lr);
+    int log2p = 0;
+    for (int ps = 0; ps < np; ++ps) {
+      std::vector<c32> tile(4096);
+      for (int tid = 0; tid < 256; ++tid) {
+        c32 v[16];
+        for (int q = 0; q < 16; ++q) v[q] = c32{(float)tid, (float)q};
+        switch (lr[ps]) {
+          case 1: stockham_store<1>(tile.data(), (tid / tpf) * n, log2p, tid % tpf, tpf, v); break;
+          case 2: stockham_store<2>(tile.data(), (tid / tpf) * n, log2p, tid % tpf, tpf, v); break;
+          case 3: stockham_store<3>(tile.data(), (tid / tpf) * n, log2p, tid % tpf, tpf, v); break;
+          default: stockham_store<4>(tile.data(), (tid / tpf) * n, log2p, tid % tpf, tpf, v); break;
+        }
+      }
+      std::vector<int> where(256 * 16, -1);
+      for (int q = 0; q < 4096; ++q) where[(int)tile[q].x * 16 + (int)tile[q].y] = q;
+      for (int reg = 0; reg < 16; ++reg)
+        for (int g = 0; g < 256; g += 16) {
+          int s16[16];
+          for (int l = 0; l < 16; ++l) s16[l] = where[(g + l) * 16 + reg];
+          if (!distinct16(s16)) {
+            std::printf("bank conflict: store n=%d pass=%d reg=%d lanes %d..%d\n", n, ps, reg, g, g + 15);
+            bad = 1;
+          }
+        }
+      log2p += lr[ps];
+    }
+  }
+  for (int log2n = 13; log2n <= 17; ++log2n)
+    for (int log2A = (log2n - 12 > 4 ? log2n - 12 : 4); log2A <= (log2n - 4 < 12 ? log2n - 4 : 12); ++log2A) {
+      SplitGeom g = split_geom(log2n, log2A);
+      for (int base = 0; base < 4096; base += 16) {
+        int s1[16], s2[16];
+        for (int l = 0; l < 16; ++l) {
+          int idx, slot, sidx, te, oidx;
+          split_p1_load(g, 0, base + l, idx, slot);
+          s1[l] = tile_slot(slot);
+          split_p2_store(g, 0, base + l, slot, oidx);
+          s2[l] = tile_slot(slot);
+          split_p1_store(g, 0, base + l, slot, sidx, te);
+          if (tile_slot(slot) != s1[l]) bad = 1;   // pass 1 reads its tile as it loaded it
+        }
+        if (!distinct16(s1) || !distinct16(s2)) {
+          std::printf("bank conflict: split n=%d A=%d elements %d..%d\n", 1 << log2n, 1 << log2A, base, base + 15);
+          bad = 1;
+        }
+      }
+    }
+  return bad;
+}
+
 int main() {
   const int log2tw = 17;
   auto tw = twiddles(log2tw);
@@ -159,6 +225,8 @@ int main() {
     }
     std::printf("tile_slot permutation %s\n", bad ? "BROKEN" : "ok");
   }
+  if (bank_spread_failures()) bad = 1;
+  else std::printf("tile bank spread ok\n");
   for (int log2n = 4; log2n <= 12; ++log2n)
     for (int dir : {-1, 1}) {
       double e = check(log2n, dir, tw, log2tw);

@@ -152,6 +152,7 @@ def test_fft_tile_index_logic_host_emulation(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.strip().endswith("OK")
+    assert "tile_slot permutation ok" in out.stdout and "tile bank spread ok" in out.stdout
 
 
 def _dec(cfg, max_batch=2):
