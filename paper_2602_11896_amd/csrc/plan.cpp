@@ -801,6 +801,13 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
       return JTFS_ERR_UNSUPPORTED;
     }
   }
+  // The adjoint gathers read a term's band at an index clamped into it: no term band may
+  // be empty.
+  for (const SegTerm& t : p.segterms)
+    if (t.len < 1 || t.len > t.L) {
+      err = "an adjoint-gather term has an empty filter band";
+      return JTFS_ERR_UNSUPPORTED;
+    }
 
   // ---- workspace layout (bytes, 256-aligned regions)
   size_t o = 0;
