@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 namespace jtfs {
 namespace {
@@ -17,6 +18,7 @@ constexpr double kBandThresh = 1e-10; // Fourier bins below this fraction of the
 constexpr double kTapThresh = 1e-9;   // frequential taps below this fraction of the peak are skipped
 constexpr int kPeriods = 4;           // period-1 images of a Fourier Gaussian on each side
 constexpr double kPi = 3.14159265358979323846;
+constexpr int64_t kPlanThreads = 16;  // host threads evaluating one long filter band
 
 int ceil_log2(int64_t n) {
   int p = 0;
@@ -78,13 +80,26 @@ int32_t add_band(SigPlan& p, int64_t L, const Fn& value, double wlo, double whi)
     mlo = 0;
     mhi = L - 1;
   }
-  std::vector<double> v(static_cast<size_t>(mhi - mlo + 1));
-  double peak = 0.0;
-  for (int64_t m = mlo; m <= mhi; ++m) {
-    double w = static_cast<double>(m) / static_cast<double>(L);
-    v[m - mlo] = value(w);
-    peak = std::max(peak, std::fabs(v[m - mlo]));
+  const int64_t nv = mhi - mlo + 1;
+  std::vector<double> v(static_cast<size_t>(nv));
+  // Every bin is evaluated on its own, so long windows (up to a few million bins for the
+  // first-order bank of a 2^20-sample signal) are split across host threads; the values,
+  // and hence the tables, are the same as in one thread.
+  auto fill = [&](int64_t a, int64_t b) {
+    for (int64_t i = a; i < b; ++i) v[static_cast<size_t>(i)] = value(static_cast<double>(mlo + i) / static_cast<double>(L));
+  };
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int64_t nt = nv >= (int64_t{1} << 16) ? std::max<int64_t>(1, std::min<int64_t>(kPlanThreads, hw)) : 1;
+  if (nt > 1) {
+    std::vector<std::thread> th;
+    for (int64_t t = 1; t < nt; ++t) th.emplace_back(fill, nv * t / nt, nv * (t + 1) / nt);
+    fill(0, nv / nt);
+    for (std::thread& x : th) x.join();
+  } else {
+    fill(0, nv);
   }
+  double peak = 0.0;
+  for (double x : v) peak = std::max(peak, std::fabs(x));
   int64_t first = 0, last = static_cast<int64_t>(v.size()) - 1;
   const double thr = kBandThresh * peak;
   while (first < last && std::fabs(v[first]) <= thr) ++first;
