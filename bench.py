@@ -3,7 +3,13 @@
 One step = one jtfs_metamer_step of the config-2 workload (N = 2^16 samples, J = 12,
 Q1 = 12, Q2 = 2, J_fr = 4, Q_fr = 2, T = 2^13, F = 24 bins; Adam, lr 0.1): forward
 transform, loss, exact backward and update, with the signal and target resident on
-the GPU. Prints one JSON line (see the README of this repository for the fields).
+the GPU. Prints one JSON line: metric, value (iterations/s), unit, n_gpus, steps, warmup,
+ms_per_step, higher_is_better, scaling, vs_baseline, dtype, data and config (the
+workload), then per-stage times, `roofline` (the frequential backward against the FP32
+MFMA peak, with its counted HBM traffic when the committed counter record matches the
+kernel source and schedules), the tile schedules used, `config4` (time to relative loss
+1e-2 from the learned, coloured-noise and white-noise starts), `decoder` and
+`cpu_baseline` (the FP64 oracle on one host thread, on a bounded sample).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -176,8 +182,9 @@ def hbm_traffic(kernel: str, tuning: dict):
     rt = rec.get("tuning")
     if not isinstance(rt, dict) or any(rt.get(f) != tuning[f] for f in fields):
         return None
-    # a stage may launch several shapes of the kernel (one per group size): sum them
-    hits = [mb for k, mb in rec["hbm_MB_per_launch"].items() if k.startswith("k_" + kernel + "<")]
+    # a stage may launch several shapes of its kernel (one per group size): sum them
+    prefixes = {"freq_fwd": ("k_freq_fwd2<", "k_freq_fwd<")}.get(kernel, ("k_" + kernel + "<",))
+    hits = [mb for k, mb in rec["hbm_MB_per_launch"].items() if k.startswith(prefixes)]
     return round(sum(hits) * 1e6) if hits else None
 
 

@@ -1,0 +1,65 @@
+"""Host-side rules of bench.py: the counted HBM traffic is reported only while the committed
+counter record matches the kernel source and the tile schedules it was taken with, and a
+run asked for more than one GPU stops with a message."""
+import json
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+REC = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def _record():
+    return json.load(open(REC))
+
+
+def test_traffic_of_the_recorded_schedules():
+    rec = _record()
+    tuning = dict(rec["tuning"])
+    expect = sum(mb for k, mb in rec["hbm_MB_per_launch"].items() if k.startswith("k_freq_bwd<"))
+    assert expect > 0
+    assert bench.hbm_traffic("freq_bwd", tuning) == round(expect * 1e6)
+
+
+def test_traffic_is_null_for_other_backward_schedules():
+    tuning = dict(_record()["tuning"])
+    tuning["bwd_rows_k"] = [v * 2 for v in tuning["bwd_rows_k"]]
+    assert bench.hbm_traffic("freq_bwd", tuning) is None
+    # the forward's figure does not depend on the backward's schedules
+    assert bench.hbm_traffic("freq_fwd", tuning) is not None
+
+
+def test_traffic_is_null_once_the_kernel_source_changed(tmp_path, monkeypatch):
+    rec = _record()
+    (tmp_path / "profiles").mkdir()
+    src = tmp_path / rec["source"]
+    src.parent.mkdir(parents=True)
+    shutil.copy(os.path.join(ROOT, rec["source"]), src)
+    shutil.copy(REC, tmp_path / "profiles" / "hbm_traffic.json")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    tuning = dict(rec["tuning"])
+    assert bench.hbm_traffic("freq_bwd", tuning) is not None      # an exact copy still matches
+    with open(src, "a") as f:
+        f.write("\n// edited\n")
+    assert bench.hbm_traffic("freq_bwd", tuning) is None
+
+
+def test_traffic_is_null_without_a_record(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.hbm_traffic("freq_bwd", dict(_record()["tuning"])) is None
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_more_than_one_gpu_is_refused(n):
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)],
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode == 2
+    assert "one GPU" in out.stderr
+    assert out.stdout == ""
