@@ -63,3 +63,9 @@ def test_more_than_one_gpu_is_refused(n):
     assert out.returncode == 2
     assert "one GPU" in out.stderr
     assert out.stdout == ""
+
+
+def test_default_run_uses_the_recorded_schedules():
+    """A default bench run (library schedules) reports counted traffic: the committed record
+    was taken with exactly those schedules."""
+    assert bench.effective_tuning(None) == _record()["tuning"]
