@@ -126,6 +126,30 @@ def test_small_shift_changes_little():
     assert rel[0] < 0.63 * 4 / p.T
 
 
+def test_transposition_changes_little_up_to_F():
+    # Invariance to frequency transposition up to F (Sec. 2.2): moving a tone by one
+    # first-order bin (a factor 2^(1/Q1)) changes S by a small fraction that grows with the
+    # shift, and the change per bin shrinks as the frequential averaging F widens. Missing
+    # or misplaced phi_F averaging along log-frequency makes a one-bin move large.
+    N, Q1 = 1 << 13, 8
+
+    def tone(f):
+        k = round(f * N)
+        return np.cos(2 * np.pi * k * np.arange(N) / N)
+
+    def rel_change(F, bins):
+        p = make_plan(N, 8, Q1, 1, 3, 1, 9, F, periodic=True)
+        a = fftroute.forward(p, tone(0.04))
+        return [np.linalg.norm(fftroute.forward(p, tone(0.04 * 2 ** (b / Q1))) - a) / np.linalg.norm(a)
+                for b in bins]
+
+    wide = rel_change(8, (1, 4, 16))     # F = 8 bins, one octave
+    assert wide[0] < wide[1] < wide[2]
+    assert wide[0] < 0.1 and wide[2] > 0.5
+    narrow = rel_change(2, (1,))         # F = 2 bins
+    assert narrow[0] > 2.5 * wide[0]
+
+
 def test_time_reversal_swaps_spin():
     p = make_plan(1024, 4, 4, 2, 2, 2, 5, 2, periodic=True)
     rng = np.random.default_rng(7)
