@@ -69,8 +69,8 @@ __device__ inline void term_add(const DevSig& s, const c32* base, const SegTerm&
   acc.y += v.y * hm;
 }
 
-// seg0 = the row's first segment. When the whole wave's bins lie in one segment (rows of
-// 64 bins or more), its term list is read with scalar loads.
+// seg0 = the row's first segment. When the whole wave's bins lie in one segment (single-
+// tile rows of 64 bins or more, the bin-parallel gather), its terms come by scalar loads.
 __device__ inline c32 term_gather(const DevSig& s, const c32* base, int seg0, int m) {
   c32 acc{0.f, 0.f};
   const int sg = seg0 + (m >> 9);
