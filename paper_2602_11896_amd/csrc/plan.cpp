@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <system_error>
 #include <thread>
 
 namespace jtfs {
@@ -92,7 +93,15 @@ int32_t add_band(SigPlan& p, int64_t L, const Fn& value, double wlo, double whi)
   const int64_t nt = nv >= (int64_t{1} << 16) ? std::max<int64_t>(1, std::min<int64_t>(kPlanThreads, hw)) : 1;
   if (nt > 1) {
     std::vector<std::thread> th;
-    for (int64_t t = 1; t < nt; ++t) th.emplace_back(fill, nv * t / nt, nv * (t + 1) / nt);
+    th.reserve(static_cast<size_t>(nt - 1));
+    for (int64_t t = 1; t < nt; ++t) {
+      try {
+        th.emplace_back(fill, nv * t / nt, nv * (t + 1) / nt);
+      } catch (const std::system_error&) {   // no thread to be had: the rest runs here
+        fill(nv * t / nt, nv);
+        break;
+      }
+    }
     fill(0, nv / nt);
     for (std::thread& x : th) x.join();
   } else {
