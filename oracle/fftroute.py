@@ -183,23 +183,17 @@ def first_layer_cache(plan: OraclePlan, x: np.ndarray, fc: FilterCache = None) -
     """The intermediates ``backward`` needs (first layer and the transformed order-1 input)."""
     fc = fc or FilterCache(plan)
     Xh, Z1, U1h, S1 = first_layer(plan, x, fc)
-    A = np.zeros((plan.N_fr, plan.nf_pad), dtype=np.float64)
-    A[:plan.N1] = S1
-    return dict(Xh=Xh, Z1=Z1, U1h=U1h, S1=S1, Ah=np.fft.fft(A, axis=0), fc=fc)
+    return dict(Xh=Xh, Z1=Z1, U1h=U1h, S1=S1, Ah=transformed_s1(plan, S1), fc=fc)
 
 
-def forward(plan: OraclePlan, x: np.ndarray, fc: FilterCache = None, return_cache: bool = False):
-    """S(x) as a flat FP64 vector in the plan's output layout."""
-    fc = fc or FilterCache(plan)
-    Xh, Z1, U1h, S1 = first_layer(plan, x, fc)
-    S = np.zeros(plan.n_coeff, dtype=np.float64)
+def order1_blocks(plan: OraclePlan, Ah: np.ndarray, fc: FilterCache, S: np.ndarray) -> None:
+    """Order-1 joint paths (Sec. 3.5 on real input, Eq. 3 for phi_F) written into S.
+
+    ``Ah`` is the DFT along log-frequency of S1 zero-padded to N_fr rows."""
     n_bins_out = plan.N_fr >> plan.s_F
-
-    A = np.zeros((plan.N_fr, plan.nf_pad), dtype=np.float64)
-    A[:plan.N1] = S1
-    Ah = np.fft.fft(A, axis=0)
-    blocks1 = [blk for blk in plan.blocks if blk.order == 1]
-    for blk in blocks1:
+    for blk in plan.blocks:
+        if blk.order != 1:
+            continue
         g, b = blk.n_fr, plan.fr[blk.n_fr]
         V = freq_filter(plan, Ah, g, fc)
         if b.lowpass:
@@ -209,23 +203,43 @@ def forward(plan: OraclePlan, x: np.ndarray, fc: FilterCache = None, return_cach
         assert out.shape[0] == n_bins_out
         _block_view(plan, blk, S)[:] = _keep(plan, blk, out)
 
-    by_n2 = {}
+
+def order2_group(plan: OraclePlan, grp, U1h, fc: FilterCache, S: np.ndarray) -> None:
+    """Every order-2 joint path of the second-order filter ``grp.n2`` written into S:
+    the width-first stack Y2 (Sec. 3.3), the frequential filters along log-frequency
+    (Sec. 3.5), the modulus, then phi_T over time and (band-pass paths) phi_F (Eq. 4)."""
+    Y = second_layer_group(plan, grp, U1h, fc)
+    Yh = np.fft.fft(Y, axis=0)
+    phT = fc.phi_t(grp.j2)
     for blk in plan.blocks:
-        if blk.order == 2:
-            by_n2.setdefault(blk.n2, []).append(blk)
+        if blk.order != 2 or blk.n2 != grp.n2:
+            continue
+        g, b = blk.n_fr, plan.fr[blk.n_fr]
+        W = np.abs(freq_filter(plan, Yh, g, fc))
+        P = filt_dec(W, phT, plan.log2_T - grp.j2, axis=1).real
+        if b.lowpass:
+            out = P
+        else:
+            out = filt_dec(P, fc.phi_f(b.k), plan.s_F - b.k, axis=0).real
+        _block_view(plan, blk, S)[:] = _keep(plan, blk, out)
+
+
+def transformed_s1(plan: OraclePlan, S1: np.ndarray) -> np.ndarray:
+    """DFT along log-frequency of S1 with its rows zero-padded to N_fr (Sec. 3.5)."""
+    A = np.zeros((plan.N_fr, plan.nf_pad), dtype=np.float64)
+    A[:plan.N1] = S1
+    return np.fft.fft(A, axis=0)
+
+
+def forward(plan: OraclePlan, x: np.ndarray, fc: FilterCache = None, return_cache: bool = False):
+    """S(x) as a flat FP64 vector in the plan's output layout."""
+    fc = fc or FilterCache(plan)
+    Xh, Z1, U1h, S1 = first_layer(plan, x, fc)
+    S = np.zeros(plan.n_coeff, dtype=np.float64)
+    Ah = transformed_s1(plan, S1)
+    order1_blocks(plan, Ah, fc, S)
     for grp in plan.groups:
-        Y = second_layer_group(plan, grp, U1h, fc)
-        Yh = np.fft.fft(Y, axis=0)
-        phT = fc.phi_t(grp.j2)
-        for blk in by_n2[grp.n2]:
-            g, b = blk.n_fr, plan.fr[blk.n_fr]
-            W = np.abs(freq_filter(plan, Yh, g, fc))
-            P = filt_dec(W, phT, plan.log2_T - grp.j2, axis=1).real
-            if b.lowpass:
-                out = P
-            else:
-                out = filt_dec(P, fc.phi_f(b.k), plan.s_F - b.k, axis=0).real
-            _block_view(plan, blk, S)[:] = _keep(plan, blk, out)
+        order2_group(plan, grp, U1h, fc, S)
     if return_cache:
         return S, dict(Xh=Xh, Z1=Z1, U1h=U1h, S1=S1, Ah=Ah, fc=fc)
     return S
@@ -297,37 +311,18 @@ def backward(plan: OraclePlan, x: np.ndarray, dS: np.ndarray, cache=None, fc: Fi
 # ----------------------------------------------------------------------------- partial forward
 
 def forward_partial(plan: OraclePlan, x: np.ndarray, n2_list, order1: bool = True, fc: FilterCache = None):
-    """The order-1 blocks (if ``order1``) and the order-2 blocks of the listed n2; every
-    other coefficient is NaN. Used for sampled parity at full size."""
+    """The order-1 blocks (if ``order1``) and the order-2 blocks of the listed n2, computed
+    by the same per-block steps as ``forward``; every other coefficient is NaN. Used for
+    sampled parity at full size."""
     fc = fc or FilterCache(plan)
     _, _, U1h, S1 = first_layer(plan, x, fc)
     S = np.full(plan.n_coeff, np.nan)
     if order1:
-        A = np.zeros((plan.N_fr, plan.nf_pad), dtype=np.float64)
-        A[:plan.N1] = S1
-        Ah = np.fft.fft(A, axis=0)
-        for blk in plan.blocks:
-            if blk.order != 1:
-                continue
-            g, b = blk.n_fr, plan.fr[blk.n_fr]
-            V = freq_filter(plan, Ah, g, fc)
-            out = V.real if b.lowpass else filt_dec(np.abs(V), fc.phi_f(b.k), plan.s_F - b.k, axis=0).real
-            _block_view(plan, blk, S)[:] = _keep(plan, blk, out)
+        order1_blocks(plan, transformed_s1(plan, S1), fc, S)
     want = set(n2_list)
     for grp in plan.groups:
-        if grp.n2 not in want:
-            continue
-        Y = second_layer_group(plan, grp, U1h, fc)
-        Yh = np.fft.fft(Y, axis=0)
-        phT = fc.phi_t(grp.j2)
-        for blk in plan.blocks:
-            if blk.order != 2 or blk.n2 != grp.n2:
-                continue
-            g, b = blk.n_fr, plan.fr[blk.n_fr]
-            W = np.abs(freq_filter(plan, Yh, g, fc))
-            P = filt_dec(W, phT, plan.log2_T - grp.j2, axis=1).real
-            out = P if b.lowpass else filt_dec(P, fc.phi_f(b.k), plan.s_F - b.k, axis=0).real
-            _block_view(plan, blk, S)[:] = _keep(plan, blk, out)
+        if grp.n2 in want:
+            order2_group(plan, grp, U1h, fc, S)
     return S
 
 

@@ -29,40 +29,53 @@ R_PSI = math.sqrt(0.5)      # r_psi of the Sec. 3.1 generator: neighbours cross 
 BAND_EDGE_WIDTHS = 5.0      # a filter's band edge is xi + 5 sigma (subsampling rule)
 
 
+def constant_q_count(sigma_top: float, sigma_min: float, Q: int) -> int:
+    """How many constant-Q filters the Sec. 3.1 generator emits.
+
+    Widths shrink by 2^(1/Q) per filter, sigma_k = sigma_top 2^(-k/Q), and a filter of the
+    constant-Q region is kept while its width stays strictly above the floor sigma_min
+    (the elbow). With R = Q log2(sigma_top / sigma_min) that is every k < R: ceil(R)
+    filters, or R itself when R is an integer (the member of width exactly sigma_min
+    belongs to the constant-bandwidth region). R within 1e-9 of an integer counts as
+    that integer, so the decision does not hang on the last bit of a logarithm.
+    No room at all (sigma_top <= sigma_min) gives 0.
+    """
+    if sigma_top <= sigma_min:
+        return 0
+    R = Q * math.log2(sigma_top / sigma_min)
+    m = round(R)
+    if abs(R - m) <= 1e-9 * max(1.0, R):
+        return max(1, m)
+    return max(1, math.ceil(R))
+
+
 def morlet_bank(J: int, Q: int):
-    """(xi, sigma) pairs of a wavelet filterbank, Sec. 3.1.
+    """(xi, sigma) pairs of a wavelet filterbank (Sec. 3.1), in closed form.
 
-    The top filter sits at max(1 / (1 + 2^(3/Q)), 0.35). Its width follows from the
-    requirement that neighbouring Gaussians, a factor 2^(1/Q) apart, cross at r_psi
-    of their peak. Centres and widths then shrink geometrically by 2^(1/Q) (constant Q)
-    while the width stays above sigma0 / 2^J scaled by one step; below that "elbow"
-    Q - 1 further filters are spaced arithmetically at the minimum width.
-
-    The arithmetic is written in the same order as the paper's generator (one division
-    per step) so that the number of constant-Q filters is decided the same way.
+    * Top filter: xi_0 = max(1 / (1 + 2^(3/Q)), 0.35). Its width sigma_0 makes two
+      Gaussians a factor 2^(1/Q) apart meet at r_psi of their peak:
+      sigma_0 = (1 - 2^(-1/Q)) / (1 + 2^(-1/Q)) * xi_0 / sqrt(2 ln(1 / r_psi)).
+    * Constant-Q region: (xi_0 2^(-k/Q), sigma_0 2^(-k/Q)) for the k counted by
+      ``constant_q_count`` against the floor sigma_min = sigma0 / 2^J.
+    * Constant-bandwidth region: Q - 1 filters of width sigma_min whose centres step
+      down arithmetically from the last constant-Q centre e by e / Q each,
+      xi = e (1 - q / Q), q = 1 .. Q - 1. Without a constant-Q region the steps start
+      from e = sigma_0.
     """
     if J < 0 or Q < 1:
         raise ValueError("need J >= 0 and Q >= 1")
-    step = math.pow(2.0, 1.0 / Q)
-    shrink = 1.0 / step
-    xi = max(1.0 / (1.0 + math.pow(2.0, 3.0 / Q)), 0.35)
-    sigma = (1.0 - shrink) / (1.0 + shrink) * xi / math.sqrt(2.0 * math.log(1.0 / R_PSI))
+    xi_top = max(1.0 / (1.0 + math.pow(2.0, 3.0 / Q)), 0.35)
+    f = math.pow(2.0, -1.0 / Q)
+    sigma_top = (1.0 - f) / (1.0 + f) * xi_top / math.sqrt(2.0 * math.log(1.0 / R_PSI))
     sigma_min = SIGMA0 / math.pow(2.0, J)
-
+    n_cq = constant_q_count(sigma_top, sigma_min, Q)
     bank = []
-    if sigma <= sigma_min:
-        # No room for a constant-Q region: the arithmetic region starts from xi = sigma.
-        xi = sigma
-    else:
-        bank.append((xi, sigma))
-        while sigma > sigma_min * step:
-            xi = xi / step
-            sigma = sigma / step
-            bank.append((xi, sigma))
-    elbow = xi
-    for _ in range(Q - 1):
-        xi = xi - elbow / Q
-        bank.append((xi, sigma_min))
+    for k in range(n_cq):
+        g = math.pow(2.0, -k / Q)
+        bank.append((xi_top * g, sigma_top * g))
+    elbow = bank[-1][0] if bank else sigma_top
+    for q in range(1, Q):
+        bank.append((elbow * (Q - q) / Q, sigma_min))
     return bank
 
 
@@ -74,8 +87,8 @@ def spun(bank):
 def subsampling_scale(xi: float, sigma: float) -> int:
     """Largest j >= 0 whose Nyquist 2^-(j+1) still lies above the band edge |xi| + 5 sigma.
 
-    Kymatio derives j from "the resolution of the cutoff frequency" (Sec. 3.2); the
-    factor 5 on sigma is this implementation's reading. Comparisons use exact powers
+    Sec. 3.2 ties the subsampling of a filter to how fine its cut-off frequency is; the
+    band edge at 5 sigma is this implementation's reading of that. Comparisons use exact powers
     of two so that the rule is decided identically everywhere.
     """
     edge = abs(xi) + BAND_EDGE_WIDTHS * sigma

@@ -160,28 +160,35 @@ int64_t add_lowpass_time(SigPlan& p, int64_t L, double sigma, int level) {
 
 }  // namespace
 
+// Number of constant-Q members of a Sec. 3.1 bank: widths sigma_top 2^(-k/Q) strictly
+// above the floor sigma_min, i.e. every k < R = Q log2(sigma_top / sigma_min); R within
+// 1e-9 of an integer counts as that integer (the member of width exactly sigma_min is
+// not constant-Q). No room (sigma_top <= sigma_min) gives 0.
+static int constant_q_members(double sigma_top, double sigma_min, int Q) {
+  if (sigma_top <= sigma_min) return 0;
+  const double R = Q * std::log2(sigma_top / sigma_min);
+  const double m = std::round(R);
+  if (std::fabs(R - m) <= 1e-9 * std::max(1.0, R)) return std::max(1, static_cast<int>(m));
+  return std::max(1, static_cast<int>(std::ceil(R)));
+}
+
+// Sec. 3.1 bank in closed form: the top filter (xi_top, sigma_top), whose neighbours a
+// factor 2^(1/Q) away cross it at sqrt(1/2) of the peak; the constant-Q members scaled
+// by 2^(-k/Q); then Q - 1 members of width sigma_min with centres e (Q - q) / Q, e the
+// last constant-Q centre (sigma_top when there is none).
 std::vector<std::pair<double, double>> wavelet_bank(int J, int Q) {
   std::vector<std::pair<double, double>> bank;
-  const double step = std::pow(2.0, 1.0 / Q);
-  const double shrink = 1.0 / step;
-  double xi = std::max(1.0 / (1.0 + std::pow(2.0, 3.0 / Q)), 0.35);
-  double sigma = (1.0 - shrink) / (1.0 + shrink) * xi / std::sqrt(2.0 * std::log(1.0 / std::sqrt(0.5)));
+  const double xi_top = std::max(1.0 / (1.0 + std::pow(2.0, 3.0 / Q)), 0.35);
+  const double f = std::pow(2.0, -1.0 / Q);
+  const double sigma_top = (1.0 - f) / (1.0 + f) * xi_top / std::sqrt(2.0 * std::log(1.0 / std::sqrt(0.5)));
   const double sigma_min = kSigma0 / std::pow(2.0, J);
-  if (sigma <= sigma_min) {
-    xi = sigma;
-  } else {
-    bank.emplace_back(xi, sigma);
-    while (sigma > sigma_min * step) {
-      xi = xi / step;
-      sigma = sigma / step;
-      bank.emplace_back(xi, sigma);
-    }
+  const int n_cq = constant_q_members(sigma_top, sigma_min, Q);
+  for (int k = 0; k < n_cq; ++k) {
+    const double g = std::pow(2.0, -static_cast<double>(k) / Q);
+    bank.emplace_back(xi_top * g, sigma_top * g);
   }
-  const double elbow = xi;
-  for (int q = 0; q < Q - 1; ++q) {
-    xi = xi - elbow / Q;
-    bank.emplace_back(xi, sigma_min);
-  }
+  const double elbow = n_cq ? bank.back().first : sigma_top;
+  for (int q = 1; q < Q; ++q) bank.emplace_back(elbow * (Q - q) / Q, sigma_min);
   return bank;
 }
 

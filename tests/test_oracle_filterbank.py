@@ -51,6 +51,71 @@ def test_bank_structure_and_count(J, Q):
     assert all(a > b > 0 for a, b in zip(xis, xis[1:]))
 
 
+def _constant_q_count_decimal(J: int, Q: int):
+    """Count of constant-Q members, k >= 0 with sigma_top 2^(-k/Q) > sigma0 / 2^J, evaluated
+    with 60-digit decimal arithmetic (independent of the float code), and how close
+    R = Q log2(sigma_top / sigma_min) lies to an integer (a tie of the rule)."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    two = Decimal(2)
+    ln2 = two.ln()
+    p2 = lambda e: (Decimal(e) * ln2).exp()            # 2^e
+    xi_top = max(Decimal(1) / (1 + p2(Decimal(3) / Q)), Decimal("0.35"))
+    f = p2(Decimal(-1) / Q)
+    # sqrt(2 ln(1 / r_psi)) with r_psi = sqrt(1/2) is sqrt(ln 2)
+    s_top = (1 - f) / (1 + f) * xi_top / ln2.sqrt()
+    s_min = Decimal("0.1") / (two ** J)
+    if s_top <= s_min:
+        return 0, None
+    R = Q * (s_top / s_min).ln() / ln2
+    n = int(R.to_integral_value(rounding="ROUND_CEILING"))
+    return max(1, n), float(abs(R - R.to_integral_value()))
+
+
+def test_constant_q_count_against_high_precision():
+    # Every (J, Q) in a wide grid: the float count equals the exact one; the pairs whose
+    # R lies closest to an integer (the boundary cases of the rule) are included.
+    closest = []
+    for J in range(0, 21):
+        for Q in range(1, 33):
+            n_ref, dist = _constant_q_count_decimal(J, Q)
+            bank = fb.morlet_bank(J, Q)
+            n_cq = sum(1 for (_, s) in bank if s > 0.1 / 2 ** J)
+            assert n_cq == n_ref, (J, Q)
+            assert len(bank) == n_ref + Q - 1, (J, Q)
+            if dist is not None:
+                closest.append((dist, J, Q))
+    closest.sort()
+    # the nearest approach to a tie stays far above the 1e-9 tie tolerance
+    assert closest[0][0] > 1e-6
+
+
+def test_bank_sizes_of_the_workloads():
+    # N1 = constant-Q + (Q - 1) linear members at configs 1, 2, 5; N2 at Q2 = 1 and 2
+    assert len(fb.morlet_bank(6, 8)) == 38
+    assert len(fb.morlet_bank(12, 12)) == 124
+    assert len(fb.morlet_bank(14, 16)) == 191
+    assert len(fb.morlet_bank(6, 1)) == 7
+    assert len(fb.morlet_bank(12, 2)) == 25
+    assert len(fb.morlet_bank(14, 2)) == 29
+
+
+def test_no_constant_q_room():
+    # J = 0 with Q = 1: sigma_top = 0.14 > 0.1, so one constant-Q member; a tiny J and a
+    # large Q leave none, and the linear members then step down from sigma_top
+    bank = fb.morlet_bank(0, 1)
+    assert len(bank) == 1
+    xi_top = 1.0 / (1.0 + 2.0 ** (3.0 / 40))  # 0.487 > 0.35
+    f = 2.0 ** (-1.0 / 40)
+    s_top = (1 - f) / (1 + f) * xi_top / math.sqrt(math.log(2.0))
+    assert s_top < 0.1                       # no room at J = 0, Q = 40
+    bank = fb.morlet_bank(0, 40)
+    assert len(bank) == 39
+    for q, (xi, s) in enumerate(bank, start=1):
+        assert s == 0.1
+        assert xi == pytest.approx(s_top * (1 - q / 40), rel=1e-14)
+
+
 def test_adjacent_constant_q_filters_cross_at_minus_3db():
     # r_psi = sqrt(1/2): neighbouring Gaussians intersect at sqrt(1/2) of their peak.
     for J, Q in [(6, 8), (12, 12), (10, 2), (8, 1)]:
