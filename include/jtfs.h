@@ -185,6 +185,30 @@ jtfs_status jtfs_forward_ex(jtfs_plan_t plan, const float* x, float* S, void* ws
                             uint32_t flags, jtfs_stream_t stream);
 
 /*
+ * No-allocation forward, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ *
+ * JTFS_NOALLOC_SCRATCH_BYTES is the size of a device array the library holds on every
+ * device it runs on, until the process ends; it stands in for the forward's workspace.
+ *
+ * jtfs_plan_prepare - set-up on the current device (allocates; call it outside the
+ * no-allocation region): uploads the plan's tables if they are not there yet and
+ * resolves the device address of the scratch array. Call it once per plan and device.
+ *
+ * jtfs_forward_noalloc - S = S(x) exactly as jtfs_forward (the signals of a batch run one
+ * after another on `stream`), with the scratch array as workspace; enqueues kernels and
+ * allocates nothing. Returns JTFS_ERR_WORKSPACE if the plan's ws_shared_forward exceeds
+ * JTFS_NOALLOC_SCRATCH_BYTES (e.g. N = 2^13 with J = 6, Q1 = 8 needs 14.5 MB; N = 2^16 with
+ * J = 12, Q1 = 12 needs 273 MB and is refused), JTFS_ERR_ARG if jtfs_plan_prepare has not
+ * run for this plan on this device. All calls on one device share its array and it keeps
+ * the last call's contents: calls that overlap in time on one device race (serialise them,
+ * e.g. on one stream). Stage timing (jtfs_timing_*) does not apply to this call.
+ */
+#define JTFS_NOALLOC_SCRATCH_BYTES (64u << 20)
+jtfs_status jtfs_plan_prepare(jtfs_plan_t plan);
+jtfs_status jtfs_forward_noalloc(jtfs_plan_t plan, const float* x, float* S, jtfs_stream_t stream);
+
+/*
  * jtfs_backward - dx = J_S(x)^T dS, the exact adjoint of jtfs_forward at x
  * (Sec. 2.3, Eqs. 5-7, composed in reverse order; the modulus has subgradient 0 at 0).
  * With dS = 2 (S(y) - S(x)) this is grad E. dS: n_coeff_total floats; dx:

@@ -24,6 +24,7 @@ JTFS_OPT_ADAM = 2
 
 JTFS_REUSE_FORWARD = 1
 JTFS_SHARED_WORKSPACE = 2
+JTFS_NOALLOC_SCRATCH_BYTES = 64 << 20
 JTFS_N_STAGES = 19
 STAGE_NAMES = ["signal_dft", "l1_wavelet", "l1_modulus_dft", "l1_average", "order1_freq", "l2_wavelet",
                "freq_fwd", "freq_pool", "freq_dP", "freq_bwd", "order1_bwd", "l1_average_adj", "dY2_dft",
@@ -85,6 +86,8 @@ SIGNATURES = [
     ("jtfs_opt_state_floats", c_int64, [c_void_p, c_int32]),
     ("jtfs_forward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("jtfs_forward_ex", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_uint32, c_void_p]),
+    ("jtfs_plan_prepare", c_int32, [c_void_p]),
+    ("jtfs_forward_noalloc", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     ("jtfs_colored_noise", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("jtfs_backward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_uint32, c_void_p]),
     ("jtfs_metamer_step", c_int32, [c_void_p, c_void_p, c_void_p, POINTER(jtfs_opt), c_void_p, c_void_p, c_size_t,

@@ -191,6 +191,18 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
   return JTFS_OK;
 }
 
+// The arena of the current device if the plan's tables are already there (no upload).
+jtfs_status find_tables(jtfs_plan_t p, const DeviceArena** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(JTFS_ERR_HIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lock(p->mu);
+  auto it = p->dev.find(dev);
+  if (it == p->dev.end())
+    return fail(JTFS_ERR_ARG, "the plan's tables are not on this device: call jtfs_plan_prepare first");
+  *out = &it->second;
+  return JTFS_OK;
+}
+
 // Runs body(signal, stream) for every signal. A single signal, or every signal when
 // `serial` is set, runs on the caller's stream; otherwise a batch is spread over the arena's streams, which first wait for the work
 // already enqueued on the caller's stream and are waited for by it at the end (event
@@ -279,10 +291,11 @@ jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void
 }
 
 // Runs `launch` (a callable returning hipError_t) and, when timing is on, brackets it
-// with two events on `st`.
+// with two events on `st`. A null plan never times (the no-allocation path: creating
+// events is not allowed there).
 template <class F>
 hipError_t timed(jtfs_plan_t p, int stage, hipStream_t st, F launch) {
-  if (!((p->timing >> stage) & 1u)) return launch();
+  if (!p || !((p->timing >> stage) & 1u)) return launch();
   jtfs_plan_s::Mark m{stage, nullptr, nullptr};
   hipError_t e = hipEventCreate(&m.a);
   if (e != hipSuccess) return e;
@@ -682,8 +695,28 @@ const char* jtfs_last_error(void) { return g_last_error.c_str(); }
 namespace jtfs {
 // Records the detail string of a failure for jtfs_last_error (used by the decoder ABI).
 jtfs_status report(jtfs_status s, const std::string& msg) { return fail(s, msg); }
+
+jtfs_status prepare_tables(jtfs_plan_t plan) {
+  if (!plan) return fail(JTFS_ERR_ARG, "NULL plan");
+  const DeviceArena* a = nullptr;
+  return device_tables(plan, &a);
+}
+
+size_t shared_forward_bytes(jtfs_plan_t plan) { return plan->ws_fwd_shared; }
+
+// Forward of every signal in turn on `stream`, each in the one segment at ws, with the
+// plan's tables already on the device and no stage timing: enqueues kernels only.
+jtfs_status forward_prepared(jtfs_plan_t plan, const float* x, float* S, void* ws, hipStream_t stream) {
+  const DeviceArena* a = nullptr;
+  jtfs_status r = find_tables(plan, &a);
+  if (r != JTFS_OK) return r;
+  for (size_t s = 0; s < plan->sig.size(); ++s) {
+    jtfs::DevSig d = make_devsig(plan, s, a->sig[s], ws, true);
+    d.x = x + plan->x_off[s];
+    d.S = S + plan->s_off[s];
+    r = forward_signal(nullptr, d, plan->sig[s], stream);
+    if (r != JTFS_OK) return r;
+  }
+  return JTFS_OK;
+}
 }  // namespace jtfs
-
-extern "C" {
-
-}  // extern "C"

@@ -207,6 +207,19 @@ class Plan:
                                         _stream(x.device)), "jtfs_forward_ex")
         return S
 
+    def prepare(self, device="cuda") -> None:
+        """Set-up for forward_noalloc on `device` (jtfs_plan_prepare; allocates)."""
+        with torch.cuda.device(torch.device(device)):
+            L.check(L.lib().jtfs_plan_prepare(self._h), "jtfs_plan_prepare")
+
+    def forward_noalloc(self, x: torch.Tensor, S: torch.Tensor) -> torch.Tensor:
+        """S(x) with the library's static scratch as workspace (jtfs_forward_noalloc): the
+        caller passes the output; the call allocates nothing. Needs prepare() first."""
+        _require(x, self.n_samples, "x")
+        _require(S, self.n_coeff, "S")
+        L.check(L.lib().jtfs_forward_noalloc(self._h, _ptr(x), _ptr(S), _stream(x.device)), "jtfs_forward_noalloc")
+        return S
+
     def backward(self, x: torch.Tensor, dS: torch.Tensor, dx: torch.Tensor = None, ws: torch.Tensor = None,
                  reuse_forward: bool = False, shared: bool = False) -> torch.Tensor:
         """dx = J_S(x)^T dS. shared=True: the signals run one after another in a workspace
