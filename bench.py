@@ -29,6 +29,14 @@ CFG2 = dict(n=65536, J=12, Q1=12, Q2=2, J_fr=4, Q_fr=2, log2_T=13, F=24.0)
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0   # dense
 PEAK_HBM_GBS = 8000.0
+# Time-axis (FFT and pointwise) stages of one config-2 step, bracketed by events in the
+# per-stage pass, and their algorithmic bytes: the stage-boundary tensors the method
+# materialises (x, its DFT, the first-order spectra U1hat, the second-order stacks Y2, and
+# in the backward dY2, its DFT, dU1hat, the signal-spectrum gradient and dx), 136.6 MB
+# forward + 245.7 MB backward at N = 2^16, J = 12, Q1 = 12.
+TIME_AXIS_STAGES = ("signal_dft", "l1_wavelet", "l1_modulus_dft", "l1_average", "l2_wavelet", "dY2_dft",
+                    "l2_adj_gather", "dZ1_dft", "l1_adj_gather", "l1_average_adj")
+TIME_AXIS_ALGO_BYTES_CFG2 = 382.3e6
 
 
 def cpu_baseline() -> dict:
@@ -292,6 +300,13 @@ def main() -> int:
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": hbm_traffic(name, eff_tuning),
                 "algorithmic_flop_per_launch": flops, "avg_launch_ms": round(t_ms, 4), "launches": n}
 
+    t_axis_ms = sum(breakdown.get(k, (0.0, 0))[0] for k in TIME_AXIS_STAGES) / n_brk
+    ta_gbs = TIME_AXIS_ALGO_BYTES_CFG2 / (t_axis_ms * 1e-3) / 1e9
+    roofline_time_axis = {"kernels": "time-axis FFT and pointwise stages (" + ", ".join(TIME_AXIS_STAGES) + ")",
+                          "bound": "hbm", "achieved": round(ta_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                          "frac": round(ta_gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                          "algorithmic_bytes_per_step": TIME_AXIS_ALGO_BYTES_CFG2, "ms_per_step": round(t_axis_ms, 4)}
+
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -301,6 +316,7 @@ def main() -> int:
                    "global_batch": 1, "seq_len": 65536, "parallelism": "single GPU"},
         "stages_ms_per_step": {k: round(v[0] / n_brk, 4) for k, v in breakdown.items()},
         "roofline": roofline,
+        "roofline_time_axis": roofline_time_axis,
         "tuning": dict(eff_tuning, source=("autotune" if tune_ms is not None else
                                            "--tuning" if args.tuning else "default"),
                        autotune_fwd_bwd_ms=None if tune_ms is None else round(tune_ms, 4)),

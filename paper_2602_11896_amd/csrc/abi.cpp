@@ -45,6 +45,7 @@ struct SigTables {
   const jtfs::SplitTask* stasks;
   const int64_t* s_off;
   const int32_t* band_psi1;   // per first-order filter: its band (level 0, N_pad grid)
+  const int32_t* gchunks;
 };
 
 struct DeviceArena {
@@ -137,6 +138,7 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     append_bytes(buf, o, sp.segterms);
     append_bytes(buf, o, sp.stasks);
     append_bytes(buf, o, sp.band_psi1);
+    append_bytes(buf, o, sp.gchunks);
   }
   DeviceArena a;
   if (hipMalloc(&a.base, buf.size() + 256) != hipSuccess) return fail(JTFS_ERR_NOMEM, "hipMalloc of plan tables failed");
@@ -165,6 +167,7 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     t.segterms = reinterpret_cast<const jtfs::SegTerm*>(b + o[14]);
     t.stasks = reinterpret_cast<const jtfs::SplitTask*>(b + o[15]);
     t.band_psi1 = reinterpret_cast<const int32_t*>(b + o[16]);
+    t.gchunks = reinterpret_cast<const int32_t*>(b + o[17]);
     a.sig.push_back(t);
   }
   if (p->sig.size() > 1) {
@@ -252,6 +255,7 @@ jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void
   d.segs = t.segs;
   d.segterms = t.segterms;
   d.stasks = t.stasks;
+  d.gchunks = t.gchunks;
   d.s_off = t.s_off;
   d.Xh = reinterpret_cast<jtfs::c32*>(base + w.Xh);
   d.Z1 = reinterpret_cast<jtfs::c32*>(base + w.Z1);

@@ -24,6 +24,7 @@ struct DevSig {
   const int32_t* segs;      // per gather segment: first index into segterms, count
   const SegTerm* segterms;
   const SplitTask* stasks;  // two-pass transform workgroups
+  const int32_t* gchunks;   // bin-parallel gather chunks: (job, first bin) pairs
   const int64_t* s_off;     // output offset of block (group gi, filter g) at gi*n_g + g;
                             // order-1 blocks at n_groups*n_g + (index in the real list)
   // ---- per-call arrays

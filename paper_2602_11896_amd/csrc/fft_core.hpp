@@ -102,37 +102,51 @@ JTFS_HD inline int fft_radices(int log2n, int* lr) {
   return np;
 }
 
-// Read phase of one radix-2^LR pass for thread t (of tpf threads on the column whose
-// first element is tile element cbase): loads, twiddles and transforms the thread's
-// 16 / R butterflies into v[0..16). `tw` holds exp(-2 pi i q / 2^log2tw); log2p is log2
-// of the span p. cbase (a multiple of n), i < n / R and r * (n / R) share no bits, so
-// the slot of cbase + i + r * (n / R) is the XOR of their slots.
+// Twiddle table reads of one radix-2^LR pass for thread t: for each of its 16 / R
+// butterflies i, the powers w^(2^q), q < LR, of w = exp(-+2 pi i k / (R p)), k = i mod p
+// (wp[b * LR + q]). They depend only on the thread, so a kernel can issue them before
+// it waits for its data. `tw` holds exp(-2 pi i q / 2^log2tw); DIR > 0 conjugates.
 template <int DIR, int LR>
-JTFS_HD inline void stockham_compute(const c32* tile, int cbase, int log2n, int log2p, int t, int tpf,
-                                     const c32* tw, int log2tw, c32* v) {
+JTFS_HD inline void stockham_twiddles(int log2n, int log2p, int t, int tpf, const c32* tw, int log2tw, c32* wp) {
+  constexpr int NB = 16 >> LR;
+  const int pmask = (1 << log2p) - 1;
+  const int tshift = log2tw - (log2p + LR);
+  (void)log2n;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int k = (t + tpf * b) & pmask;
+#pragma unroll
+    for (int q = 0; q < LR; ++q) {
+      c32 x = tw[(k << q) << tshift];
+      if (DIR > 0) x.y = -x.y;
+      wp[b * LR + q] = x;
+    }
+  }
+}
+
+// Read phase of one radix-2^LR pass for thread t (of tpf threads on the column whose
+// first element is tile element cbase), with the twiddle powers of stockham_twiddles:
+// loads, twiddles and transforms the thread's 16 / R butterflies into v[0..16). A pass
+// of span p > 1 multiplies input r by w^r, the powers not read from the table being
+// products of those that are, in binary order (at most LR - 1 complex multiplications
+// each). cbase (a multiple of n), i < n / R and r * (n / R) share no bits, so the slot
+// of cbase + i + r * (n / R) is the XOR of their slots.
+template <int DIR, int LR>
+JTFS_HD inline void stockham_compute_tw(const c32* tile, int cbase, int log2n, int log2p, int t, int tpf,
+                                        const c32* wp, c32* v) {
   constexpr int R = 1 << LR;
   constexpr int NB = 16 >> LR;
   const int stride = (1 << log2n) >> LR;
-  const int pmask = (1 << log2p) - 1;
-  const int tshift = log2tw - (log2p + LR);
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int i = t + tpf * b;
-    const int k = i & pmask;
     const int sb = tile_slot(cbase + i);
 #pragma unroll
     for (int r = 0; r < R; ++r) v[b * R + r] = tile[sb ^ tile_slot(r * stride)];
     if (log2p > 0) {
-      // twiddles w^r, w = exp(-+2 pi i k / (R p)): the powers w^(2^q) come from the table
-      // (LR scattered loads instead of R - 1), the others are products of them in
-      // binary order (at most LR - 1 complex multiplications each)
       c32 w[R];
 #pragma unroll
-      for (int q = 0; q < LR; ++q) {
-        c32 t = tw[(k << q) << tshift];
-        if (DIR > 0) t.y = -t.y;
-        w[1 << q] = t;
-      }
+      for (int q = 0; q < LR; ++q) w[1 << q] = wp[b * LR + q];
 #pragma unroll
       for (int r = 3; r < R; ++r)
         if (r & (r - 1)) w[r] = cmul(w[r & (r - 1)], w[r & -r]);
@@ -141,6 +155,15 @@ JTFS_HD inline void stockham_compute(const c32* tile, int cbase, int log2n, int 
     }
     dft_reg<LR, DIR>(v + b * R);
   }
+}
+
+// Both of the above in one call (twiddles read at the point of use).
+template <int DIR, int LR>
+JTFS_HD inline void stockham_compute(const c32* tile, int cbase, int log2n, int log2p, int t, int tpf,
+                                     const c32* tw, int log2tw, c32* v) {
+  c32 wp[16];
+  if (log2p > 0) stockham_twiddles<DIR, LR>(log2n, log2p, t, tpf, tw, log2tw, wp);
+  stockham_compute_tw<DIR, LR>(tile, cbase, log2n, log2p, t, tpf, wp, v);
 }
 
 // Write phase of the same pass: stores the 16 results of thread t. The output index
@@ -208,22 +231,34 @@ JTFS_HD inline void split_p1_store(const SplitGeom& g, int n1_0, int e, int& slo
 // multiplications each) instead of sixteen scattered reads. tw: exp(-2 pi i q / 2^log2tw);
 // DIR > 0 conjugates.
 template <int DIR>
-JTFS_HD inline void split_p1_twiddles(const SplitGeom& g, int n1_0, int t, const c32* tw, int tshift, c32* w16) {
+JTFS_HD inline void split_p1_twiddle_bases(const SplitGeom& g, int n1_0, int t, const c32* tw, int tshift, c32* b5) {
   const int c = t & ((1 << g.log2C1) - 1), k2_0 = t >> g.log2C1;
   const int n1 = n1_0 + c;
   const int step = 256 >> g.log2C1;
-  c32 p[4];
   for (int q = 0; q < 4; ++q) {
-    p[q] = tw[((n1 * step) << q) << tshift];
-    if (DIR > 0) p[q].y = -p[q].y;
+    b5[q] = tw[((n1 * step) << q) << tshift];
+    if (DIR > 0) b5[q].y = -b5[q].y;
   }
-  w16[0] = tw[(n1 * k2_0) << tshift];
-  if (DIR > 0) w16[0].y = -w16[0].y;
+  b5[4] = tw[(n1 * k2_0) << tshift];
+  if (DIR > 0) b5[4].y = -b5[4].y;
+}
+
+// The sixteen twiddles from the five table reads above (b5[4] = w^(n1 k2_0),
+// b5[q] = w^(n1 s 2^q)).
+JTFS_HD inline void split_p1_twiddle_expand(const c32* b5, c32* w16) {
+  w16[0] = b5[4];
   for (int i = 1; i < 16; ++i) {
     const int low = i & -i;
     const int q = low == 1 ? 0 : low == 2 ? 1 : low == 4 ? 2 : 3;
-    w16[i] = cmul(w16[i - low], p[q]);
+    w16[i] = cmul(w16[i - low], b5[q]);
   }
+}
+
+template <int DIR>
+JTFS_HD inline void split_p1_twiddles(const SplitGeom& g, int n1_0, int t, const c32* tw, int tshift, c32* w16) {
+  c32 b5[5];
+  split_p1_twiddle_bases<DIR>(g, n1_0, t, tw, tshift, b5);
+  split_p1_twiddle_expand(b5, w16);
 }
 
 // pass 2 load: scratch index of element e (row base k2_0); the tile element is e itself

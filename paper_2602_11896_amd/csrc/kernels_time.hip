@@ -27,13 +27,13 @@
 namespace jtfs {
 namespace {
 
-__device__ inline float cabs(c32 z) { return sqrtf(z.x * z.x + z.y * z.y); }
+__device__ __forceinline__ float cabs(c32 z) { return sqrtf(z.x * z.x + z.y * z.y); }
 
 // Fourier subsampling by 2^shift of (src . band) onto an n-point grid, output bin q.
 // The plan guarantees that a band is not empty and spans at most two aliased blocks
 // (1 <= len <= 2 n), so both are read without a loop, at indices clamped into the band and with an absent second
 // term masked by value: the loads of several bins can be in flight together.
-__device__ inline c32 fold_gather(const c32* src, const Band& b, const float* vals, int n, int shift, int q) {
+__device__ __forceinline__ c32 fold_gather(const c32* src, const Band& b, const float* vals, int n, int shift, int q) {
   const int nmask = n - 1;
   const int d0 = (q - (b.lo & nmask)) & nmask;
   c32 acc{0.f, 0.f};
@@ -54,99 +54,70 @@ __device__ inline c32 fold_gather(const c32* src, const Band& b, const float* va
   return c32{acc.x * sc, acc.y * sc};
 }
 
-// Adjoint gather: sum over terms of band[m] * src_t[m mod len_t], output bin m; only the
-// terms whose band meets m's 512-bin segment are visited. Every band is non-empty, so a
-// term whose band misses m reads the band at a clamped index and is masked by value: no
-// branch, so the loads of several terms can be in flight together.
-__device__ inline void term_add(const DevSig& s, const c32* base, const SegTerm& g, int m, c32& acc) {
-  int d = m - g.lo;
-  if (d < 0) d += g.L;
-  const bool in = d < g.len;
-  const float h = s.bandvals[g.off + (in ? d : 0)];
-  const c32 v = base[g.src + (m & (g.src_len - 1))];
-  const float hm = in ? h : 0.f;
-  acc.x += v.x * hm;
-  acc.y += v.y * hm;
-}
-
-// seg0 = the row's first segment. When the whole wave's bins lie in one segment (single-
-// tile rows of 64 bins or more, the bin-parallel gather), its terms come by scalar loads.
-__device__ inline c32 term_gather(const DevSig& s, const c32* base, int seg0, int m) {
-  c32 acc{0.f, 0.f};
-  const int sg = seg0 + (m >> 9);
-  const int sgu = __builtin_amdgcn_readfirstlane(sg);
-  if (__all(sg == sgu)) {
-    const int first = s.segs[2 * sgu], count = s.segs[2 * sgu + 1];
-#pragma unroll 4
-    for (int i = 0; i < count; ++i) term_add(s, base, s.segterms[first + i], m, acc);
-  } else {
-    const int first = s.segs[2 * sg], count = s.segs[2 * sg + 1];
-#pragma unroll 4
-    for (int i = 0; i < count; ++i) term_add(s, base, s.segterms[first + i], m, acc);
-  }
-  return acc;
-}
-
 template <int ST>
 struct Ops;
 
+// Each stage's Ops: transform direction DIR, the element load and store, and LB, how
+// many element loads a thread keeps in flight before storing them to LDS (16: all of
+// them; fewer where one element is itself a gather of several loads, to bound registers).
 template <>
 struct Ops<ST_XHAT> {
-  static constexpr int DIR = -1;
-  __device__ static c32 load(const DevSig& s, const RowJob&, const Band&, int idx) {
+  static constexpr int DIR = -1, LB = 16;
+  __device__ __forceinline__ static c32 load(const DevSig& s, const RowJob&, const Band&, int idx) {
     const int j = idx - s.pad_left;
     return c32{(j >= 0 && j < s.N) ? s.x[j] : 0.f, 0.f};
   }
-  __device__ static void store(const DevSig& s, const RowJob&, int idx, c32 v) { s.Xh[idx] = v; }
+  __device__ __forceinline__ static void store(const DevSig& s, const RowJob&, int idx, c32 v) { s.Xh[idx] = v; }
 };
 
 template <>
 struct Ops<ST_L1Z> {
-  static constexpr int DIR = +1;
-  __device__ static c32 load(const DevSig& s, const RowJob& j, const Band& b, int idx) {
+  static constexpr int DIR = +1, LB = 8;
+  __device__ __forceinline__ static c32 load(const DevSig& s, const RowJob& j, const Band& b, int idx) {
     return fold_gather(s.Xh, b, s.bandvals, j.n, j.shift, idx);
   }
-  __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.Z1[j.dst + idx] = v; }
+  __device__ __forceinline__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.Z1[j.dst + idx] = v; }
 };
 
 template <>
 struct Ops<ST_L1UH> {
-  static constexpr int DIR = -1;
-  __device__ static c32 load(const DevSig& s, const RowJob& j, const Band&, int idx) {
+  static constexpr int DIR = -1, LB = 16;
+  __device__ __forceinline__ static c32 load(const DevSig& s, const RowJob& j, const Band&, int idx) {
     return c32{cabs(s.Z1[j.src + idx]), 0.f};
   }
-  __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.U1h[j.dst + idx] = v; }
+  __device__ __forceinline__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.U1h[j.dst + idx] = v; }
 };
 
 template <>
 struct Ops<ST_L2Y> {
-  static constexpr int DIR = +1;
-  __device__ static c32 load(const DevSig& s, const RowJob& j, const Band& b, int idx) {
+  static constexpr int DIR = +1, LB = 8;
+  __device__ __forceinline__ static c32 load(const DevSig& s, const RowJob& j, const Band& b, int idx) {
     return fold_gather(s.U1h + j.src, b, s.bandvals, j.n, j.shift, idx);
   }
-  __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.Y2[j.dst + idx] = v; }
+  __device__ __forceinline__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.Y2[j.dst + idx] = v; }
 };
 
 template <>
 struct Ops<ST_BYH> {
-  static constexpr int DIR = -1;
-  __device__ static c32 load(const DevSig& s, const RowJob& j, const Band&, int idx) { return s.dYpart[j.src + idx]; }
-  __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.dYh[j.dst + idx] = v; }
+  static constexpr int DIR = -1, LB = 16;
+  __device__ __forceinline__ static c32 load(const DevSig& s, const RowJob& j, const Band&, int idx) { return s.dYpart[j.src + idx]; }
+  __device__ __forceinline__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.dYh[j.dst + idx] = v; }
 };
 
 template <>
 struct Ops<ST_BU> {
-  static constexpr int DIR = +1;
-  __device__ static c32 load(const DevSig& s, const RowJob& j, const Band&, int idx) {
-    return term_gather(s, s.dYh, j.t0, idx);
+  static constexpr int DIR = +1, LB = 16;
+  // the gather itself runs beforehand in k_seg_gather, into the row's slot of dZh
+  __device__ __forceinline__ static c32 load(const DevSig& s, const RowJob& j, const Band&, int idx) {
+    return s.dZh[j.dst + idx];
   }
-  __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.dU1[j.dst + idx] = v.x; }
+  __device__ __forceinline__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.dU1[j.dst + idx] = v.x; }
 };
 
 template <>
 struct Ops<ST_BZH> {
-  static constexpr int DIR = -1;
-  __device__ static c32 load(const DevSig& s, const RowJob& j, const Band&, int idx) {
+  static constexpr int DIR = -1, LB = 16;
+  __device__ __forceinline__ static c32 load(const DevSig& s, const RowJob& j, const Band&, int idx) {
     // u times the phase z / |z| (rsq, within 1 ulp; subgradient 0 where |z| vanishes,
     // below 1.1e-19 the square underflows anyway)
     const float u = s.dU1[j.src + idx];
@@ -155,165 +126,314 @@ struct Ops<ST_BZH> {
     const float r = m2 >= 1.17549435e-38f ? u * __builtin_amdgcn_rsqf(m2) : 0.f;
     return c32{z.x * r, z.y * r};
   }
-  __device__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.dZh[j.dst + idx] = v; }
+  __device__ __forceinline__ static void store(const DevSig& s, const RowJob& j, int idx, c32 v) { s.dZh[j.dst + idx] = v; }
 };
 
 template <>
 struct Ops<ST_BX> {
-  static constexpr int DIR = +1;
-  // the gather itself runs beforehand in k_bx_gather, over the whole spectrum at once
-  __device__ static c32 load(const DevSig& s, const RowJob&, const Band&, int idx) { return s.dXh[idx]; }
-  __device__ static void store(const DevSig& s, const RowJob&, int idx, c32 v) {
+  static constexpr int DIR = +1, LB = 16;
+  // the gather itself runs beforehand in k_seg_gather, over the whole spectrum at once
+  __device__ __forceinline__ static c32 load(const DevSig& s, const RowJob&, const Band&, int idx) { return s.dXh[idx]; }
+  __device__ __forceinline__ static void store(const DevSig& s, const RowJob&, int idx, c32 v) {
     const int k = idx - s.pad_left;
     if (k >= 0 && k < s.N) s.dx[k] = v.x;
   }
 };
 
-// Gather of the first-order adjoint onto the padded signal spectrum,
-//   dXhat[m] = sum_n1 psi1_n1[m] dZ1hat_n1[m mod L1_n1],
-// one thread per bin (the inverse DFT of stage BX reads the result).
-__global__ __launch_bounds__(256) void k_bx_gather(DevSig s, int job) {
-  const int m = blockIdx.x * 256 + threadIdx.x;
-  if (m >= s.N_pad) return;
-  s.dXh[m] = term_gather(s, s.dZh, s.jobs[job].t0, m);
-}
-
-// One radix-2^LR pass over the tile (two barriers: all reads before any write).
-template <int DIR, int LR>
-__device__ inline void tile_pass(c32* tile, int cbase, int log2n, int log2p, int t, int tpf, const c32* tw,
-                                 int log2tw) {
-  c32 v[16];
-  stockham_compute<DIR, LR>(tile, cbase, log2n, log2p, t, tpf, tw, log2tw, v);
-  __syncthreads();
-  stockham_store<LR>(tile, cbase, log2p, t, tpf, v);
-  __syncthreads();
-}
-
-// In-place FFT of the 4096 / n columns of the tile (natural order in and out; element
-// e at LDS slot tile_slot(e)).
-template <int DIR>
-__device__ void fft_tile(c32* lds, int log2n, const c32* tw, int log2tw) {
-  const int tpf = 1 << (log2n - 4);
-  const int t = threadIdx.x & (tpf - 1);
-  const int cbase = (threadIdx.x >> (log2n - 4)) << log2n;
-  int lr[8];
-  const int np = fft_radices(log2n, lr);
-  int log2p = 0;
-  for (int p = 0; p < np; ++p) {
-    switch (lr[p]) {
-      case 1: tile_pass<DIR, 1>(lds, cbase, log2n, log2p, t, tpf, tw, log2tw); break;
-      case 2: tile_pass<DIR, 2>(lds, cbase, log2n, log2p, t, tpf, tw, log2tw); break;
-      case 3: tile_pass<DIR, 3>(lds, cbase, log2n, log2p, t, tpf, tw, log2tw); break;
-      default: tile_pass<DIR, 4>(lds, cbase, log2n, log2p, t, tpf, tw, log2tw); break;
+// Bin-parallel adjoint gathers, run before the stage's inverse transforms:
+//  BU: dU1hat_n1[m] = sum_n2 psi2_n2^(k1)[m] dY2hat_(n1,n2)[m mod L2] (+ the phi_T term),
+//      into the row's slot in dZh (free until stage BZH writes it);
+//  BX: dXhat[m] = sum_n1 psi1_n1[m] dZ1hat_n1[m mod L1_n1].
+// One thread per output bin, one chunk of up to 256 bins of one row per workgroup (the
+// plan's chunk list). A wave's 64 bins lie in one 512-bin segment, so its term records
+// come by scalar loads. Terms go in batches of eight: the batch's records, then its
+// sixteen element loads, then the sums (a band that misses the bin is read at a clamped
+// index and masked by value: no branch).
+template <int ST>
+__global__ __launch_bounds__(256) void k_seg_gather(DevSig s, int ch0) {
+  const int c = ch0 + blockIdx.x;
+  const int job = s.gchunks[2 * c];
+  const int m = s.gchunks[2 * c + 1] + threadIdx.x;
+  const RowJob j = s.jobs[job];
+  if (m >= j.n) return;
+  const c32* base = ST == ST_BU ? s.dYh : s.dZh;
+  c32 acc{0.f, 0.f};
+  const int sg = __builtin_amdgcn_readfirstlane(j.t0 + (m >> 9));
+  const int first = s.segs[2 * sg], count = s.segs[2 * sg + 1];
+  for (int i0 = 0; i0 < count; i0 += 8) {
+    SegTerm g[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) g[k] = s.segterms[first + min(i0 + k, count - 1)];
+    float h[8];
+    c32 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int d = m - g[k].lo;
+      if (d < 0) d += g[k].L;
+      const bool in = d < g[k].len && i0 + k < count;
+      const float hv = s.bandvals[g[k].off + (in ? d : 0)];
+      h[k] = in ? hv : 0.f;
+      v[k] = base[g[k].src + (m & (g[k].src_len - 1))];
     }
-    log2p += lr[p];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      acc.x += v[k].x * h[k];
+      acc.y += v[k].y * h[k];
+    }
+  }
+  if constexpr (ST == ST_BU)
+    s.dZh[j.dst + m] = acc;
+  else
+    s.dXh[m] = acc;
+}
+
+// Twiddle powers of every pass of a 2^LOG2N-point tile transform for this thread (pass
+// PI has span 2^(4 PI) and radix min(16, 2^(LOG2N - 4 PI)); pass 0 needs none), read
+// before the data so that their latency overlaps the element loads.
+template <int LOG2N>
+struct TileTw {
+  static constexpr int NP = (LOG2N + 3) / 4;
+  c32 w[NP][8];
+};
+
+template <int DIR, int LOG2N, int PI>
+__device__ __forceinline__ void tile_twiddles_rec(TileTw<LOG2N>& f, int t, const c32* tw, int log2tw) {
+  if constexpr (PI < TileTw<LOG2N>::NP) {
+    constexpr int LOG2P = 4 * PI;
+    constexpr int LR = (LOG2N - LOG2P) >= 4 ? 4 : (LOG2N - LOG2P);
+    if constexpr (PI > 0) stockham_twiddles<DIR, LR>(LOG2N, LOG2P, t, (1 << LOG2N) >> 4, tw, log2tw, f.w[PI]);
+    tile_twiddles_rec<DIR, LOG2N, PI + 1>(f, t, tw, log2tw);
   }
 }
 
-// One workgroup per task: `count` rows of one length, all in one 4096-element tile. The
-// rows' jobs and bands are staged in LDS first (count <= 4096 / 16), so that each element
-// reads only its data from global memory.
-constexpr int kMaxTileRows = 256;
+template <int DIR, int LOG2N>
+__device__ __forceinline__ TileTw<LOG2N> tile_twiddles(const c32* tw, int log2tw) {
+  TileTw<LOG2N> f;
+  tile_twiddles_rec<DIR, LOG2N, 0>(f, threadIdx.x & ((1 << (LOG2N - 4)) - 1), tw, log2tw);
+  return f;
+}
+
+// Pass PI over the tile (two barriers: all reads before any write). The length and span
+// are compile-time constants, so every index folds to a constant offset from the
+// thread's base slot.
+template <int DIR, int LOG2N, int PI>
+__device__ __forceinline__ void tile_passes_ct(c32* tile, int cbase, int t, const TileTw<LOG2N>& f) {
+  if constexpr (PI < TileTw<LOG2N>::NP) {
+    constexpr int LOG2P = 4 * PI;
+    constexpr int LR = (LOG2N - LOG2P) >= 4 ? 4 : (LOG2N - LOG2P);
+    constexpr int TPF = (1 << LOG2N) >> 4;
+    c32 v[16];
+    stockham_compute_tw<DIR, LR>(tile, cbase, LOG2N, LOG2P, t, TPF, f.w[PI], v);
+    __syncthreads();
+    stockham_store<LR>(tile, cbase, LOG2P, t, TPF, v);
+    __syncthreads();
+    tile_passes_ct<DIR, LOG2N, PI + 1>(tile, cbase, t, f);
+  }
+}
+
+// In-place FFT of the 4096 / 2^LOG2N columns of the tile (natural order in and out;
+// element e at LDS slot tile_slot(e)); the caller has synchronised after its writes.
+template <int DIR, int LOG2N>
+__device__ __forceinline__ void fft_tile_ct(c32* lds, const TileTw<LOG2N>& f) {
+  const int t = threadIdx.x & ((1 << (LOG2N - 4)) - 1);
+  const int cbase = (threadIdx.x >> (LOG2N - 4)) << LOG2N;
+  tile_passes_ct<DIR, LOG2N, 0>(lds, cbase, t, f);
+}
+
+// Row of tile element e for rows of 2^LOG2N points. From 64 points on, the 64 lanes of
+// a wave lie in one row (e = threadIdx.x + 256 i), so the row is wave-uniform and its job
+// and band records come through scalar loads.
+template <int LOG2N>
+__device__ __forceinline__ int tile_row(int e) {
+  const int row = e >> LOG2N;
+  if constexpr (LOG2N >= 6) return __builtin_amdgcn_readfirstlane(row);
+  return row;
+}
 
 template <int ST>
-__device__ void rows_body(const DevSig& s, c32* lds, RowJob* tj, Band* tb, int task) {
+__device__ __forceinline__ Band job_band(const DevSig& s, const RowJob& j) {
+  return j.band >= 0 ? s.bands[j.band] : Band{0, 0, 0, 0, 0};
+}
+
+// Single-pass task: `count` rows of 2^LOG2N points in one tile. All sixteen element loads
+// of a thread are issued before any is stored to LDS, and all sixteen results are read
+// from LDS before the first store to global memory.
+template <int ST, int LOG2N>
+__device__ __forceinline__ void rows_body_ct(const DevSig& s, c32* lds, const RowTask& tk) {
   using O = Ops<ST>;
+  constexpr int N = 1 << LOG2N;
+  const int count = tk.count;
+  const TileTw<LOG2N> twp = tile_twiddles<O::DIR, LOG2N>(s.tw, s.log2_Npad);
+  // rows under 64 points: each lane reads its own job record, so fewer loads in flight
+  constexpr int LB = LOG2N >= 6 ? O::LB : (O::LB < 4 ? O::LB : 4);
+#pragma unroll
+  for (int i0 = 0; i0 < 16; i0 += LB) {
+    c32 vb[LB];
+#pragma unroll
+    for (int b = 0; b < LB; ++b) {
+      // (elements past the last row load from it and are zeroed by value)
+      const int e = threadIdx.x + 256 * (i0 + b);
+      const int row = tile_row<LOG2N>(e);
+      const int rc = min(row, count - 1);
+      const RowJob j = s.jobs[tk.job0 + rc];
+      const c32 x = O::load(s, j, job_band<ST>(s, j), e & (N - 1));
+      vb[b] = row < count ? x : c32{0.f, 0.f};
+    }
+#pragma unroll
+    for (int b = 0; b < LB; ++b) lds[tile_slot(threadIdx.x + 256 * (i0 + b))] = vb[b];
+  }
+  __syncthreads();
+  c32 v[16];
+  fft_tile_ct<O::DIR, LOG2N>(lds, twp);
+  const float sc = O::DIR > 0 ? 1.0f / N : 1.0f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = lds[tile_slot(threadIdx.x + 256 * i)];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    const int row = tile_row<LOG2N>(e);
+    if (row < count) O::store(s, s.jobs[tk.job0 + row], e & (N - 1), cscale(v[i], sc));
+  }
+}
+
+template <int ST>
+__device__ __forceinline__ void rows_body(const DevSig& s, c32* lds, int task) {
   const RowTask tk = s.tasks[task];
-  const int log2n = tk.log2n;
-  const int n = 1 << log2n;
-  const int count = min(tk.count, kMaxTileRows);
-  for (int r = threadIdx.x; r < count; r += 256) {
-    const RowJob j = s.jobs[tk.job0 + r];
-    tj[r] = j;
-    tb[r] = j.band >= 0 ? s.bands[j.band] : Band{0, 0, 0, 0, 0};
-  }
-  __syncthreads();
-#pragma unroll 4
-  for (int i = 0; i < 16; ++i) {
-    // (elements past the last row load from it and are zeroed by value: no branch, so
-    // the loads of consecutive elements can be in flight together)
-    const int e = threadIdx.x + 256 * i;
-    const int row = e >> log2n;
-    const int rc = min(row, count - 1);
-    const c32 v = O::load(s, tj[rc], tb[rc], e & (n - 1));
-    lds[tile_slot(e)] = row < count ? v : c32{0.f, 0.f};
-  }
-  __syncthreads();
-  fft_tile<O::DIR>(lds, log2n, s.tw, s.log2_Npad);
-  const float sc = O::DIR > 0 ? 1.0f / n : 1.0f;
-#pragma unroll 4
-  for (int i = 0; i < 16; ++i) {
-    const int e = threadIdx.x + 256 * i;
-    const int row = e >> log2n;
-    if (row < count) O::store(s, tj[row], e & (n - 1), cscale(lds[tile_slot(e)], sc));
+  switch (tk.log2n) {
+    case 4: rows_body_ct<ST, 4>(s, lds, tk); break;
+    case 5: rows_body_ct<ST, 5>(s, lds, tk); break;
+    case 6: rows_body_ct<ST, 6>(s, lds, tk); break;
+    case 7: rows_body_ct<ST, 7>(s, lds, tk); break;
+    case 8: rows_body_ct<ST, 8>(s, lds, tk); break;
+    case 9: rows_body_ct<ST, 9>(s, lds, tk); break;
+    case 10: rows_body_ct<ST, 10>(s, lds, tk); break;
+    case 11: rows_body_ct<ST, 11>(s, lds, tk); break;
+    default: rows_body_ct<ST, 12>(s, lds, tk); break;
   }
 }
 
-// Two-pass transforms: every row of a stage, of any length above 4096, in one launch per
-// pass; each workgroup reads its row, length, block and scratch offset from the task list.
-template <int ST>
-__device__ void split1_body(const DevSig& s, c32* lds, int task) {
+// Pass 1 of a two-pass row (n = A B, B = 2^LOG2B): C1 = 4096 / B consecutive columns n1,
+// each a B-point transform over n2, twiddled by w_n^(n1 k2) and written to scratch.
+template <int ST, int LOG2B>
+__device__ __forceinline__ void split1_ct(const DevSig& s, c32* lds, const SplitTask& tk) {
   using O = Ops<ST>;
-  const SplitTask tk = s.stasks[task];
-  const int log2n = tk.log2n;
-  const SplitGeom g = split_geom(log2n, tk.log2A);
+  const SplitGeom g = split_geom(LOG2B + tk.log2A, tk.log2A);
   const RowJob job = s.jobs[tk.job];
-  const Band band = job.band >= 0 ? s.bands[job.band] : Band{0, 0, 0, 0, 0};
+  const Band band = job_band<ST>(s, job);
   const int n1_0 = tk.blk << g.log2C1;
-#pragma unroll 4
-  for (int i = 0; i < 16; ++i) {
-    int idx, slot;
-    split_p1_load(g, n1_0, threadIdx.x + 256 * i, idx, slot);
-    lds[tile_slot(slot)] = O::load(s, job, band, idx);
+  const TileTw<LOG2B> twp = tile_twiddles<O::DIR, LOG2B>(s.tw, s.log2_Npad);
+  c32 b5[5];
+  split_p1_twiddle_bases<O::DIR>(g, n1_0, threadIdx.x, s.tw, s.log2_Npad - g.log2n, b5);
+  constexpr int LB = O::LB;
+#pragma unroll
+  for (int i0 = 0; i0 < 16; i0 += LB) {
+    c32 vb[LB];
+#pragma unroll
+    for (int b = 0; b < LB; ++b) {
+      int idx, slot;
+      split_p1_load(g, n1_0, threadIdx.x + 256 * (i0 + b), idx, slot);
+      vb[b] = O::load(s, job, band, idx);
+    }
+#pragma unroll
+    for (int b = 0; b < LB; ++b) {
+      int idx, slot;
+      split_p1_load(g, n1_0, threadIdx.x + 256 * (i0 + b), idx, slot);
+      lds[tile_slot(slot)] = vb[b];
+    }
   }
   __syncthreads();
-  fft_tile<O::DIR>(lds, g.log2B, s.tw, s.log2_Npad);
+  c32 v[16];
+  fft_tile_ct<O::DIR, LOG2B>(lds, twp);
   c32* scr = s.scr + tk.scr;
-  const int tshift = s.log2_Npad - log2n;
   c32 w16[16];
-  split_p1_twiddles<O::DIR>(g, n1_0, threadIdx.x, s.tw, tshift, w16);
+  split_p1_twiddle_expand(b5, w16);
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     int slot, sidx, te;
     split_p1_store(g, n1_0, threadIdx.x + 256 * i, slot, sidx, te);
-    scr[sidx] = cmul(lds[tile_slot(slot)], w16[i]);
+    v[i] = cmul(lds[tile_slot(slot)], w16[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    int slot, sidx, te;
+    split_p1_store(g, n1_0, threadIdx.x + 256 * i, slot, sidx, te);
+    scr[sidx] = v[i];
+  }
+}
+
+template <int ST>
+__device__ __forceinline__ void split1_body(const DevSig& s, c32* lds, int task) {
+  const SplitTask tk = s.stasks[task];
+  switch (tk.log2n - tk.log2A) {
+    case 4: split1_ct<ST, 4>(s, lds, tk); break;
+    case 5: split1_ct<ST, 5>(s, lds, tk); break;
+    case 6: split1_ct<ST, 6>(s, lds, tk); break;
+    case 7: split1_ct<ST, 7>(s, lds, tk); break;
+    case 8: split1_ct<ST, 8>(s, lds, tk); break;
+    case 9: split1_ct<ST, 9>(s, lds, tk); break;
+    case 10: split1_ct<ST, 10>(s, lds, tk); break;
+    case 11: split1_ct<ST, 11>(s, lds, tk); break;
+    default: split1_ct<ST, 12>(s, lds, tk); break;
   }
 }
 
 // First launch of a stage: the short-row tasks (whole rows in one tile), then pass 1 of
 // every long row; the two sets are independent, so they share one launch.
 template <int ST>
-__global__ __launch_bounds__(256) void k_fft_stage1(DevSig s, int task0, int ntask, int split0) {
+__global__ __launch_bounds__(256, 3) void k_fft_stage1(DevSig s, int task0, int ntask, int split0) {
   __shared__ c32 lds[4096];
-  __shared__ RowJob tj[kMaxTileRows];
-  __shared__ Band tb[kMaxTileRows];
   if (static_cast<int>(blockIdx.x) < ntask)
-    rows_body<ST>(s, lds, tj, tb, task0 + blockIdx.x);
+    rows_body<ST>(s, lds, task0 + blockIdx.x);
   else
     split1_body<ST>(s, lds, split0 + blockIdx.x - ntask);
+}
+
+// Pass 2 of a two-pass row (A = 2^LOG2A): C2 = 4096 / A consecutive scratch rows k2, each
+// an A-point transform over n1, giving X[k2 + B k1].
+template <int ST, int LOG2A>
+__device__ __forceinline__ void split2_ct(const DevSig& s, c32* lds, const SplitTask& tk) {
+  using O = Ops<ST>;
+  const SplitGeom g = split_geom(tk.log2n, LOG2A);
+  const RowJob job = s.jobs[tk.job];
+  const int k2_0 = tk.blk << g.log2C2;
+  const c32* scr = s.scr + tk.scr;
+  const TileTw<LOG2A> twp = tile_twiddles<O::DIR, LOG2A>(s.tw, s.log2_Npad);
+  c32 v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = scr[split_p2_load(g, k2_0, threadIdx.x + 256 * i)];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) lds[tile_slot(threadIdx.x + 256 * i)] = v[i];
+  __syncthreads();
+  fft_tile_ct<O::DIR, LOG2A>(lds, twp);
+  const float sc = O::DIR > 0 ? 1.0f / static_cast<float>(1 << g.log2n) : 1.0f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    int slot, oidx;
+    split_p2_store(g, k2_0, threadIdx.x + 256 * i, slot, oidx);
+    v[i] = lds[tile_slot(slot)];
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    int slot, oidx;
+    split_p2_store(g, k2_0, threadIdx.x + 256 * i, slot, oidx);
+    O::store(s, job, oidx, cscale(v[i], sc));
+  }
 }
 
 template <int ST>
 __global__ __launch_bounds__(256) void k_fft_split2(DevSig s, int task0) {
   __shared__ c32 lds[4096];
-  using O = Ops<ST>;
   const SplitTask tk = s.stasks[task0 + blockIdx.x];
-  const int log2n = tk.log2n;
-  const SplitGeom g = split_geom(log2n, tk.log2A);
-  const RowJob job = s.jobs[tk.job];
-  const int k2_0 = tk.blk << g.log2C2;
-  const c32* scr = s.scr + tk.scr;
-  for (int i = 0; i < 16; ++i) {
-    const int e = threadIdx.x + 256 * i;
-    lds[tile_slot(e)] = scr[split_p2_load(g, k2_0, e)];
-  }
-  __syncthreads();
-  fft_tile<O::DIR>(lds, g.log2A, s.tw, s.log2_Npad);
-  const float sc = O::DIR > 0 ? 1.0f / static_cast<float>(1 << log2n) : 1.0f;
-  for (int i = 0; i < 16; ++i) {
-    int slot, oidx;
-    split_p2_store(g, k2_0, threadIdx.x + 256 * i, slot, oidx);
-    O::store(s, job, oidx, cscale(lds[tile_slot(slot)], sc));
+  switch (tk.log2A) {
+    case 4: split2_ct<ST, 4>(s, lds, tk); break;
+    case 5: split2_ct<ST, 5>(s, lds, tk); break;
+    case 6: split2_ct<ST, 6>(s, lds, tk); break;
+    case 7: split2_ct<ST, 7>(s, lds, tk); break;
+    case 8: split2_ct<ST, 8>(s, lds, tk); break;
+    case 9: split2_ct<ST, 9>(s, lds, tk); break;
+    case 10: split2_ct<ST, 10>(s, lds, tk); break;
+    case 11: split2_ct<ST, 11>(s, lds, tk); break;
+    default: split2_ct<ST, 12>(s, lds, tk); break;
   }
 }
 
@@ -365,10 +485,12 @@ __global__ __launch_bounds__(256) void k_ds1h(DevSig s) {
 
 template <int ST, bool GATHER = true>
 hipError_t run_stage_t(const DevSig& s, const SigPlan& p, hipStream_t st) {
-  if (ST == ST_BX && GATHER) {
-    hipLaunchKernelGGL(k_bx_gather, dim3((p.N_pad + 255) / 256), dim3(256), 0, st, s, p.bx_job);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  if constexpr (ST == ST_BU || (ST == ST_BX && GATHER)) {
+    if (p.gchn[ST] > 0) {
+      hipLaunchKernelGGL(k_seg_gather<ST>, dim3(p.gchn[ST]), dim3(256), 0, st, s, p.gch0[ST]);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
   if (p.ntask[ST] + p.split1_n[ST] > 0) {
     hipLaunchKernelGGL(k_fft_stage1<ST>, dim3(p.ntask[ST] + p.split1_n[ST]), dim3(256), 0, st, s, p.task0[ST],

@@ -681,6 +681,8 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   // the others workgroup tasks of one launch per stage (4096 / n rows per workgroup).
   auto emit = [&](int stage, std::vector<RowJob> js) {
     std::stable_sort(js.begin(), js.end(), [](const RowJob& a, const RowJob& b) { return a.n > b.n; });
+    p.task_jobs0[stage] = static_cast<int32_t>(p.jobs.size());
+    p.task_jobs1[stage] = static_cast<int32_t>(p.jobs.size() + js.size());
     p.task0[stage] = static_cast<int32_t>(p.tasks.size());
     int64_t stage_scr = 0;
     size_t i = 0;
@@ -814,6 +816,18 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     }
     j.t0 = seg0;
     j.t1 = seg0 + nseg;
+  }
+  // Chunks of the bin-parallel gathers: every row of the stage, 256 bins at a time.
+  for (int st : {ST_BU, ST_BX}) {
+    p.gch0[st] = static_cast<int32_t>(p.gchunks.size() / 2);
+    const int32_t j0 = st == ST_BX ? p.bx_job : p.task_jobs0[st];
+    const int32_t j1 = st == ST_BX ? p.bx_job + 1 : p.task_jobs1[st];
+    for (int32_t j = j0; j < j1; ++j)
+      for (int32_t m0 = 0; m0 < p.jobs[j].n; m0 += 256) {
+        p.gchunks.push_back(j);
+        p.gchunks.push_back(m0);
+      }
+    p.gchn[st] = static_cast<int32_t>(p.gchunks.size() / 2) - p.gch0[st];
   }
   p.s1_job0 = static_cast<int32_t>(p.jobs.size());
   for (int32_t n1 = 0; n1 < N1; ++n1) {

@@ -109,6 +109,11 @@ struct SigPlan {
   // pass-2 launch, each row with its own scratch (tasks of stage st: [split0, split0 + nsplit)
   // for pass 1, then the same count shifted by nsplit1 for pass 2).
   std::vector<SplitTask> stasks;
+  // Bin-parallel adjoint gathers (stages BU and BX): chunks of up to 256 output bins of
+  // one row, pairs (job, first bin); the chunks of stage st are [gch0[st], gch0[st] + gchn[st]).
+  std::vector<int32_t> gchunks;
+  int32_t gch0[ST_COUNT] = {0}, gchn[ST_COUNT] = {0};
+  int32_t task_jobs0[ST_COUNT] = {0}, task_jobs1[ST_COUNT] = {0};   // each stage's jobs
   int32_t bx_job = -1;   // the job of the final gather onto the padded signal spectrum
   int32_t split1_0[ST_COUNT] = {0}, split1_n[ST_COUNT] = {0};
   int32_t split2_0[ST_COUNT] = {0}, split2_n[ST_COUNT] = {0};
