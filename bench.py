@@ -39,63 +39,155 @@ TIME_AXIS_STAGES = ("signal_dft", "l1_wavelet", "l1_modulus_dft", "l1_average", 
 TIME_AXIS_ALGO_BYTES_CFG2 = 382.3e6
 
 
-def cpu_baseline() -> dict:
-    """The FP64 oracle timed on this host on a bounded sample of the config-2 iteration.
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
-    An oracle forward + backward of config 2 takes about a minute, so it is timed in parts:
-    the first layer and order-1 paths (forward and adjoint) exactly, and the second-order
-    groups through three sampled groups (one each with j2 = 2, 3, 4; about 15 s of CPU
-    work in all). Every second-order group does the same work per time sample (a
-    frequential DFT of N_fr points and the filters of the frequential list per column), so
-    a group's cost is taken as proportional to its length L2 and the sampled groups' cost
-    per sample is applied to all groups.
-    """
+
+# State a forked pool worker inherits (plan, first-layer spectra, filter cache, dS).
+_ORACLE_POOL = {}
+
+
+def _oracle_group_task(n2):
+    """Forward and adjoint of one second-order group in a pool worker (one thread)."""
     import numpy as np
-
-    import jtfs_inputs as ji
+    from threadpoolctl import threadpool_limits
     from oracle import fftroute
-    from oracle.plan import make_plan
+    st = _ORACLE_POOL
+    op, U1h, fc, dS = st["op"], st["U1h"], st["fc"], st["dS"]
+    grp = next(g for g in op.groups if g.n2 == n2)
+    with threadpool_limits(limits=1):
+        S = np.zeros(op.n_coeff)
+        fftroute.order2_group(op, grp, U1h, fc, S)
+        rows = [np.zeros(U1h[n1].shape[0]) for n1 in range(grp.K)]
+        fftroute.order2_group_adjoint(op, grp, U1h, fc, dS, rows)
+    return n2, rows
 
-    op = make_plan(CFG2["n"], CFG2["J"], CFG2["Q1"], CFG2["Q2"], CFG2["J_fr"], CFG2["Q_fr"], CFG2["log2_T"],
-                   CFG2["F"])
-    y = ji.white_noise_like(ji.config2_signal(2), 3)
-    fc = fftroute.FilterCache(op)
-    samples = [next(g for g in op.groups if g.j2 == j) for j in (2, 3, 4)]
-    picked = {g.n2 for g in samples}
-    dS_group = np.zeros(op.n_coeff)
-    for b in op.blocks:
-        if b.order == 2 and b.n2 in picked:
-            dS_group[b.offset: b.offset + b.n_lambda * b.n_frames] = 1.0
+
+def _oracle_iteration_parts(op, y, dS, fc, groups, pool):
+    """One oracle forward + backward split as the parallel oracle runs it: the first layer
+    and the order-1 paths (forward and adjoint) on the calling thread, the listed
+    second-order groups on `pool` (or in turn if None). Returns (serial s, groups s)."""
+    import numpy as np
+    from oracle import fftroute
+    t0 = time.perf_counter()
+    cache = fftroute.first_layer_cache(op, y, fc)
+    S = np.zeros(op.n_coeff)
+    fftroute.order1_blocks(op, cache["Ah"], fc, S)
     dS_o1 = np.zeros(op.n_coeff)
     for b in op.blocks:
         if b.order == 1:
-            dS_o1[b.offset: b.offset + b.n_lambda * b.n_frames] = 1.0
+            dS_o1[b.offset: b.offset + b.n_lambda * b.n_frames] = dS[b.offset: b.offset + b.n_lambda * b.n_frames]
+    dx = fftroute.backward(op, y, dS_o1, cache=cache)       # first layer + order-1 adjoint
+    t_serial = time.perf_counter() - t0
+    _ORACLE_POOL.update(op=op, U1h=cache["U1h"], fc=fc, dS=dS)
+    t0 = time.perf_counter()
+    if pool is None:
+        out = [_oracle_group_task(n2) for n2 in groups]
+    else:
+        out = pool.map(_oracle_group_task, groups)
+    t_groups = time.perf_counter() - t0
+    del dx, out
+    return t_serial, t_groups
 
+
+def cpu_baseline(full: bool = False) -> dict:
+    """The FP64 oracle timed on this host's cores, in two settings: one thread, and every
+    core of the process's affinity with a fork pool over second-order (n2) groups.
+
+    Config 2 (one metamer iteration = forward + backward): the first layer and the order-1
+    paths, which the pool does not split, always run in full on one thread. The groups: in
+    the default bounded run one thread times three groups (j2 = 2, 3, 4), scaled to all
+    groups by second-order length sum(L2) (a group's frequential transforms run over the
+    same N_fr rows for every time sample, so its cost follows L2), and `value` is this
+    one-thread figure. With full=True (minutes of CPU time) one thread runs every group, and
+    then a pool of min(cores, groups) processes runs them all again; `value` is then the
+    every-core figure. Config 1 (N = 2^13): one forward + backward on one thread; with
+    full=True also the 20-step gradient descent.
+    """
+    import multiprocessing as mp
+
+    import numpy as np
     from threadpoolctl import threadpool_limits
 
-    def timed(fn):
-        with threadpool_limits(limits=1):   # one host thread, as reported in "cores"
-            t0 = time.perf_counter()
-            fn()
-            return time.perf_counter() - t0
+    import jtfs_inputs as ji
+    from oracle import descent, fftroute
+    from oracle.plan import make_plan
 
-    fftroute.forward_partial(op, y, [], order1=False, fc=fc)          # fills the filter cache
-    t_fl = timed(lambda: fftroute.forward_partial(op, y, [], order1=False, fc=fc))
-    t_fl_o1 = timed(lambda: fftroute.forward_partial(op, y, [], order1=True, fc=fc))
-    t_fl_g = timed(lambda: fftroute.forward_partial(op, y, sorted(picked), order1=False, fc=fc))
-    t_b_o1 = timed(lambda: fftroute.backward(op, y, dS_o1, fc=fc))
-    t_b_g = timed(lambda: fftroute.backward(op, y, dS_group + dS_o1, fc=fc))
-    t_g = max(t_fl_g - t_fl, 0.0) + max(t_b_g - t_b_o1, 0.0)
-    per_sample = t_g / sum(op.N_pad >> g.j2 for g in samples)
-    groups_total = sum(per_sample * (op.N_pad >> g.j2) for g in op.groups)
-    total = t_fl_o1 + t_b_o1 + groups_total
-    spent = t_fl + t_fl_o1 + t_fl_g + t_b_o1 + t_b_g
-    return {"value": 1.0 / total, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": (f"config 2, FP64 NumPy oracle on one thread: first layer + order-1 paths timed in full "
-                       f"(fwd {t_fl_o1:.2f} s, bwd {t_b_o1:.2f} s), second-order groups n2={sorted(picked)} "
-                       f"(j2=2,3,4) timed fwd+bwd ({t_g:.2f} s) and extrapolated to all "
-                       f"{len(op.groups)} groups in proportion to their length: {total:.1f} s per iteration; "
-                       f"{spent:.1f} s of CPU work measured")}
+    cores = len(os.sched_getaffinity(0))
+    out = {"unit": "iters/s", "kind": "oracle", "cpu_model": _cpu_model(), "affinity_cores": cores}
+
+    def progress(msg):
+        print(f"[cpu_baseline] {msg}", file=sys.stderr, flush=True)
+
+    # config 1: forward + backward (and the descent)
+    op1 = make_plan(8192, 6, 8, 1, 3, 1, 9, 4.0)
+    x1 = ji.config1_signal(0)
+    y1 = ji.white_noise_like(x1, 1)
+    with threadpool_limits(limits=1):
+        fc1 = fftroute.FilterCache(op1)
+        S1 = fftroute.forward(op1, x1, fc=fc1)
+        t0 = time.perf_counter()
+        Sy, cache = fftroute.forward(op1, y1, fc=fc1, return_cache=True)
+        fftroute.backward(op1, y1, 2.0 * (Sy - S1), cache=cache)
+        t_c1 = time.perf_counter() - t0
+        out["config1_iters_per_s_1thread"] = round(1.0 / t_c1, 4)
+        progress(f"config 1 forward + backward {t_c1:.2f} s")
+        if full:
+            t0 = time.perf_counter()
+            descent.metamer(op1, S1, y1, descent.OptState(kind="gd", lr=0.1), steps=20)
+            out["config1_descent20_seconds_1thread"] = round(time.perf_counter() - t0, 2)
+
+    # config 2
+    op = make_plan(CFG2["n"], CFG2["J"], CFG2["Q1"], CFG2["Q2"], CFG2["J_fr"], CFG2["Q_fr"], CFG2["log2_T"],
+                   CFG2["F"])
+    x = ji.config2_signal(2)
+    y = ji.white_noise_like(x, 3)
+    rng = np.random.default_rng(4)
+    dS = rng.standard_normal(op.n_coeff)
+    fc = fftroute.FilterCache(op)
+    all_n2 = [g.n2 for g in op.groups]
+    L2 = {g.n2: op.N_pad >> g.j2 for g in op.groups}
+    total_L2 = sum(L2.values())
+    with threadpool_limits(limits=1):
+        fftroute.first_layer_cache(op, y, fc)                    # fills the filter cache
+        one = all_n2 if full else [next(g.n2 for g in op.groups if g.j2 == j) for j in (2, 3, 4)]
+        ts1, tg1 = _oracle_iteration_parts(op, y, dS, fc, one, None)
+    t1 = ts1 + tg1 * total_L2 / sum(L2[n] for n in one)
+    progress(f"config 2 one thread: {t1:.1f} s per iteration")
+    out["config2_iters_per_s_1thread"] = round(1.0 / t1, 5)
+    desc = ("config 2, FP64 NumPy oracle, one forward + backward: first layer and order-1 paths on one thread "
+            f"({ts1:.1f} s); second-order groups on one thread " + (
+                f"all {len(all_n2)} timed" if full else
+                f"{', '.join(f'n2={n}' for n in one)} timed and scaled by their length to all {len(all_n2)}") +
+            f" ({tg1:.1f} s): {t1:.1f} s per iteration")
+    if full:
+        # every core: a fork pool (one thread per process) over all groups
+        P = min(cores, len(all_n2))
+        with threadpool_limits(limits=1), mp.get_context("fork").Pool(P) as pool:
+            pool.map(_oracle_group_task, [])                      # start the workers
+            tsa, tga = _oracle_iteration_parts(op, y, dS, fc, all_n2, pool)
+        ta = tsa + tga
+        progress(f"config 2 on {P} processes: {ta:.1f} s per iteration")
+        out["config2_iters_per_s_all_cores"] = round(1.0 / ta, 5)
+        out.update(value=round(1.0 / ta, 5), cores=P)
+        desc += (f"; every core ({P} processes over the groups): first layer and order-1 {tsa:.1f} s + groups "
+                 f"{tga:.1f} s = {ta:.1f} s per iteration (value)")
+    else:
+        out.update(value=round(1.0 / t1, 5), cores=1)
+        desc += " (value; the every-core setting runs with --cpu-baseline-full)"
+    desc += f". Config 1 forward + backward on one thread: {t_c1:.2f} s"
+    if full:
+        desc += f"; its 20-step descent {out['config1_descent20_seconds_1thread']} s"
+    out["sample"] = desc
+    return out
 
 
 def config4_part(n_signals: int) -> dict:
@@ -202,6 +294,11 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="with --cpu-baseline-only: time the oracle on every second-order group, on one thread and "
+                         "on a process pool over all cores, and the config-1 descent (minutes of CPU)")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="print only the oracle baseline and touch no GPU (the every-core pool forks only here)")
     ap.add_argument("--no-config4", action="store_true", help="skip the learned-start and decoder measurements")
     ap.add_argument("--autotune", action="store_true",
                     help="measure the tile schedules on this device before planning (jtfs_autotune) instead of "
@@ -224,6 +321,11 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4, "repeats": 3}), flush=True)
         return 0
+    if args.cpu_baseline_only:
+        print(json.dumps({"cpu_baseline": cpu_baseline(full=args.cpu_baseline_full)}), flush=True)
+        return 0
+    if args.cpu_baseline_full:
+        sys.exit("--cpu-baseline-full runs with --cpu-baseline-only (its process pool must not inherit a GPU context)")
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
@@ -325,7 +427,7 @@ def main() -> int:
         out["config4"] = config4_part(args.config4_signals)
         out["decoder"] = decoder_part()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(full=args.cpu_baseline_full)
     print(json.dumps(out), flush=True)
     return 0
 

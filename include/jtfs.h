@@ -38,7 +38,8 @@ typedef enum {
   JTFS_ERR_NOMEM = 2,        /* host or device allocation of plan tables failed */
   JTFS_ERR_HIP = 3,          /* a HIP runtime call or kernel launch failed */
   JTFS_ERR_WORKSPACE = 4,    /* ws_bytes smaller than the plan requires */
-  JTFS_ERR_UNSUPPORTED = 5   /* parameters outside what the kernels implement */
+  JTFS_ERR_UNSUPPORTED = 5,  /* parameters outside what the kernels implement */
+  JTFS_ERR_NONFINITE = 6     /* a metamer step met a non-finite loss (jtfs_opt_status) */
 } jtfs_status;
 
 /*
@@ -223,13 +224,22 @@ jtfs_status jtfs_backward(jtfs_plan_t plan, const float* x, const float* dS, flo
  * jtfs_metamer_step - one descent step of Sec. 2.3 for every signal: computes
  * S(y), loss[s] = ||S(y) - S_target||^2 (per signal, before the update, device
  * floats), grad E through jtfs_backward, and updates y in place with `opt`.
- * If a signal's loss is not finite, its y is left unchanged, its momentum is cleared
- * and the optimiser scalars are not advanced; this is decided on the device, so the
- * call never waits for the stream and the caller sees the case in `loss`.
+ * If a signal's loss is not finite, its y is left unchanged, its momentum is cleared,
+ * the optimiser scalars are not advanced and the signal's non-finite step count (a
+ * device scalar in opt->state) is incremented; this is decided on the device, so the
+ * call never waits for the stream: jtfs_opt_status reports it when the host syncs.
  * Requires ws_backward bytes of workspace.
  */
 jtfs_status jtfs_metamer_step(jtfs_plan_t plan, float* y, const float* S_target, const jtfs_opt* opt,
                               float* loss, void* ws, size_t ws_bytes, jtfs_stream_t stream);
+
+/*
+ * jtfs_opt_status - waits for `stream`, then reads the per-signal count of metamer steps
+ * whose loss was not finite since opt->state was zeroed (counts: host array of batch
+ * entries, or NULL). Returns JTFS_ERR_NONFINITE if any count is nonzero, JTFS_OK
+ * otherwise (Sec. 2.3 descent; the flag of a non-finite loss, read at synchronisation).
+ */
+jtfs_status jtfs_opt_status(jtfs_plan_t plan, const jtfs_opt* opt, int32_t* counts, jtfs_stream_t stream);
 
 /*
  * jtfs_colored_noise - the descent start of Sec. 2.3: Gaussian noise whose power spectral

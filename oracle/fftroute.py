@@ -245,6 +245,36 @@ def forward(plan: OraclePlan, x: np.ndarray, fc: FilterCache = None, return_cach
     return S
 
 
+def order2_group_adjoint(plan: OraclePlan, grp, U1h, fc: FilterCache, dS: np.ndarray, dU1) -> None:
+    """Adds to the rows dU1[n1] (n1 < K) the adjoint of ``order2_group`` applied to the
+    order-2 blocks of dS for the second-order filter ``grp.n2``: back through the phi_F and
+    phi_T pooling, the modulus (subgradient 0 at 0), the frequential filters and the
+    second layer."""
+    blocks = [blk for blk in plan.blocks if blk.order == 2 and blk.n2 == grp.n2]
+    if not any(np.any(_block_view(plan, blk, dS)) for blk in blocks):
+        return    # every path of this group has zero gradient: it contributes nothing
+    n_bins_out = plan.N_fr >> plan.s_F
+    Y = second_layer_group(plan, grp, U1h, fc)
+    Yh = np.fft.fft(Y, axis=0)
+    phT = fc.phi_t(grp.j2)
+    dY = np.zeros_like(Y)
+    for blk in blocks:
+        g, b = blk.n_fr, plan.fr[blk.n_fr]
+        dout = _unkeep(plan, blk, _block_view(plan, blk, dS), n_bins_out)
+        if not np.any(dout):
+            continue
+        if b.lowpass:
+            dP = dout
+        else:
+            dP = filt_dec_adj(dout, fc.phi_f(b.k), plan.s_F - b.k, axis=0).real
+        dW = filt_dec_adj(dP, phT, plan.log2_T - grp.j2, axis=1).real
+        V = freq_filter(plan, Yh, g, fc)
+        dY += filt_dec_adj(dW * phase(V), fc.fr(g), b.k, axis=0)
+    for n1 in range(grp.K):
+        k1 = plan.psi1[n1].k
+        dU1[n1] += filt_dec_adj(dY[n1], fc.psi2(grp.n2, k1), grp.j2 - k1).real
+
+
 def backward(plan: OraclePlan, x: np.ndarray, dS: np.ndarray, cache=None, fc: FilterCache = None) -> np.ndarray:
     """dx = J_S(x)^T dS, the exact adjoint of ``forward``."""
     dS = np.asarray(dS, dtype=np.float64)
@@ -273,32 +303,8 @@ def backward(plan: OraclePlan, x: np.ndarray, dS: np.ndarray, cache=None, fc: Fi
         dU1[n1] += filt_dec_adj(dA[n1], fc.phi_t(b.k), plan.log2_T - b.k).real
 
     # order 2: per n2 group, back through pooling, modulus, frequential filters, second layer
-    by_n2 = {}
-    for blk in plan.blocks:
-        if blk.order == 2:
-            by_n2.setdefault(blk.n2, []).append(blk)
     for grp in plan.groups:
-        if not any(np.any(_block_view(plan, blk, dS)) for blk in by_n2[grp.n2]):
-            continue    # every path of this group has zero gradient: it contributes nothing
-        Y = second_layer_group(plan, grp, U1h, fc)
-        Yh = np.fft.fft(Y, axis=0)
-        phT = fc.phi_t(grp.j2)
-        dY = np.zeros_like(Y)
-        for blk in by_n2[grp.n2]:
-            g, b = blk.n_fr, plan.fr[blk.n_fr]
-            dout = _unkeep(plan, blk, _block_view(plan, blk, dS), n_bins_out)
-            if not np.any(dout):
-                continue
-            if b.lowpass:
-                dP = dout
-            else:
-                dP = filt_dec_adj(dout, fc.phi_f(b.k), plan.s_F - b.k, axis=0).real
-            dW = filt_dec_adj(dP, phT, plan.log2_T - grp.j2, axis=1).real
-            V = freq_filter(plan, Yh, g, fc)
-            dY += filt_dec_adj(dW * phase(V), fc.fr(g), b.k, axis=0)
-        for n1 in range(grp.K):
-            k1 = plan.psi1[n1].k
-            dU1[n1] += filt_dec_adj(dY[n1], fc.psi2(grp.n2, k1), grp.j2 - k1).real
+        order2_group_adjoint(plan, grp, U1h, fc, dS, dU1)
 
     # first layer: modulus, then the first-order filters, onto the padded signal
     dxp = np.zeros(plan.N_pad, dtype=np.float64)

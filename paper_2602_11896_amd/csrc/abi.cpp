@@ -602,6 +602,24 @@ jtfs_status jtfs_metamer_step(jtfs_plan_t plan, float* y, const float* S_target,
   });
 }
 
+jtfs_status jtfs_opt_status(jtfs_plan_t plan, const jtfs_opt* opt, int32_t* counts, jtfs_stream_t stream) {
+  if (!plan || !opt || !opt->state) return fail(JTFS_ERR_ARG, "NULL argument");
+  const int64_t nv = state_vectors(opt->kind);
+  if (nv < 0) return fail(JTFS_ERR_ARG, "unknown optimiser kind");
+  const size_t batch = plan->sig.size();
+  std::vector<float> scal(4 * batch);
+  HIPCHK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  HIPCHK(hipMemcpy(scal.data(), opt->state + nv * plan->n_total, sizeof(float) * scal.size(), hipMemcpyDeviceToHost));
+  bool any = false;
+  for (size_t s = 0; s < batch; ++s) {
+    const int32_t c = static_cast<int32_t>(scal[4 * s + 3]);
+    if (counts) counts[s] = c;
+    any = any || c != 0;
+  }
+  if (any) return fail(JTFS_ERR_NONFINITE, "a metamer step met a non-finite loss; y was left unchanged");
+  return JTFS_OK;
+}
+
 jtfs_status jtfs_colored_noise(jtfs_plan_t plan, const float* x, const float* w, float* y0, void* ws, size_t ws_bytes,
                                jtfs_stream_t stream) {
   if (!plan || !x || !w || !y0 || !ws) return fail(JTFS_ERR_ARG, "NULL argument");
@@ -688,6 +706,7 @@ const char* jtfs_status_str(jtfs_status s) {
     case JTFS_ERR_HIP: return "HIP error";
     case JTFS_ERR_WORKSPACE: return "workspace too small";
     case JTFS_ERR_UNSUPPORTED: return "unsupported parameters";
+    case JTFS_ERR_NONFINITE: return "non-finite loss";
   }
   return "unknown status";
 }

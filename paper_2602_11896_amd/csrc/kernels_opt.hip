@@ -6,9 +6,11 @@
 //         not increase; otherwise y returns to the last kept iterate, the momentum is
 //         cleared, mu shrinks by bold_down and a fresh step is taken from the kept
 //         iterate along its stored gradient.
-// A non-finite E leaves y unchanged (momentum cleared) and freezes the scalars.
+// A non-finite E leaves y unchanged (momentum cleared), freezes the other scalars and
+// counts the step in scalar [3].
 // Scalars per signal: [0] step count (Adam) / initialised flag (momentum), [1] mu,
-// [2] last kept E. They are updated by a one-thread kernel after the element update.
+// [2] last kept E, [3] non-finite steps. They are updated by a one-thread kernel after
+// the element update.
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
@@ -82,7 +84,10 @@ __global__ void k_update_momentum(float* y, const float* g, const float* loss, f
 
 __global__ void k_update_scalars(int kind, const float* loss, float* scal, float lr, float up, float down) {
   const float E = loss[0];
-  if (!isfinite(E)) return;
+  if (!isfinite(E)) {
+    scal[3] += 1.0f;
+    return;
+  }
   if (kind == JTFS_OPT_ADAM) {
     scal[0] += 1.0f;
   } else if (kind == JTFS_OPT_MOMENTUM_BOLD) {

@@ -31,24 +31,29 @@ __device__ __forceinline__ float cabs(c32 z) { return sqrtf(z.x * z.x + z.y * z.
 
 // Fourier subsampling by 2^shift of (src . band) onto an n-point grid, output bin q.
 // The plan guarantees that a band is not empty and spans at most two aliased blocks
-// (1 <= len <= 2 n), so both are read without a loop, at indices clamped into the band and with an absent second
-// term masked by value: the loads of several bins can be in flight together.
+// (1 <= len <= 2 n). A band of at most n bins meets bin q in one block only, and a row's
+// band is the same for all its bins (a uniform branch); otherwise both blocks are read at
+// indices clamped into the band, an absent second term masked by value, so the loads of
+// several bins can be in flight together.
 __device__ __forceinline__ c32 fold_gather(const c32* src, const Band& b, const float* vals, int n, int shift, int q) {
   const int nmask = n - 1;
   const int d0 = (q - (b.lo & nmask)) & nmask;
   c32 acc{0.f, 0.f};
+  const int nk = b.len > n ? 2 : 1;
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const int d = d0 + k * n;
-    const bool in = d < b.len;
-    const int dc = in ? d : 0;
-    int m = b.lo + dc;
-    if (m >= b.L) m -= b.L;
-    const float h = vals[b.off + dc];
-    const c32 v = src[m];
-    const float hm = in ? h : 0.f;
-    acc.x += v.x * hm;
-    acc.y += v.y * hm;
+    if (k < nk) {
+      const int d = d0 + k * n;
+      const bool in = d < b.len;
+      const int dc = in ? d : 0;
+      int m = b.lo + dc;
+      if (m >= b.L) m -= b.L;
+      const float h = vals[b.off + dc];
+      const c32 v = src[m];
+      const float hm = in ? h : 0.f;
+      acc.x += v.x * hm;
+      acc.y += v.y * hm;
+    }
   }
   const float sc = ldexpf(1.0f, -shift);
   return c32{acc.x * sc, acc.y * sc};

@@ -300,6 +300,18 @@ class Optimizer:
         self.state.zero_()
 
 
+def opt_status(plan: Plan, opt: Optimizer, raise_nonfinite: bool = True) -> List[int]:
+    """Per-signal counts of metamer steps whose loss was not finite (jtfs_opt_status; waits
+    for the current stream). Raises JTFSError with JTFS_ERR_NONFINITE if any is nonzero and
+    raise_nonfinite is set."""
+    counts = (ctypes.c_int32 * plan.batch)()
+    c = opt.c()
+    st = L.lib().jtfs_opt_status(plan._h, ctypes.byref(c), counts, _stream(opt.state.device))
+    if st not in (L.JTFS_OK, L.JTFS_ERR_NONFINITE) or (st == L.JTFS_ERR_NONFINITE and raise_nonfinite):
+        L.check(st, "jtfs_opt_status")
+    return list(counts)
+
+
 # Names of the C ABI, for callers that prefer them.
 jtfs_plan = Plan
 

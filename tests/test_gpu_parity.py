@@ -245,11 +245,17 @@ def test_nonfinite_loss_leaves_signal():
     y[7] = float("nan")
     before = y.clone()
     loss = torch.zeros(1, device="cuda")
+    assert J.opt_status(plan, opt) == [0]
     plan.metamer_step(y, torch.zeros(plan.n_coeff, device="cuda"), opt, loss, ws)
     torch.cuda.synchronize()
     assert not math.isfinite(float(loss[0]))
     assert torch.equal(torch.isnan(y), torch.isnan(before))
     assert torch.equal(y[~torch.isnan(y)], before[~torch.isnan(before)])
+    # the device flag reaches the host at synchronisation as JTFS_ERR_NONFINITE
+    assert J.opt_status(plan, opt, raise_nonfinite=False) == [1]
+    with pytest.raises(J.L.JTFSError) as err:
+        J.opt_status(plan, opt)
+    assert err.value.status == J.L.JTFS_ERR_NONFINITE
 
 
 def test_batched_plan_matches_single():
