@@ -149,3 +149,56 @@ def test_nonfinite_loss_leaves_iterate():
     y = np.array([1.0, 2.0])
     y1, ok = descent.update(y, np.array([np.nan, 1.0]), float("nan"), st)
     assert not ok and np.array_equal(y1, y)
+
+
+# ---------------------------------------------------------------- config 2, 64 indices
+
+_FD = {}
+
+
+def _fd_partial_loss(args):
+    """E restricted to the order-1 blocks and the listed groups, at y + s h e_i (worker)."""
+    from threadpoolctl import threadpool_limits
+    i, s = args
+    st = _FD
+    y = st["y"].copy()
+    y[i] += s * st["h"]
+    with threadpool_limits(limits=1):
+        S = fftroute.forward_partial(st["op"], y, st["n2s"], fc=st["fc"])
+    m = st["mask"]
+    d = S[m] - st["S_t"][m]
+    return float(np.dot(d, d))
+
+
+@pytest.mark.slow
+def test_config2_central_differences_64_indices():
+    # BASELINE config 2's gradient check at full size (N = 2^16, J = 12, Q1 = 12) on the
+    # oracle: central differences at 64 random sample indices (seed 4), h = 1e-5 rms(y), of
+    # E restricted to the order-1 paths and the two coarsest second-order groups (every
+    # path of the first layer, order 1 and the second layer's adjoint at this size; a full
+    # forward per difference would take hours on the host). A fork pool over the host
+    # cores evaluates the 128 partial forwards.
+    import multiprocessing as mp
+    import os
+
+    import jtfs_inputs as ji
+    op = make_plan(65536, 12, 12, 2, 4, 2, 13, 24.0)
+    x = ji.config2_signal(2)
+    y = ji.white_noise_like(x, 3)
+    n2s = [g.n2 for g in op.groups[-2:]]
+    fc = fftroute.FilterCache(op)
+    S_t = fftroute.forward_partial(op, x, n2s, fc=fc)
+    S_y = fftroute.forward_partial(op, y, n2s, fc=fc)
+    mask = ~np.isnan(S_y)
+    dS = np.where(mask, 2.0 * (np.nan_to_num(S_y) - np.nan_to_num(S_t)), 0.0)
+    g = fftroute.backward(op, y, dS, fc=fc)
+    idx = np.random.default_rng(4).choice(op.N, 64, replace=False)
+    h = 1e-5 * float(np.sqrt(np.mean(y * y)))
+    _FD.update(op=op, y=y, n2s=n2s, fc=fc, S_t=S_t, mask=mask, h=h)
+    jobs = [(int(i), s) for i in idx for s in (+1, -1)]
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    with mp.get_context("fork").Pool(procs) as pool:
+        Es = pool.map(_fd_partial_loss, jobs)
+    fd = np.array([(Es[2 * k] - Es[2 * k + 1]) / (2 * h) for k in range(len(idx))])
+    gs = g[idx]
+    assert np.linalg.norm(fd - gs) <= 1e-6 * np.linalg.norm(gs)
