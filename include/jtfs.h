@@ -260,6 +260,20 @@ jtfs_status jtfs_colored_noise(jtfs_plan_t plan, const float* x, const float* w,
                                size_t ws_bytes, jtfs_stream_t stream);
 
 /*
+ * jtfs_joint_wavelet - the interference pattern of a joint path (Sec. 2.1, Eq. 2 and
+ * Fig. 1): out[r * n_t + t] = Re(psi_alpha(t - n_t / 2) * psi_beta(r - N_fr / 2)), r < N_fr,
+ * t < n_t, where psi_alpha is the second-order wavelet n2 (Sec. 3.1 bank of Q2) at the
+ * signal's rate on its N_pad-point grid (time in samples) and psi_beta the frequential
+ * filter n_fr of the list [phi_F, psi_fr(xi > 0)..., psi_fr(xi < 0)...] on the N_fr
+ * log-frequency bins (Sec. 3.4-3.5; index = jtfs_path.n_fr), both built from the plan's
+ * tables and circularly centred. out: N_fr * n_t device floats (N_fr from
+ * jtfs_plan_sizes). JTFS_ERR_ARG if n2 has no second-order paths (j2 = 0), if n_fr is out
+ * of range, or if n_t is outside [1, min(N_pad, 2^20)].
+ */
+jtfs_status jtfs_joint_wavelet(jtfs_plan_t plan, int32_t signal, int32_t n2, int32_t n_fr, int32_t n_t, float* out,
+                               jtfs_stream_t stream);
+
+/*
  * jtfs_loss - per-signal metamer loss and its gradient with respect to S (Sec. 2.3):
  * loss[s] = scale ||S_s - T_s||^2 / N_s and dS_s = 2 scale (S_s - T_s) / N_s, where
  * N_s = ||T_s||^2 if `relative` (the relative loss; N_s = 1 when T_s = 0) and 1 otherwise.

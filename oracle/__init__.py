@@ -23,6 +23,8 @@ descent     Loss, relative loss and the metamer updates (Sec. 2.3): gradient
 init        The paper's descent start (Sec. 2.3): Gaussian noise whose power spectral
             density matches S1 x (band levels, Rayleigh factor, the interpolated
             spectrum and the shaping of given standard normal draws).
+figure      The joint time--log-frequency wavelet of a path (Sec. 2.1, Fig. 1): the real
+            part of psi_alpha(t) psi_beta(log2 lambda) from the time-domain filters.
 decoder     The learned warm start (an addition to the method, not in the paper): a
             1-D transposed-convolution decoder from coefficients to a waveform, its
             exact adjoint with the device's bfloat16 storage points, and Adam.

@@ -93,6 +93,7 @@ SIGNATURES = [
     ("jtfs_backward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_uint32, c_void_p]),
     ("jtfs_metamer_step", c_int32, [c_void_p, c_void_p, c_void_p, POINTER(jtfs_opt), c_void_p, c_void_p, c_size_t,
                                     c_void_p]),
+    ("jtfs_joint_wavelet", c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     ("jtfs_opt_status", c_int32, [c_void_p, POINTER(jtfs_opt), POINTER(c_int32), c_void_p]),
     ("jtfs_loss", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, ctypes.c_float, c_void_p]),
     ("jtfs_timing_enable", c_int32, [c_void_p, c_int32]),

@@ -648,6 +648,26 @@ jtfs_status jtfs_colored_noise(jtfs_plan_t plan, const float* x, const float* w,
   });
 }
 
+jtfs_status jtfs_joint_wavelet(jtfs_plan_t plan, int32_t signal, int32_t n2, int32_t n_fr, int32_t n_t, float* out,
+                               jtfs_stream_t stream) {
+  if (!plan || !out || signal < 0 || signal >= static_cast<int32_t>(plan->sig.size()))
+    return fail(JTFS_ERR_ARG, "bad plan, signal or out");
+  const jtfs::SigPlan& sp = plan->sig[signal];
+  if (n_fr < 0 || n_fr >= static_cast<int32_t>(sp.fr.size())) return fail(JTFS_ERR_ARG, "n_fr out of range");
+  auto it = sp.band_psi2.find({n2, 0});
+  if (it == sp.band_psi2.end()) return fail(JTFS_ERR_ARG, "n2 has no second-order paths in this plan");
+  if (n_t < 1 || n_t > sp.N_pad || n_t > (1 << 20)) return fail(JTFS_ERR_ARG, "n_t outside [1, min(N_pad, 2^20)]");
+  const DeviceArena* a = nullptr;
+  jtfs_status r = device_tables(plan, &a);
+  if (r != JTFS_OK) return r;
+  // only the plan tables are read: no workspace
+  jtfs::DevSig d = make_devsig(plan, static_cast<size_t>(signal), a->sig[signal], nullptr, true);
+  const jtfs::Band band = sp.bands[static_cast<size_t>(it->second)];
+  const float* taps = a->sig[signal].tables + sp.frf[static_cast<size_t>(n_fr)].taps;
+  HIPCHK(jtfs::run_joint_wavelet(d, band, taps, sp.N_fr, n_t, out, static_cast<hipStream_t>(stream)));
+  return JTFS_OK;
+}
+
 jtfs_status jtfs_loss(jtfs_plan_t plan, const float* S, const float* S_target, float* dS, float* loss,
                       int32_t relative, float scale, jtfs_stream_t stream) {
   if (!plan || !S || !S_target || !dS || !loss) return fail(JTFS_ERR_ARG, "NULL argument");

@@ -24,6 +24,11 @@ hipError_t run_cn_levels(const DevSig& s, const SigPlan& p, const int32_t* band_
 hipError_t run_cn_shape(const DevSig& s, const SigPlan& p, const int32_t* band_psi1, const float* c,
                         hipStream_t st);
 
+// kernels_joint.hip: out[r][t] = Re(psi_alpha(t - n_t / 2) g(r - N_fr / 2)) for the band b of
+// psi_alpha on the N_pad grid and the N_fr complex taps of g (Sec. 2.1, Fig. 1).
+hipError_t run_joint_wavelet(const DevSig& s, const Band& b, const float* taps, int n_fr_bins, int n_t, float* out,
+                             hipStream_t st);
+
 // kernels_freq.hip
 hipError_t run_order1_fwd(const DevSig& s, const SigPlan& p, hipStream_t st);
 hipError_t run_freq_fwd(const DevSig& s, const SigPlan& p, hipStream_t st);

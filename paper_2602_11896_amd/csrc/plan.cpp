@@ -452,7 +452,12 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
         im[d] = si / L;
         peak = std::max(peak, std::hypot(re[d], im[d]));
       }
-      const FrFilter& ff = p.frf[g];
+      FrFilter& ff = p.frf[g];
+      ff.taps = static_cast<int64_t>(p.tables.size());
+      for (int32_t d = 0; d < L; ++d) {
+        p.tables.push_back(static_cast<float>(re[d]));
+        p.tables.push_back(static_cast<float>(im[d]));
+      }
       for (int32_t r = 0; r < ff.M; ++r) {
         for (int32_t n = 0; n < N1; ++n) {
           int32_t d = static_cast<int32_t>(((static_cast<int64_t>(r) << f.k) - n) % L);

@@ -99,6 +99,7 @@ struct FrFilter {
   int32_t lowpass;  // 1 for phi_F
   int64_t phiF;     // float offset of phi_F at level k_g (time domain, M values)
   int32_t spin, pad_;
+  int64_t taps;     // float offset of g's N_fr complex taps at level 0 (re, im pairs)
 };
 
 }  // namespace jtfs

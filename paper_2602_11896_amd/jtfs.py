@@ -207,6 +207,15 @@ class Plan:
                                         _stream(x.device)), "jtfs_forward_ex")
         return S
 
+    def joint_wavelet(self, n2: int, n_fr: int, n_t: int, signal: int = 0, device="cuda") -> torch.Tensor:
+        """Re(psi_alpha(t) psi_beta(log2 lambda)) of path (n2, n_fr) on N_fr x n_t centred
+        samples (jtfs_joint_wavelet; the interference pattern of Sec. 2.1, Fig. 1)."""
+        n_fr_bins = self.sizes(signal)["N_fr"]
+        out = torch.empty((n_fr_bins, n_t), dtype=torch.float32, device=device)
+        L.check(L.lib().jtfs_joint_wavelet(self._h, signal, n2, n_fr, n_t, _ptr(out), _stream(out.device)),
+                "jtfs_joint_wavelet")
+        return out
+
     def prepare(self, device="cuda") -> None:
         """Set-up for forward_noalloc on `device` (jtfs_plan_prepare; allocates)."""
         with torch.cuda.device(torch.device(device)):
