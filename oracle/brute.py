@@ -48,7 +48,18 @@ def forward(plan: OraclePlan, x: np.ndarray, return_intermediates: bool = False)
 
     def put(blk, full):
         blockv = S[blk.offset: blk.offset + blk.n_lambda * blk.n_frames].reshape(blk.n_lambda, blk.n_frames)
-        blockv[:] = full[:blk.n_lambda, plan.f_lo: plan.f_lo + plan.n_frames]
+        blockv[:] = full[:blk.n_lambda, blk.t_lo: blk.t_lo + blk.n_frames]
+
+    def fr_pooled(b):
+        return (not b.lowpass) and plan.average_local_fr
+
+    for blk in plan.blocks:
+        if blk.order == 0:
+            if plan.average_local:
+                S0 = conv_matrix(fb.lowpass_time(plan.N_pad, plan.sigma_T, 0), plan.log2_T) @ xp
+                put(blk, S0[None, :])
+            else:
+                put(blk, xp[None, :])   # U0: the kept samples of the padded signal
 
     A = np.zeros((plan.N_fr, plan.nf_pad))
     A[:plan.N1] = S1
@@ -59,9 +70,11 @@ def forward(plan: OraclePlan, x: np.ndarray, return_intermediates: bool = False)
         V = conv_matrix(_fr_time(plan, blk.n_fr), b.k) @ A
         if b.lowpass:
             out = V.real
-        else:
+        elif fr_pooled(b):
             Mg = plan.N_fr >> b.k
             out = (conv_matrix(fb.lowpass_time(Mg, plan.sigma_F, b.k), plan.s_F - b.k) @ np.abs(V)).real
+        else:
+            out = np.abs(V)
         put(blk, out)
 
     for grp in plan.groups:
@@ -79,12 +92,12 @@ def forward(plan: OraclePlan, x: np.ndarray, return_intermediates: bool = False)
                 continue
             b = plan.fr[blk.n_fr]
             W = np.abs(conv_matrix(_fr_time(plan, blk.n_fr), b.k) @ Y)
-            P = (W @ Ct.T).real
-            if b.lowpass:
-                out = P
-            else:
+            P = (W @ Ct.T).real if plan.average_local else W
+            if fr_pooled(b):
                 Mg = plan.N_fr >> b.k
                 out = (conv_matrix(fb.lowpass_time(Mg, plan.sigma_F, b.k), plan.s_F - b.k) @ P).real
+            else:
+                out = P
             put(blk, out)
     if return_intermediates:
         return S, dict(Z1=Z1, U1=U1, S1=S1)

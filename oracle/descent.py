@@ -26,9 +26,22 @@ import numpy as np
 from . import fftroute
 
 
-def loss_and_grad_S(S_y: np.ndarray, S_x: np.ndarray):
+def loss_and_grad_S(S_y: np.ndarray, S_x: np.ndarray, weights: np.ndarray = None):
+    """E = sum w (S_y - S_x)^2 and dE/dS_y (w = 1 unless ``weights`` is given)."""
     d = S_y - S_x
-    return float(np.dot(d, d)), 2.0 * d
+    if weights is None:
+        return float(np.dot(d, d)), 2.0 * d
+    return float(np.dot(weights * d, d)), 2.0 * weights * d
+
+
+def block_weights(plan, w0: float) -> np.ndarray:
+    """Per-coefficient loss weights: w0 on the zeroth-order block, 1 elsewhere (Eqs. 5-7
+    hold only the first and second orders, so the default reading is w0 = 0)."""
+    w = np.ones(plan.n_coeff)
+    for blk in plan.blocks:
+        if blk.order == 0:
+            w[blk.offset: blk.offset + blk.n_lambda * blk.n_frames] = w0
+    return w
 
 
 def relative_loss(E: float, S_x: np.ndarray) -> float:

@@ -137,14 +137,29 @@ def _block_view(plan, blk, S):
 
 
 def _keep(plan, blk, full):
-    """Unpad a (bins x padded frames) array to the block's kept bins and frames."""
-    return full[:blk.n_lambda, plan.f_lo: plan.f_lo + plan.n_frames]
+    """Unpad a (bins x padded times) array to the block's kept bins and times."""
+    return full[:blk.n_lambda, blk.t_lo: blk.t_lo + blk.n_frames]
 
 
-def _unkeep(plan, blk, block, n_bins):
-    full = np.zeros((n_bins, plan.nf_pad), dtype=np.float64)
-    full[:blk.n_lambda, plan.f_lo: plan.f_lo + plan.n_frames] = block
+def _unkeep(plan, blk, block, n_bins, n_times=None):
+    full = np.zeros((n_bins, plan.nf_pad if n_times is None else n_times), dtype=np.float64)
+    full[:blk.n_lambda, blk.t_lo: blk.t_lo + blk.n_frames] = block
     return full
+
+
+def _fr_pooled(plan, b) -> bool:
+    """Whether the path of frequential filter b is averaged by phi_F (every band-pass
+    path unless frequential averaging is off; phi_F itself is already a low-pass)."""
+    return (not b.lowpass) and plan.average_local_fr
+
+
+def zeroth_order(plan: OraclePlan, x: np.ndarray, fc: "FilterCache") -> np.ndarray:
+    """The zeroth-order block: S0 = (x_pad * phi_T) at stride T when averaging is local,
+    else U0 = x (Sec. 3.6 main algorithm)."""
+    if not plan.average_local:
+        return np.asarray(x, dtype=np.float64).copy()
+    S0 = filt_dec(pad_signal(plan, x), fc.phi_t(0), plan.log2_T).real
+    return S0[plan.f_lo: plan.f_lo + plan.n_frames]
 
 
 # ----------------------------------------------------------------------------- stages
@@ -190,7 +205,6 @@ def order1_blocks(plan: OraclePlan, Ah: np.ndarray, fc: FilterCache, S: np.ndarr
     """Order-1 joint paths (Sec. 3.5 on real input, Eq. 3 for phi_F) written into S.
 
     ``Ah`` is the DFT along log-frequency of S1 zero-padded to N_fr rows."""
-    n_bins_out = plan.N_fr >> plan.s_F
     for blk in plan.blocks:
         if blk.order != 1:
             continue
@@ -198,9 +212,10 @@ def order1_blocks(plan: OraclePlan, Ah: np.ndarray, fc: FilterCache, S: np.ndarr
         V = freq_filter(plan, Ah, g, fc)
         if b.lowpass:
             out = V.real
-        else:
+        elif _fr_pooled(plan, b):
             out = filt_dec(np.abs(V), fc.phi_f(b.k), plan.s_F - b.k, axis=0).real
-        assert out.shape[0] == n_bins_out
+        else:
+            out = np.abs(V)
         _block_view(plan, blk, S)[:] = _keep(plan, blk, out)
 
 
@@ -216,11 +231,11 @@ def order2_group(plan: OraclePlan, grp, U1h, fc: FilterCache, S: np.ndarray) -> 
             continue
         g, b = blk.n_fr, plan.fr[blk.n_fr]
         W = np.abs(freq_filter(plan, Yh, g, fc))
-        P = filt_dec(W, phT, plan.log2_T - grp.j2, axis=1).real
-        if b.lowpass:
-            out = P
-        else:
+        P = filt_dec(W, phT, plan.log2_T - grp.j2, axis=1).real if plan.average_local else W
+        if _fr_pooled(plan, b):
             out = filt_dec(P, fc.phi_f(b.k), plan.s_F - b.k, axis=0).real
+        else:
+            out = P
         _block_view(plan, blk, S)[:] = _keep(plan, blk, out)
 
 
@@ -236,6 +251,9 @@ def forward(plan: OraclePlan, x: np.ndarray, fc: FilterCache = None, return_cach
     fc = fc or FilterCache(plan)
     Xh, Z1, U1h, S1 = first_layer(plan, x, fc)
     S = np.zeros(plan.n_coeff, dtype=np.float64)
+    for blk in plan.blocks:
+        if blk.order == 0:
+            _block_view(plan, blk, S)[:] = zeroth_order(plan, x, fc)
     Ah = transformed_s1(plan, S1)
     order1_blocks(plan, Ah, fc, S)
     for grp in plan.groups:
@@ -253,21 +271,22 @@ def order2_group_adjoint(plan: OraclePlan, grp, U1h, fc: FilterCache, dS: np.nda
     blocks = [blk for blk in plan.blocks if blk.order == 2 and blk.n2 == grp.n2]
     if not any(np.any(_block_view(plan, blk, dS)) for blk in blocks):
         return    # every path of this group has zero gradient: it contributes nothing
-    n_bins_out = plan.N_fr >> plan.s_F
     Y = second_layer_group(plan, grp, U1h, fc)
     Yh = np.fft.fft(Y, axis=0)
     phT = fc.phi_t(grp.j2)
+    L2 = plan.N_pad >> grp.j2
     dY = np.zeros_like(Y)
     for blk in blocks:
         g, b = blk.n_fr, plan.fr[blk.n_fr]
-        dout = _unkeep(plan, blk, _block_view(plan, blk, dS), n_bins_out)
+        n_rows = plan.N_fr >> (plan.s_F if _fr_pooled(plan, b) or b.lowpass else b.k)
+        dout = _unkeep(plan, blk, _block_view(plan, blk, dS), n_rows, None if plan.average_local else L2)
         if not np.any(dout):
             continue
-        if b.lowpass:
-            dP = dout
-        else:
+        if _fr_pooled(plan, b):
             dP = filt_dec_adj(dout, fc.phi_f(b.k), plan.s_F - b.k, axis=0).real
-        dW = filt_dec_adj(dP, phT, plan.log2_T - grp.j2, axis=1).real
+        else:
+            dP = dout
+        dW = filt_dec_adj(dP, phT, plan.log2_T - grp.j2, axis=1).real if plan.average_local else dP
         V = freq_filter(plan, Yh, g, fc)
         dY += filt_dec_adj(dW * phase(V), fc.fr(g), b.k, axis=0)
     for n1 in range(grp.K):
@@ -282,7 +301,6 @@ def backward(plan: OraclePlan, x: np.ndarray, dS: np.ndarray, cache=None, fc: Fi
         cache = first_layer_cache(plan, x, fc)
     fc = cache["fc"]
     Z1, U1h, Ah = cache["Z1"], cache["U1h"], cache["Ah"]
-    n_bins_out = plan.N_fr >> plan.s_F
     dU1 = [np.zeros(z.shape[0], dtype=np.float64) for z in Z1]
 
     # order 1: back through phi_F pooling, modulus, frequential filters, onto S1
@@ -291,12 +309,13 @@ def backward(plan: OraclePlan, x: np.ndarray, dS: np.ndarray, cache=None, fc: Fi
         if blk.order != 1:
             continue
         g, b = blk.n_fr, plan.fr[blk.n_fr]
-        dout = _unkeep(plan, blk, _block_view(plan, blk, dS), n_bins_out)
+        n_rows = plan.N_fr >> (plan.s_F if _fr_pooled(plan, b) or b.lowpass else b.k)
+        dout = _unkeep(plan, blk, _block_view(plan, blk, dS), n_rows)
         if b.lowpass:
             dV = dout.astype(np.complex128)
         else:
             V = freq_filter(plan, Ah, g, fc)
-            dW = filt_dec_adj(dout, fc.phi_f(b.k), plan.s_F - b.k, axis=0).real
+            dW = filt_dec_adj(dout, fc.phi_f(b.k), plan.s_F - b.k, axis=0).real if _fr_pooled(plan, b) else dout
             dV = dW * phase(V)
         dA += filt_dec_adj(dV, fc.fr(g), b.k, axis=0).real
     for n1, b in enumerate(plan.psi1):
@@ -311,6 +330,17 @@ def backward(plan: OraclePlan, x: np.ndarray, dS: np.ndarray, cache=None, fc: Fi
     for n1, b in enumerate(plan.psi1):
         dZ = dU1[n1] * phase(Z1[n1])
         dxp += filt_dec_adj(dZ, fc.psi1(n1), b.k).real
+    # zeroth order: the adjoint of phi_T at stride T (S0), or the identity (U0)
+    for blk in plan.blocks:
+        if blk.order != 0:
+            continue
+        d0 = _block_view(plan, blk, dS)[0]
+        if plan.average_local:
+            full = np.zeros(plan.nf_pad)
+            full[blk.t_lo: blk.t_lo + blk.n_frames] = d0
+            dxp += filt_dec_adj(full, fc.phi_t(0), plan.log2_T).real
+        else:
+            dxp[plan.pad_left: plan.pad_left + plan.N] += d0
     return dxp[plan.pad_left: plan.pad_left + plan.N].copy()
 
 
@@ -324,6 +354,9 @@ def forward_partial(plan: OraclePlan, x: np.ndarray, n2_list, order1: bool = Tru
     _, _, U1h, S1 = first_layer(plan, x, fc)
     S = np.full(plan.n_coeff, np.nan)
     if order1:
+        for blk in plan.blocks:
+            if blk.order == 0:
+                _block_view(plan, blk, S)[:] = zeroth_order(plan, x, fc)
         order1_blocks(plan, transformed_s1(plan, S1), fc, S)
     want = set(n2_list)
     for grp in plan.groups:

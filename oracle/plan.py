@@ -22,7 +22,20 @@ Readings where the paper is silent, each with its reason:
 * Output: order-1 block, then order-2 blocks for ascending n2; inside a block the
   frequential filter (list order), then the log-frequency bin, then the frame. Only
   unpadded frames (pad_left <= f T < pad_left + N) and unpadded bins (b 2^sF < n1_max)
-  are kept. Zeroth order is not part of the output (it does not enter Eqs. 5-7).
+  are kept. Zeroth order is not part of the output (it does not enter Eqs. 5-7) unless
+  ``zeroth`` asks for it; then its block comes first (the main algorithm of Sec. 3.6
+  yields it before order 1).
+* Variants of the Sec. 3.3 / 3.5 listings and the Sec. 3.6 main algorithm:
+  - ``zeroth``: the zeroth-order block: S0 = (x * phi_T) at stride T (kept frames) when
+    averaging is local, else U0 = x itself (the listing's "U_0 indexed by time");
+  - ``average_local = False``: no phi_T averaging of the second order: each joint path
+    keeps |Y_2_fr| at its own time resolution 2^j2 (the listing's "time[n2]"), unpadded to
+    the times t with pad_left <= t 2^j2 < pad_left + N. With the second-order rule
+    k1 + k2 = j2 <= log2 T of this plan, the listing's subsampling exponents coincide
+    with the averaged ones. The first order stays averaged (S1 = U1 * phi_T, "time[log2_T]");
+  - ``average_local_fr = False``: k_fr = j_fr instead of min(j_fr, floor(log2 F)), and no
+    phi_F averaging of band-pass paths: each keeps |Y_fr| at log-frequency resolution
+    2^k_fr, unpadded to the bins b with b 2^k_fr < n1_max.
 """
 from __future__ import annotations
 
@@ -59,15 +72,16 @@ class Group:
 
 @dataclass
 class PathBlock:
-    order: int
-    n2: int               # -1 for order 1
-    n_fr: int             # index in the frequential filter list
+    order: int            # 0, 1 or 2
+    n2: int               # -1 for orders 0 and 1
+    n_fr: int             # index in the frequential filter list (-1 for order 0)
     spin: int
-    j2: int               # -1 for order 1
+    j2: int               # -1 for orders 0 and 1
     j_fr: int
     n_lambda: int
     n_frames: int
     offset: int
+    t_lo: int = 0         # first kept sample on the block's time grid
 
 
 @dataclass
@@ -97,6 +111,9 @@ class OraclePlan:
     n_frames: int = 0
     blocks: List[PathBlock] = field(default_factory=list)
     n_coeff: int = 0
+    zeroth: bool = False
+    average_local: bool = True
+    average_local_fr: bool = True
 
     @property
     def N1(self) -> int:
@@ -108,10 +125,12 @@ class OraclePlan:
 
 
 def make_plan(N: int, J: int, Q1: int, Q2: int, J_fr: int, Q_fr: int, log2_T: int, F: float,
-              periodic: bool = False) -> OraclePlan:
+              periodic: bool = False, zeroth: bool = False, average_local: bool = True,
+              average_local_fr: bool = True) -> OraclePlan:
     if N < 2:
         raise ValueError("N must be >= 2")
     p = OraclePlan(N, J, Q1, Q2, J_fr, Q_fr, log2_T, float(F), bool(periodic))
+    p.zeroth, p.average_local, p.average_local_fr = bool(zeroth), bool(average_local), bool(average_local_fr)
     if periodic:
         if N & (N - 1):
             raise ValueError("periodic mode needs N a power of two")
@@ -146,7 +165,7 @@ def make_plan(N: int, J: int, Q1: int, Q2: int, J_fr: int, Q_fr: int, log2_T: in
     for sign in (+1, -1):
         for xi, s in bank_fr:
             j = fb.subsampling_scale(xi, s)
-            p.fr.append(Band(sign * xi, s, j, min(j, p.s_F), spin=sign))
+            p.fr.append(Band(sign * xi, s, j, min(j, p.s_F) if p.average_local_fr else j, spin=sign))
 
     for n2, b2 in enumerate(p.psi2):
         K = 0
@@ -172,18 +191,38 @@ def make_plan(N: int, J: int, Q1: int, Q2: int, J_fr: int, Q_fr: int, log2_T: in
         f_hi = -(-(p.pad_left + N) // p.T)
     p.n_frames = f_hi - p.f_lo
 
-    def bins(K):
-        return -(-K // (1 << p.s_F))
+    def bins(K, k):
+        return -(-K // (1 << k))
+
+    def kept_times(j):
+        """First kept sample and count on a grid of stride 2^j (unpadded samples)."""
+        if periodic:
+            return 0, p.N_pad >> j
+        lo = -(-p.pad_left // (1 << j))
+        return lo, -(-(p.pad_left + N) // (1 << j)) - lo
+
+    def lam(K, b):
+        """Kept log-frequency bins of a path: phi_F-averaged (stride 2^sF) or, for a
+        band-pass without frequential averaging, its own stride 2^k_fr."""
+        return bins(K, b.k if (not b.lowpass and not p.average_local_fr) else p.s_F)
 
     off = 0
+    if p.zeroth:
+        if p.average_local:
+            blk = PathBlock(0, -1, -1, 0, -1, -1, 1, p.n_frames, off, p.f_lo)
+        else:
+            blk = PathBlock(0, -1, -1, 0, -1, -1, 1, N, off, p.pad_left)
+        p.blocks.append(blk)
+        off += blk.n_lambda * blk.n_frames
     for g in p.fr_real():
         b = p.fr[g]
-        blk = PathBlock(1, -1, g, b.spin, -1, b.j, bins(p.N1), p.n_frames, off)
+        blk = PathBlock(1, -1, g, b.spin, -1, b.j, lam(p.N1, b), p.n_frames, off, p.f_lo)
         p.blocks.append(blk)
         off += blk.n_lambda * blk.n_frames
     for grp in p.groups:
+        t_lo, n_t = (p.f_lo, p.n_frames) if p.average_local else kept_times(grp.j2)
         for g, b in enumerate(p.fr):
-            blk = PathBlock(2, grp.n2, g, b.spin, grp.j2, b.j, bins(grp.K), p.n_frames, off)
+            blk = PathBlock(2, grp.n2, g, b.spin, grp.j2, b.j, lam(grp.K, b), n_t, off, t_lo)
             p.blocks.append(blk)
             off += blk.n_lambda * blk.n_frames
     p.n_coeff = off
