@@ -53,17 +53,32 @@ typedef enum {
  *          frequential subsampling is 2^floor(log2 F).
  *  periodic 0: zero-pad to 2^(ceil(log2 n)+1) samples, n split evenly on both sides
  *          (Sec. 3.2 pads both sides); 1: no padding, n must be a power of two.
+ *  flags   0, or JTFS_ZEROTH: the output starts with the zeroth-order block of the Sec. 3.6
+ *          main algorithm, S0 = (x * phi_T) at stride T over the kept frames (one row,
+ *          path order 0). JTFS_NO_AVERAGE_LOCAL / JTFS_NO_AVERAGE_LOCAL_FR (the listings'
+ *          average_local / average_local_fr switched off: U0 = x as zeroth order, second-
+ *          order paths without phi_T, band-pass paths without phi_F) are not implemented
+ *          by the kernels: JTFS_ERR_UNSUPPORTED. Other bits: JTFS_ERR_ARG.
+ *  zeroth_weight  weight of the zeroth-order block in the metamer loss (jtfs_metamer_step,
+ *          jtfs_loss), finite and >= 0; Eqs. 5-7 hold only the first and second orders, so
+ *          0 (the block is output but does not steer the descent) is the paper's loss.
  */
+#define JTFS_ZEROTH 1u
+#define JTFS_NO_AVERAGE_LOCAL 2u
+#define JTFS_NO_AVERAGE_LOCAL_FR 4u
 typedef struct {
   int64_t n;
   int32_t J, Q1, Q2, J_fr, Q_fr, log2_T;
   double F;
   int32_t periodic;
+  uint32_t flags;
+  float zeroth_weight;
 } jtfs_params;
 
 /*
  * One block of the output (the paths of Sec. 2.1 after averaging, Eqs. 3-4).
- * order 1: n2 = j2 = -1, the alpha = 0 paths; order 2: second-order filter n2 with scale j2.
+ * order 0 (JTFS_ZEROTH): n2 = n_fr = j2 = j_fr = -1, one row S0; order 1: n2 = j2 = -1,
+ * the alpha = 0 paths; order 2: second-order filter n2 with scale j2.
  * n_fr indexes the frequential list [phi_F, psi_fr(xi > 0)..., psi_fr(xi < 0)...];
  * spin is 0 for phi_F, +1 / -1 for the two spins (Sec. 3.4). The block holds
  * n_lambda x n_frames FP32 values, row-major (log-frequency bin, then frame), starting
@@ -275,8 +290,10 @@ jtfs_status jtfs_joint_wavelet(jtfs_plan_t plan, int32_t signal, int32_t n2, int
 
 /*
  * jtfs_loss - per-signal metamer loss and its gradient with respect to S (Sec. 2.3):
- * loss[s] = scale ||S_s - T_s||^2 / N_s and dS_s = 2 scale (S_s - T_s) / N_s, where
- * N_s = ||T_s||^2 if `relative` (the relative loss; N_s = 1 when T_s = 0) and 1 otherwise.
+ * loss[s] = scale sum_i w_i (S_s - T_s)_i^2 / N_s and dS_s = 2 scale w (S_s - T_s) / N_s,
+ * where w_i is the signal's zeroth_weight on its zeroth-order block and 1 elsewhere, and
+ * N_s = sum_i w_i T_s,i^2 if `relative` (the relative loss; N_s = 1 when it is 0) and 1
+ * otherwise. jtfs_metamer_step uses the same weights (relative = 0, scale = 1).
  * S, S_target, dS: n_coeff_total device floats in the plan's coefficient layout (dS is
  * overwritten and may not alias S or S_target); loss: batch device floats. Enqueued
  * on `stream`; sums are taken in FP64 in a fixed order.

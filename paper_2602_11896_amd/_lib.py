@@ -23,6 +23,10 @@ JTFS_OPT_GD = 0
 JTFS_OPT_MOMENTUM_BOLD = 1
 JTFS_OPT_ADAM = 2
 
+JTFS_ZEROTH = 1
+JTFS_NO_AVERAGE_LOCAL = 2
+JTFS_NO_AVERAGE_LOCAL_FR = 4
+
 JTFS_REUSE_FORWARD = 1
 JTFS_SHARED_WORKSPACE = 2
 JTFS_NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -34,7 +38,8 @@ STAGE_NAMES = ["signal_dft", "l1_wavelet", "l1_modulus_dft", "l1_average", "orde
 
 class jtfs_params(ctypes.Structure):
     _fields_ = [("n", c_int64), ("J", c_int32), ("Q1", c_int32), ("Q2", c_int32), ("J_fr", c_int32),
-                ("Q_fr", c_int32), ("log2_T", c_int32), ("F", c_double), ("periodic", c_int32)]
+                ("Q_fr", c_int32), ("log2_T", c_int32), ("F", c_double), ("periodic", c_int32),
+                ("flags", ctypes.c_uint32), ("zeroth_weight", ctypes.c_float)]
 
 
 class jtfs_path(ctypes.Structure):

@@ -291,6 +291,10 @@ jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void
   d.R_pad = sp.R_pad;
   d.NW = sp.NW;
   d.y2_total = sp.y2_total;
+  d.z1_total = sp.z1_total;
+  d.s0_off = sp.s0_off;
+  d.s0_band = sp.s0_band;
+  d.w0 = sp.w0;
   return d;
 }
 
@@ -403,6 +407,7 @@ jtfs_status jtfs_plan_tuned(const jtfs_params* sig, int32_t batch, const jtfs_tu
       std::vector<int64_t> bo(sp.groups.size() * sp.fr.size() + sp.fr_real.size(), -1);
       size_t gi = 0, ri = 0;
       for (const jtfs_path& r : sp.paths) {
+        if (r.order == 0) continue;   // the zeroth-order block is written by its own kernel
         if (r.order == 1) {
           bo[sp.groups.size() * sp.fr.size() + ri++] = r.offset;
         } else {
@@ -589,7 +594,8 @@ jtfs_status jtfs_metamer_step(jtfs_plan_t plan, float* y, const float* S_target,
     jtfs_status r = forward_signal(plan, d, sp, st);
     if (r != JTFS_OK) return r;
     jtfs_plan_t p = plan;
-    STAGE(16, jtfs::run_loss(S_y, S_target + plan->s_off[s], dS, loss + s, sp.n_coeff, st));
+    STAGE(16, jtfs::run_loss(S_y, S_target + plan->s_off[s], dS, loss + s, sp.n_coeff, sp.s0_off >= 0 ? sp.n_frames : 0,
+                             sp.w0, st));
     d.dS = dS;
     d.dx = grad;
     r = backward_signal(plan, d, sp, true, st);
@@ -675,7 +681,9 @@ jtfs_status jtfs_loss(jtfs_plan_t plan, const float* S, const float* S_target, f
   hipStream_t st = static_cast<hipStream_t>(stream);
   for (size_t s = 0; s + 1 < plan->s_off.size(); ++s) {
     const int64_t o = plan->s_off[s], n = plan->s_off[s + 1] - o;
-    const hipError_t e = jtfs::run_rel_loss(S + o, S_target + o, dS + o, loss + s, n, relative, scale, st);
+    const jtfs::SigPlan& sp = plan->sig[s];
+    const hipError_t e = jtfs::run_rel_loss(S + o, S_target + o, dS + o, loss + s, n, sp.s0_off >= 0 ? sp.n_frames : 0,
+                                            sp.w0, relative, scale, st);
     if (e != hipSuccess) return fail(JTFS_ERR_HIP, std::string("loss kernel: ") + hipGetErrorString(e));
   }
   return JTFS_OK;

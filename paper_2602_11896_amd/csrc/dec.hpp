@@ -53,8 +53,9 @@ hipError_t run_dec_wgrad(int s, const uint16_t* dzp, const uint16_t* x_ct, int t
 // Adam on the FP32 master parameters (bias corrections bc1 = 1 - beta1^t, bc2 = 1 - beta2^t).
 hipError_t run_dec_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
                         float eps, float bc1, float bc2, hipStream_t st);
-// Per-signal loss: loss[i] = scale ||S_i - T_i||^2 / (relative ? ||T_i||^2 : 1), dS_i its gradient.
-hipError_t run_rel_loss(const float* S, const float* T, float* dS, float* loss, int64_t n, int relative, float scale,
-                        hipStream_t st);
+// Per-signal loss: loss[i] = scale sum w (S_i - T_i)^2 / (relative ? sum w T_i^2 : 1), dS_i its
+// gradient, w = w0 on the first n0 coefficients (the zeroth-order block) and 1 elsewhere.
+hipError_t run_rel_loss(const float* S, const float* T, float* dS, float* loss, int64_t n, int64_t n0, float w0,
+                        int relative, float scale, hipStream_t st);
 
 }  // namespace jtfs

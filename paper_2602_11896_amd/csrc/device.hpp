@@ -53,7 +53,10 @@ struct DevSig {
   int32_t N, N_pad, pad_left, log2_Npad;
   int32_t N1, nf_pad, f_lo, nF, Lf, log2T, N_fr, sF;
   int32_t n_g, n_groups, n_real, R_pad, NW;
-  int64_t y2_total;
+  int64_t y2_total, z1_total;
+  int64_t s0_off;           // zeroth-order coefficients (n_frames), -1: none
+  int32_t s0_band;          // phi_T at level 0 on the N_pad grid
+  float w0;                 // loss weight of the zeroth-order block
 };
 
 }  // namespace jtfs

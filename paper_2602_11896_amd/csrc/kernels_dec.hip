@@ -609,13 +609,14 @@ __global__ void k_dec_adam(float* __restrict__ p, const float* __restrict__ g, f
 
 __global__ __launch_bounds__(1024) void k_rel_loss(const float* __restrict__ S, const float* __restrict__ T,
                                                    float* __restrict__ dS, float* __restrict__ loss, int64_t n,
-                                                   int relative, float scale) {
+                                                   int64_t n0, float w0, int relative, float scale) {
   __shared__ double red[2][1024];
   double e = 0.0, t2 = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double w = i < n0 ? double(w0) : 1.0;
     const double d = double(S[i]) - double(T[i]);
-    e += d * d;
-    t2 += double(T[i]) * double(T[i]);
+    e += w * d * d;
+    t2 += w * double(T[i]) * double(T[i]);
   }
   red[0][threadIdx.x] = e;
   red[1][threadIdx.x] = t2;
@@ -629,7 +630,7 @@ __global__ __launch_bounds__(1024) void k_rel_loss(const float* __restrict__ S, 
   }
   const double norm = relative ? (red[1][0] > 0.0 ? red[1][0] : 1.0) : 1.0;
   const float f = static_cast<float>(2.0 * scale / norm);
-  for (int64_t i = threadIdx.x; i < n; i += 1024) dS[i] = f * (S[i] - T[i]);
+  for (int64_t i = threadIdx.x; i < n; i += 1024) dS[i] = (i < n0 ? w0 : 1.0f) * f * (S[i] - T[i]);
   if (threadIdx.x == 0) loss[0] = static_cast<float>(scale * red[0][0] / norm);
 }
 
@@ -778,9 +779,9 @@ hipError_t run_dec_adam(float* p, const float* g, float* m, float* v, int64_t n,
   return hipGetLastError();
 }
 
-hipError_t run_rel_loss(const float* S, const float* T, float* dS, float* loss, int64_t n, int relative, float scale,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_rel_loss, dim3(1), dim3(1024), 0, st, S, T, dS, loss, n, relative, scale);
+hipError_t run_rel_loss(const float* S, const float* T, float* dS, float* loss, int64_t n, int64_t n0, float w0,
+                        int relative, float scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_rel_loss, dim3(1), dim3(1024), 0, st, S, T, dS, loss, n, n0, w0, relative, scale);
   return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 // Metamer loss and updates (Sec. 2.3).
-//  loss   E = ||S - S_target||^2 (deterministic fixed-order reduction), dS = 2 (S - S_target).
+//  loss   E = sum w (S - S_target)^2 (deterministic fixed-order reduction), dS = 2 w (S - S_target),
+//         w the zeroth-order weight on that block (if any) and 1 elsewhere.
 //  GD     y <- y - lr grad.
 //  Adam   bias-corrected moments; the step counter lives in the state scalars.
 //  MOMENTUM_BOLD  y <- y + u with u <- m u - mu grad; mu grows by bold_up while E does
@@ -18,13 +19,15 @@
 namespace jtfs {
 namespace {
 
-__global__ __launch_bounds__(1024) void k_loss(const float* S, const float* St, float* dS, float* loss, int64_t n) {
+__global__ __launch_bounds__(1024) void k_loss(const float* S, const float* St, float* dS, float* loss, int64_t n,
+                                               int64_t n0, float w0) {
   __shared__ double part[1024];
   double acc = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const float w = i < n0 ? w0 : 1.0f;
     const float d = S[i] - St[i];
-    dS[i] = 2.0f * d;
-    acc += static_cast<double>(d) * d;
+    dS[i] = 2.0f * w * d;
+    acc += static_cast<double>(w) * d * d;
   }
   part[threadIdx.x] = acc;
   __syncthreads();
@@ -106,8 +109,9 @@ __global__ void k_update_scalars(int kind, const float* loss, float* scal, float
 
 }  // namespace
 
-hipError_t run_loss(const float* S, const float* S_target, float* dS, float* loss, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, st, S, S_target, dS, loss, n);
+hipError_t run_loss(const float* S, const float* S_target, float* dS, float* loss, int64_t n, int64_t n0, float w0,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, st, S, S_target, dS, loss, n, n0, w0);
   return hipGetLastError();
 }
 

@@ -463,16 +463,45 @@ __global__ __launch_bounds__(256) void k_s1(DevSig s, int job0) {
   }
 }
 
+// Zeroth order (Sec. 3.6 main algorithm): S0 = Re IDFT_Lf(fold(Xhat . phi_T)) at the kept
+// frames, one workgroup; the Lf-point inverse DFT is computed directly.
+__global__ __launch_bounds__(256) void k_s0(DevSig s) {
+  __shared__ c32 F[1024];
+  const int Lf = s.Lf;
+  const int log2Lf = 31 - __clz(Lf);
+  const Band b = s.bands[s.s0_band];
+  for (int q = threadIdx.x; q < Lf; q += 256) F[q] = fold_gather(s.Xh, b, s.bandvals, Lf, s.log2T, q);
+  __syncthreads();
+  const int tshift = s.log2_Npad - log2Lf;
+  for (int i = threadIdx.x; i < s.nF; i += 256) {
+    const int f = s.f_lo + i;
+    float acc = 0.f;
+    for (int q = 0; q < Lf; ++q) {
+      const c32 w = s.tw[((q * f) & (Lf - 1)) << tshift];   // exp(-2 pi i q f / Lf)
+      acc += F[q].x * w.x + F[q].y * w.y;                    // Re(F exp(+2 pi i q f / Lf))
+    }
+    s.S[s.s0_off + i] = acc / Lf;
+  }
+}
+
 // Adjoint of the first-order averaging onto the spectrum: for each first-order row,
 // dS1hat = DFT_Lf(sum over the real frequential filters of their dS1 contributions).
+// Block N1 (zeroth order present): the DFT of the padded dS0 row, after the dZ1hat rows
+// (the signal-spectrum gather of stage BX reads it with phi_T).
 __global__ __launch_bounds__(256) void k_ds1h(DevSig s) {
   __shared__ float d[1024];
   const int n1 = blockIdx.x;
   const int Lf = s.nf_pad;
   const int log2Lf = 31 - __clz(Lf);
+  const bool zeroth = n1 == s.N1;
   for (int f = threadIdx.x; f < Lf; f += 256) {
     float acc = 0.f;
-    for (int g = 0; g < s.n_real; ++g) acc += s.dS1p[(static_cast<int64_t>(g) * s.N1 + n1) * Lf + f];
+    if (zeroth) {
+      const int i = f - s.f_lo;
+      acc = (i >= 0 && i < s.nF) ? s.dS[s.s0_off + i] : 0.f;
+    } else {
+      for (int g = 0; g < s.n_real; ++g) acc += s.dS1p[(static_cast<int64_t>(g) * s.N1 + n1) * Lf + f];
+    }
     d[f] = acc;
   }
   __syncthreads();
@@ -484,7 +513,10 @@ __global__ __launch_bounds__(256) void k_ds1h(DevSig s) {
       acc.x += d[f] * w.x;
       acc.y += d[f] * w.y;
     }
-    s.dYh[s.y2_total + static_cast<int64_t>(n1) * Lf + m] = acc;
+    if (zeroth)
+      s.dZh[s.z1_total + m] = acc;
+    else
+      s.dYh[s.y2_total + static_cast<int64_t>(n1) * Lf + m] = acc;
   }
 }
 
@@ -532,11 +564,14 @@ hipError_t run_signal_idft(const DevSig& s, const SigPlan& p, hipStream_t st) {
 
 hipError_t run_s1(const DevSig& s, const SigPlan& p, hipStream_t st) {
   hipLaunchKernelGGL(k_s1, dim3(p.psi1.size()), dim3(256), 0, st, s, p.s1_job0);
+  // (the zeroth order is an output of the forward only: a backward recomputing the
+  // first layer passes no coefficient array)
+  if (p.s0_off >= 0 && s.S != nullptr) hipLaunchKernelGGL(k_s0, dim3(1), dim3(256), 0, st, s);
   return hipGetLastError();
 }
 
 hipError_t run_ds1h(const DevSig& s, const SigPlan& p, hipStream_t st) {
-  hipLaunchKernelGGL(k_ds1h, dim3(p.psi1.size()), dim3(256), 0, st, s);
+  hipLaunchKernelGGL(k_ds1h, dim3(p.psi1.size() + (p.s0_off >= 0 ? 1 : 0)), dim3(256), 0, st, s);
   return hipGetLastError();
 }
 

@@ -39,8 +39,10 @@ hipError_t run_order1_bwd(const DevSig& s, const SigPlan& p, hipStream_t st);
 hipError_t run_dy_reduce(const DevSig& s, const SigPlan& p, hipStream_t st);
 
 // kernels_opt.hip
-// loss[0] = ||S - S_target||^2 and dS = 2 (S - S_target) over n coefficients.
-hipError_t run_loss(const float* S, const float* S_target, float* dS, float* loss, int64_t n, hipStream_t st);
+// loss[0] = sum w (S - S_target)^2 and dS = 2 w (S - S_target) over n coefficients, with
+// w = w0 on the first n0 (the zeroth-order block) and 1 elsewhere.
+hipError_t run_loss(const float* S, const float* S_target, float* dS, float* loss, int64_t n, int64_t n0, float w0,
+                    hipStream_t st);
 // Optimiser update of n samples (see jtfs.h); `scal` = this signal's 4 state scalars.
 hipError_t run_update(const jtfs_opt& opt, float* y, const float* grad, const float* loss, float* vec0, float* vec1,
                       float* vec2, float* scal, int64_t n, hipStream_t st);

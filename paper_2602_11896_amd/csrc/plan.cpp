@@ -231,6 +231,14 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     err = "invalid JTFS parameters";
     return JTFS_ERR_ARG;
   }
+  if (prm.flags & (JTFS_NO_AVERAGE_LOCAL | JTFS_NO_AVERAGE_LOCAL_FR)) {
+    err = "the unaveraged variants (no local time or frequential averaging) are not implemented by the kernels";
+    return JTFS_ERR_UNSUPPORTED;
+  }
+  if ((prm.flags & ~JTFS_ZEROTH) || !(prm.zeroth_weight >= 0.f) || !std::isfinite(prm.zeroth_weight)) {
+    err = "unknown flags or a zeroth-order weight that is not finite and non-negative";
+    return JTFS_ERR_ARG;
+  }
   p.N = prm.n;
   if (prm.periodic) {
     if (prm.n & (prm.n - 1)) {
@@ -349,9 +357,16 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     return JTFS_ERR_UNSUPPORTED;
   }
 
-  // ---- output layout: order 1, then order 2 by ascending n2
+  // ---- output layout: (order 0,) order 1, then order 2 by ascending n2
   auto bins = [&](int32_t K) { return (K + (1 << p.sF) - 1) >> p.sF; };
   int64_t off = 0;
+  if (prm.flags & JTFS_ZEROTH) {
+    jtfs_path r{0, -1, -1, 0, -1, -1, 1, p.n_frames, off};
+    p.paths.push_back(r);
+    p.s0_off = off;
+    p.w0 = prm.zeroth_weight;
+    off += r.n_frames;
+  }
   for (int32_t g : p.fr_real) {
     jtfs_path r{1, -1, g, p.fr[g].spin, -1, p.fr[g].j, bins(N1), p.n_frames, off};
     p.paths.push_back(r);
@@ -394,6 +409,14 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   p.band_phiT.assign(static_cast<size_t>(p.log2T + 1), -1);
   for (const Filt& f : p.psi1) {
     if (p.band_phiT[f.k] < 0) p.band_phiT[f.k] = add_lowpass_band(p, p.N_pad >> f.k, p.sigmaT, f.k);
+  }
+  if (p.s0_off >= 0) {
+    if (p.band_phiT[0] < 0) p.band_phiT[0] = add_lowpass_band(p, p.N_pad, p.sigmaT, 0);
+    p.s0_band = p.band_phiT[0];
+    if (p.bands[static_cast<size_t>(p.s0_band)].len > 2 * p.Lf) {
+      err = "phi_T spans more than two aliased blocks of the frame grid";
+      return JTFS_ERR_UNSUPPORTED;
+    }
   }
   for (const Grp& grp : p.groups) {
     const Filt& b2 = p.psi2[grp.n2];
@@ -798,6 +821,8 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     r.t0 = static_cast<int32_t>(p.terms.size());
     for (int32_t n1 = 0; n1 < N1; ++n1)
       p.terms.push_back(GatherTerm{p.z1_off[n1], p.band_psi1[n1], Np >> p.psi1[n1].k});
+    // zeroth order: phi_T times the DFT of the padded dS0 row, kept after the dZ1hat rows
+    if (p.s0_off >= 0) p.terms.push_back(GatherTerm{p.z1_total, p.s0_band, p.Lf});
     r.t1 = static_cast<int32_t>(p.terms.size());
     p.bx_job = static_cast<int32_t>(p.jobs.size());   // emit() appends this single row next
     emit(ST_BX, {r});
@@ -888,7 +913,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   w.dYh = take(sizeof(cfloat) * (p.y2_total + int64_t(N1) * p.Lf));
   w.dS1p = take(sizeof(float) * p.fr_real.size() * N1 * p.nf_pad);
   w.dU1 = take(sizeof(float) * p.z1_total);
-  w.dZh = take(sizeof(cfloat) * p.z1_total);
+  w.dZh = take(sizeof(cfloat) * (p.z1_total + (p.s0_off >= 0 ? p.Lf : 0)));
   w.dXh = take(sizeof(cfloat) * p.N_pad);
   w.grad = take(sizeof(float) * p.N);
   w.bwd_end = o;

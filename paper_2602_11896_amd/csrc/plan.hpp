@@ -118,6 +118,11 @@ struct SigPlan {
   int32_t split1_0[ST_COUNT] = {0}, split1_n[ST_COUNT] = {0};
   int32_t split2_0[ST_COUNT] = {0}, split2_n[ST_COUNT] = {0};
   int32_t s1_job0 = 0;                   // N1 jobs for the S1 stage
+  // zeroth order (JTFS_ZEROTH): S0 coefficients at s0_off (n_frames of them, -1: none),
+  // phi_T at level 0 on the N_pad grid, and the block's loss weight
+  int64_t s0_off = -1;
+  int32_t s0_band = -1;
+  float w0 = 0.f;
   // forward frequential work, in complex multiply-adds (contraction) and real ones (pooling)
   double mac_dense = 0, mac_banded = 0, mac_exec = 0, mac_pool = 0;
   int32_t max_fwd_tiles = 0;

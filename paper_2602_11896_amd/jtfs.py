@@ -26,10 +26,13 @@ class Params:
     log2_T: int
     F: float
     periodic: bool = False
+    zeroth: bool = False          # output the zeroth-order block S0 first (JTFS_ZEROTH)
+    zeroth_weight: float = 0.0    # its weight in the metamer loss
 
     def c(self) -> L.jtfs_params:
         return L.jtfs_params(self.n, self.J, self.Q1, self.Q2, self.J_fr, self.Q_fr, self.log2_T, float(self.F),
-                             1 if self.periodic else 0)
+                             1 if self.periodic else 0, L.JTFS_ZEROTH if self.zeroth else 0,
+                             float(self.zeroth_weight))
 
 
 def _stream(device: torch.device) -> ctypes.c_void_p:

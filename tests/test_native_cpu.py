@@ -61,6 +61,36 @@ def test_plan_matches_oracle_plan(name):
                 r["offset"]) == (b.order, b.n2, b.n_fr, b.spin, b.j2, b.j_fr, b.n_lambda, b.n_frames, b.offset)
 
 
+@pytest.mark.parametrize("name", ["tiny", "cfg1"])
+def test_zeroth_order_layout_matches_oracle(name):
+    # JTFS_ZEROTH: the S0 block first, every other block shifted by the kept frames
+    args = CONFIGS[name]
+    op = make_plan(*args[:8], periodic=args[8], zeroth=True)
+    p = J.Plan(J.Params(*args, zeroth=True, zeroth_weight=0.5))
+    assert p.n_coeff == op.n_coeff
+    rows = p.meta()
+    assert len(rows) == len(op.blocks)
+    for r, b in zip(rows, op.blocks):
+        assert (r["order"], r["n2"], r["n_fr"], r["n_lambda"], r["n_frames"], r["offset"]) == \
+            (b.order, b.n2, b.n_fr, b.n_lambda, b.n_frames, b.offset)
+
+
+def test_unaveraged_variants_and_bad_weights_are_rejected():
+    from paper_2602_11896_amd import _lib as L
+    base = CONFIGS["tiny"]
+    lib = L.lib()
+    for flags, want in ((L.JTFS_NO_AVERAGE_LOCAL, L.JTFS_ERR_UNSUPPORTED),
+                        (L.JTFS_ZEROTH | L.JTFS_NO_AVERAGE_LOCAL_FR, L.JTFS_ERR_UNSUPPORTED), (8, L.JTFS_ERR_ARG)):
+        prm = J.Params(*base).c()
+        prm.flags = flags
+        h = ctypes.c_void_p()
+        assert lib.jtfs_plan(ctypes.byref(prm), 1, ctypes.byref(h)) == want
+    for w in (-1.0, float("nan"), float("inf")):
+        prm = J.Params(*base, zeroth=True, zeroth_weight=w).c()
+        h = ctypes.c_void_p()
+        assert lib.jtfs_plan(ctypes.byref(prm), 1, ctypes.byref(h)) == L.JTFS_ERR_ARG
+
+
 def test_batch_offsets():
     a, b = CONFIGS["tiny"], CONFIGS["cfg1"]
     p = J.Plan([J.Params(*a), J.Params(*b), J.Params(*a)])
