@@ -53,12 +53,17 @@ typedef enum {
  *          frequential subsampling is 2^floor(log2 F).
  *  periodic 0: zero-pad to 2^(ceil(log2 n)+1) samples, n split evenly on both sides
  *          (Sec. 3.2 pads both sides); 1: no padding, n must be a power of two.
- *  flags   0, or JTFS_ZEROTH: the output starts with the zeroth-order block of the Sec. 3.6
- *          main algorithm, S0 = (x * phi_T) at stride T over the kept frames (one row,
- *          path order 0). JTFS_NO_AVERAGE_LOCAL / JTFS_NO_AVERAGE_LOCAL_FR (the listings'
- *          average_local / average_local_fr switched off: U0 = x as zeroth order, second-
- *          order paths without phi_T, band-pass paths without phi_F) are not implemented
- *          by the kernels: JTFS_ERR_UNSUPPORTED. Other bits: JTFS_ERR_ARG.
+ *  flags   any of (other bits: JTFS_ERR_ARG)
+ *          JTFS_ZEROTH: the output starts with the zeroth-order block of the Sec. 3.6 main
+ *            algorithm (one row, path order 0): S0 = (x * phi_T) at stride T over the kept
+ *            frames, or U0 = x (its N samples) with JTFS_NO_AVERAGE_LOCAL;
+ *          JTFS_NO_AVERAGE_LOCAL (the listings' average_local off): second-order paths
+ *            without phi_T, |Y_fr| at their own time resolution 2^j2 over the kept samples
+ *            t (pad_left <= t 2^j2 < pad_left + n; jtfs_path.n_frames per group); first
+ *            order stays averaged. These outputs are as large as U2 itself: the plan
+ *            refuses more than 2^30 of them (JTFS_ERR_UNSUPPORTED);
+ *          JTFS_NO_AVERAGE_LOCAL_FR (average_local_fr off): k_fr = j_fr and no phi_F on
+ *            band-pass paths, whose bins b keep b 2^k_fr < (rows of the path).
  *  zeroth_weight  weight of the zeroth-order block in the metamer loss (jtfs_metamer_step,
  *          jtfs_loss), finite and >= 0; Eqs. 5-7 hold only the first and second orders, so
  *          0 (the block is output but does not steer the descent) is the paper's loss.

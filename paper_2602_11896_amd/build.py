@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjtfs.so")
 
 SOURCES = ["plan.cpp", "abi.cpp", "dec_abi.cpp", "autotune.cpp", "kernels_time.hip", "kernels_freq.hip", "kernels_opt.hip",
-           "kernels_dec.hip", "kernels_init.hip", "kernels_joint.hip", "noalloc.hip"]
+           "kernels_dec.hip", "kernels_init.hip", "kernels_joint.hip", "kernels_unavg.hip", "noalloc.hip"]
 
 # -packed-fp32-ops keeps the compiler from emitting packed FP32 VALU instructions.
 HIP_FLAGS = [

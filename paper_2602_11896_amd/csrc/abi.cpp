@@ -295,6 +295,11 @@ jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void
   d.s0_off = sp.s0_off;
   d.s0_band = sp.s0_band;
   d.w0 = sp.w0;
+  d.u0 = sp.u0 ? 1 : 0;
+  d.no_avg_local = sp.no_avg_local ? 1 : 0;
+  d.no_avg_fr = sp.no_avg_fr ? 1 : 0;
+  d.u2 = reinterpret_cast<float*>(base + w.u2);
+  d.dv = reinterpret_cast<jtfs::c32*>(base + w.dv);
   return d;
 }
 
@@ -339,8 +344,12 @@ jtfs_status forward_signal(jtfs_plan_t p, const jtfs::DevSig& d, const jtfs::Sig
   jtfs_status r = forward_time(p, d, sp, st);
   if (r != JTFS_OK) return r;
   STAGE(4, jtfs::run_order1_fwd(d, sp, st));
-  STAGE(6, jtfs::run_freq_fwd(d, sp, st));
-  STAGE(7, jtfs::run_freq_pool(d, sp, st));
+  if (sp.no_avg_local) {
+    STAGE(6, jtfs::run_unavg_fwd(d, sp, st));
+  } else {
+    STAGE(6, jtfs::run_freq_fwd(d, sp, st));
+    STAGE(7, jtfs::run_freq_pool(d, sp, st));
+  }
   return JTFS_OK;
 }
 
@@ -350,9 +359,13 @@ jtfs_status backward_signal(jtfs_plan_t p, const jtfs::DevSig& d, const jtfs::Si
     jtfs_status r = forward_time(p, d, sp, st);
     if (r != JTFS_OK) return r;
   }
-  STAGE(8, jtfs::run_freq_dP(d, sp, st));
-  STAGE(9, jtfs::run_freq_bwd(d, sp, st));
-  STAGE(18, jtfs::run_dy_reduce(d, sp, st));
+  if (sp.no_avg_local) {
+    STAGE(9, jtfs::run_unavg_bwd(d, sp, st));
+  } else {
+    STAGE(8, jtfs::run_freq_dP(d, sp, st));
+    STAGE(9, jtfs::run_freq_bwd(d, sp, st));
+    STAGE(18, jtfs::run_dy_reduce(d, sp, st));
+  }
   STAGE(10, jtfs::run_order1_bwd(d, sp, st));
   STAGE(11, jtfs::run_ds1h(d, sp, st));
   STAGE(12, jtfs::run_time_stage(jtfs::ST_BYH, d, sp, st));

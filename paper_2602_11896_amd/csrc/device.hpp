@@ -54,9 +54,14 @@ struct DevSig {
   int32_t N1, nf_pad, f_lo, nF, Lf, log2T, N_fr, sF;
   int32_t n_g, n_groups, n_real, R_pad, NW;
   int64_t y2_total, z1_total;
-  int64_t s0_off;           // zeroth-order coefficients (n_frames), -1: none
+  int64_t s0_off;           // zeroth-order coefficients (n_frames, or N for U0), -1: none
   int32_t s0_band;          // phi_T at level 0 on the N_pad grid
   float w0;                 // loss weight of the zeroth-order block
+  int32_t u0;               // the zeroth order is U0 = x
+  int32_t no_avg_local;     // second order without phi_T: |V| at the group's own resolution
+  int32_t no_avg_fr;        // band-pass paths without phi_F, at their own stride 2^k_fr
+  float* u2;                // |V| of the unaveraged second order (R_pad x n_t per group)
+  c32* dv;                  // its gradient dV (same layout, complex)
 };
 
 }  // namespace jtfs

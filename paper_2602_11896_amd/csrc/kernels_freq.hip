@@ -455,9 +455,13 @@ __global__ __launch_bounds__(256) void k_freq_pool(DevSig s) {
   const FreqGroup fg = s.fgroups[gi];
   const FrFilter ff = s.frf[g];
   const int nF = s.nF;
-  const int nb = (fg.K + (1 << s.sF) - 1) >> s.sF;
+  // kept bins: phi_F-averaged (stride 2^sF) or, without frequential averaging, the
+  // band-pass's own stride 2^k (its rows are output as they are)
+  const bool pooled = !ff.lowpass && !s.no_avg_fr;
+  const int kb = pooled || ff.lowpass ? s.sF : ff.k;
+  const int nb = (fg.K + (1 << kb) - 1) >> kb;
   float* out = s.S + s.s_off[gi * s.n_g + g];
-  const int Mrows = ff.lowpass ? nb : ff.M;
+  const int Mrows = pooled ? ff.M : nb;
   // blockIdx.y takes frames [8 y, 8 y + 8) (Mrows <= 1024, so the tile fits P)
   const int fw = max(1, min(nF, 8192 / Mrows));
   const int fb = min(fw, kPoolFrames);
@@ -497,7 +501,7 @@ __global__ __launch_bounds__(256) void k_freq_pool(DevSig s) {
     for (int e = threadIdx.x; e < nb * fc; e += 256) {
       const int b = e / fc, fl = e - b * fc;
       float v;
-      if (ff.lowpass) {
+      if (!pooled) {
         v = P[b * fc + fl];
       } else {
         float acc = 0.f;
@@ -563,13 +567,15 @@ __global__ __launch_bounds__(256) void k_o1_pool(DevSig s) {
   const int g = blockIdx.y;
   const FrFilter ff = s.frf[g];
   const int nF = s.nF;
-  const int nb = (s.N1 + (1 << s.sF) - 1) >> s.sF;
+  const bool pooled = !ff.lowpass && !s.no_avg_fr;
+  const int kb = pooled || ff.lowpass ? s.sF : ff.k;
+  const int nb = (s.N1 + (1 << kb) - 1) >> kb;
   const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (e >= nb * nF) return;   // whole waves leave together (no barriers below)
   const int b = e / nF, f = e - b * nF;
   float v = 0.f;
-  if (ff.lowpass) {
+  if (!pooled) {
     v = lane == 0 ? s.o1[(ff.row0 + b) * nF + f].x : 0.f;
   } else {
     const int sh = s.sF - ff.k;
@@ -592,7 +598,9 @@ __global__ __launch_bounds__(64) void k_o1_dv(DevSig s) {
   if (g >= 0) {
     const FrFilter ff = s.frf[g];
     const int r = row - ff.row0;
-    const int nb = (s.N1 + (1 << s.sF) - 1) >> s.sF;
+    const bool pooled = !ff.lowpass && !s.no_avg_fr;
+    const int kb = pooled || ff.lowpass ? s.sF : ff.k;
+    const int nb = (s.N1 + (1 << kb) - 1) >> kb;
     const float* dout = s.dS + s.s_off[s.n_groups * s.n_g + g];
     if (ff.lowpass) {
       d.x = r < nb ? dout[r * nF + f] : 0.f;
@@ -600,7 +608,11 @@ __global__ __launch_bounds__(64) void k_o1_dv(DevSig s) {
       const int sh = s.sF - ff.k;
       const float* ph = s.tables + ff.phiF;
       float du = 0.f;
-      for (int b = 0; b < nb; ++b) du += ph[((b << sh) - r) & (ff.M - 1)] * dout[b * nF + f];
+      if (pooled) {
+        for (int b = 0; b < nb; ++b) du += ph[((b << sh) - r) & (ff.M - 1)] * dout[b * nF + f];
+      } else if (r < nb) {
+        du = dout[r * nF + f];
+      }
       const c32 v = order1_v(s, row, f);
       const float m = sqrtf(v.x * v.x + v.y * v.y);
       if (m > 0.f) d = c32{du * (v.x / m), du * (v.y / m)};
@@ -678,10 +690,12 @@ __global__ __launch_bounds__(256) void k_freq_dP(DevSig s) {
   if (g >= 0) {
     const FrFilter ff = s.frf[g];
     const int r = row - ff.row0;
-    const int nb = (fg.K + (1 << s.sF) - 1) >> s.sF;
+    const bool pooled = !ff.lowpass && !s.no_avg_fr;
+    const int kb = pooled || ff.lowpass ? s.sF : ff.k;
+    const int nb = (fg.K + (1 << kb) - 1) >> kb;
     const float* in = s.dS + s.s_off[gi * s.n_g + g];
     if (r < ff.M) {
-      if (ff.lowpass) {
+      if (!pooled) {
         v = r < nb ? in[r * nF + f] : 0.f;
       } else {
         const int sh = s.sF - ff.k;
@@ -992,7 +1006,12 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
 hipError_t run_order1_fwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
   const int rows = (p.R_pad * p.n_frames + 63) / 64;
   hipLaunchKernelGGL(k_o1_v, dim3(rows), dim3(64), 0, st, s);
-  const int nb = (static_cast<int>(p.psi1.size()) + (1 << p.sF) - 1) >> p.sF;
+  int nb = 0;   // the most kept bins of any real-list filter
+  for (int32_t g : p.fr_real) {
+    const FrFilter& ff = p.frf[static_cast<size_t>(g)];
+    const int kb = (!ff.lowpass && p.no_avg_fr) ? ff.k : p.sF;
+    nb = std::max(nb, (static_cast<int>(p.psi1.size()) + (1 << kb) - 1) >> kb);
+  }
   hipLaunchKernelGGL(k_o1_pool, dim3((nb * p.n_frames + 3) / 4, p.fr_real.size()), dim3(256), 0, st, s);
   return hipGetLastError();
 }

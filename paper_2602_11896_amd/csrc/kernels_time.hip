@@ -139,9 +139,10 @@ struct Ops<ST_BX> {
   static constexpr int DIR = +1, LB = 16;
   // the gather itself runs beforehand in k_seg_gather, over the whole spectrum at once
   __device__ __forceinline__ static c32 load(const DevSig& s, const RowJob&, const Band&, int idx) { return s.dXh[idx]; }
+  // (U0 = x as zeroth order adds its gradient directly)
   __device__ __forceinline__ static void store(const DevSig& s, const RowJob&, int idx, c32 v) {
     const int k = idx - s.pad_left;
-    if (k >= 0 && k < s.N) s.dx[k] = v.x;
+    if (k >= 0 && k < s.N) s.dx[k] = v.x + ((s.u0 && s.dS != nullptr) ? s.dS[s.s0_off + k] : 0.f);
   }
 };
 
@@ -566,12 +567,15 @@ hipError_t run_s1(const DevSig& s, const SigPlan& p, hipStream_t st) {
   hipLaunchKernelGGL(k_s1, dim3(p.psi1.size()), dim3(256), 0, st, s, p.s1_job0);
   // (the zeroth order is an output of the forward only: a backward recomputing the
   // first layer passes no coefficient array)
-  if (p.s0_off >= 0 && s.S != nullptr) hipLaunchKernelGGL(k_s0, dim3(1), dim3(256), 0, st, s);
+  if (p.s0_off >= 0 && s.S != nullptr) {
+    if (p.u0) return run_u0(s, p, st);
+    hipLaunchKernelGGL(k_s0, dim3(1), dim3(256), 0, st, s);
+  }
   return hipGetLastError();
 }
 
 hipError_t run_ds1h(const DevSig& s, const SigPlan& p, hipStream_t st) {
-  hipLaunchKernelGGL(k_ds1h, dim3(p.psi1.size() + (p.s0_off >= 0 ? 1 : 0)), dim3(256), 0, st, s);
+  hipLaunchKernelGGL(k_ds1h, dim3(p.psi1.size() + (p.s0_off >= 0 && !p.u0 ? 1 : 0)), dim3(256), 0, st, s);
   return hipGetLastError();
 }
 

@@ -29,6 +29,12 @@ hipError_t run_cn_shape(const DevSig& s, const SigPlan& p, const int32_t* band_p
 hipError_t run_joint_wavelet(const DevSig& s, const Band& b, const float* taps, int n_fr_bins, int n_t, float* out,
                              hipStream_t st);
 
+// kernels_unavg.hip: the variants without local averaging (no phi_T on the second order:
+// |W_g Y2| at the group's kept times, then phi_F or not; U0 = x as zeroth order).
+hipError_t run_unavg_fwd(const DevSig& s, const SigPlan& p, hipStream_t st);
+hipError_t run_unavg_bwd(const DevSig& s, const SigPlan& p, hipStream_t st);
+hipError_t run_u0(const DevSig& s, const SigPlan& p, hipStream_t st);
+
 // kernels_freq.hip
 hipError_t run_order1_fwd(const DevSig& s, const SigPlan& p, hipStream_t st);
 hipError_t run_freq_fwd(const DevSig& s, const SigPlan& p, hipStream_t st);

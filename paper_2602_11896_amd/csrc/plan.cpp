@@ -226,16 +226,15 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   }
   p = SigPlan{};
   p.prm = prm;
+  p.no_avg_local = (prm.flags & JTFS_NO_AVERAGE_LOCAL) != 0;
+  p.no_avg_fr = (prm.flags & JTFS_NO_AVERAGE_LOCAL_FR) != 0;
   if (prm.n < 2 || prm.J < 0 || prm.Q1 < 1 || prm.Q2 < 1 || prm.J_fr < 0 || prm.Q_fr < 1 || prm.log2_T < 0 ||
       !(prm.F >= 1.0) || prm.J > 24 || prm.J_fr > 24 || prm.Q1 > 64 || prm.Q2 > 64 || prm.Q_fr > 64) {
     err = "invalid JTFS parameters";
     return JTFS_ERR_ARG;
   }
-  if (prm.flags & (JTFS_NO_AVERAGE_LOCAL | JTFS_NO_AVERAGE_LOCAL_FR)) {
-    err = "the unaveraged variants (no local time or frequential averaging) are not implemented by the kernels";
-    return JTFS_ERR_UNSUPPORTED;
-  }
-  if ((prm.flags & ~JTFS_ZEROTH) || !(prm.zeroth_weight >= 0.f) || !std::isfinite(prm.zeroth_weight)) {
+  if ((prm.flags & ~(JTFS_ZEROTH | JTFS_NO_AVERAGE_LOCAL | JTFS_NO_AVERAGE_LOCAL_FR)) ||
+      !(prm.zeroth_weight >= 0.f) || !std::isfinite(prm.zeroth_weight)) {
     err = "unknown flags or a zeroth-order weight that is not finite and non-negative";
     return JTFS_ERR_ARG;
   }
@@ -290,7 +289,8 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   for (int sign : {+1, -1}) {
     for (auto& xs : bank_fr) {
       Filt f{sign * xs.first, xs.second, subsampling_scale(xs.first, xs.second), 0, sign, false};
-      f.k = std::min(f.j, p.sF);
+      // without frequential averaging a band-pass keeps its own stride 2^j_fr
+      f.k = p.no_avg_fr ? f.j : std::min(f.j, p.sF);
       p.fr.push_back(f);
     }
   }
@@ -358,23 +358,43 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   }
 
   // ---- output layout: (order 0,) order 1, then order 2 by ascending n2
-  auto bins = [&](int32_t K) { return (K + (1 << p.sF) - 1) >> p.sF; };
+  // Kept log-frequency bins of a path: phi_F-averaged (stride 2^sF), or a band-pass
+  // without frequential averaging at its own stride 2^k_fr.
+  auto lam = [&](int32_t K, const Filt& f) {
+    const int32_t k = (!f.lowpass && p.no_avg_fr) ? f.k : p.sF;
+    return (K + (1 << k) - 1) >> k;
+  };
+  // kept samples on a grid of stride 2^j (unpadded part of the signal)
+  auto kept = [&](int32_t j, int32_t& lo) {
+    if (prm.periodic) {
+      lo = 0;
+      return static_cast<int32_t>(p.N_pad >> j);
+    }
+    const int64_t st = int64_t(1) << j;
+    lo = static_cast<int32_t>((p.pad_left + st - 1) / st);
+    return static_cast<int32_t>((p.pad_left + p.N + st - 1) / st - lo);
+  };
   int64_t off = 0;
   if (prm.flags & JTFS_ZEROTH) {
-    jtfs_path r{0, -1, -1, 0, -1, -1, 1, p.n_frames, off};
+    p.u0 = p.no_avg_local;
+    jtfs_path r{0, -1, -1, 0, -1, -1, 1, p.u0 ? static_cast<int32_t>(p.N) : p.n_frames, off};
     p.paths.push_back(r);
     p.s0_off = off;
     p.w0 = prm.zeroth_weight;
     off += r.n_frames;
   }
   for (int32_t g : p.fr_real) {
-    jtfs_path r{1, -1, g, p.fr[g].spin, -1, p.fr[g].j, bins(N1), p.n_frames, off};
+    jtfs_path r{1, -1, g, p.fr[g].spin, -1, p.fr[g].j, lam(N1, p.fr[g]), p.n_frames, off};
     p.paths.push_back(r);
     off += int64_t(r.n_lambda) * r.n_frames;
   }
-  for (const Grp& grp : p.groups) {
+  for (Grp& grp : p.groups) {
+    int32_t t_lo = p.f_lo;
+    const int32_t n_t = p.no_avg_local ? kept(grp.j2, t_lo) : p.n_frames;
+    grp.n_t = n_t;
+    grp.t_lo = t_lo;
     for (int32_t g = 0; g < static_cast<int32_t>(p.fr.size()); ++g) {
-      jtfs_path r{2, grp.n2, g, p.fr[g].spin, grp.j2, p.fr[g].j, bins(grp.K), p.n_frames, off};
+      jtfs_path r{2, grp.n2, g, p.fr[g].spin, grp.j2, p.fr[g].j, lam(grp.K, p.fr[g]), n_t, off};
       p.paths.push_back(r);
       off += int64_t(r.n_lambda) * r.n_frames;
     }
@@ -410,7 +430,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   for (const Filt& f : p.psi1) {
     if (p.band_phiT[f.k] < 0) p.band_phiT[f.k] = add_lowpass_band(p, p.N_pad >> f.k, p.sigmaT, f.k);
   }
-  if (p.s0_off >= 0) {
+  if (p.s0_off >= 0 && !p.u0) {
     if (p.band_phiT[0] < 0) p.band_phiT[0] = add_lowpass_band(p, p.N_pad, p.sigmaT, 0);
     p.s0_band = p.band_phiT[0];
     if (p.bands[static_cast<size_t>(p.s0_band)].len > 2 * p.Lf) {
@@ -564,6 +584,10 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   for (const Grp& grp : p.groups) {
     FreqGroup fg{};
     fg.y2 = p.y2_total;
+    fg.n_t = grp.n_t;
+    fg.t_lo = grp.t_lo;
+    fg.u2 = p.u2_total;
+    if (p.no_avg_local) p.u2_total += static_cast<int64_t>(p.R_pad) * grp.n_t;
     fg.K = grp.K;
     fg.L2 = static_cast<int32_t>(grp.L2);
     fg.j2 = grp.j2;
@@ -618,6 +642,10 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     p.dYpart_total += static_cast<int64_t>(fg.RS) * grp.K * grp.L2;
     p.y2_total += static_cast<int64_t>(grp.K) * grp.L2;
     p.fgroups.push_back(fg);
+  }
+  if (p.u2_total > (int64_t(1) << 30)) {
+    err = "the second-order output without time averaging exceeds 2^30 values";
+    return JTFS_ERR_UNSUPPORTED;
   }
   for (const FreqGroup& fg : p.fgroups) {
     for (size_t g = 0; g < p.frf.size(); ++g) {
@@ -822,7 +850,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     for (int32_t n1 = 0; n1 < N1; ++n1)
       p.terms.push_back(GatherTerm{p.z1_off[n1], p.band_psi1[n1], Np >> p.psi1[n1].k});
     // zeroth order: phi_T times the DFT of the padded dS0 row, kept after the dZ1hat rows
-    if (p.s0_off >= 0) p.terms.push_back(GatherTerm{p.z1_total, p.s0_band, p.Lf});
+    if (p.s0_off >= 0 && !p.u0) p.terms.push_back(GatherTerm{p.z1_total, p.s0_band, p.Lf});
     r.t1 = static_cast<int32_t>(p.terms.size());
     p.bx_job = static_cast<int32_t>(p.jobs.size());   // emit() appends this single row next
     emit(ST_BX, {r});
@@ -907,6 +935,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   w.S = take(sizeof(float) * p.n_coeff);
   w.dS = take(sizeof(float) * p.n_coeff);
   w.o1 = take(sizeof(cfloat) * p.R_pad * p.n_frames);
+  w.u2 = take(sizeof(float) * std::max<int64_t>(p.u2_total, 1));
   w.fwd_end = o;
   w.dP = take(sizeof(float) * std::max<int64_t>(p.dP_total, 1));
   w.dYpart = w.part;
@@ -916,6 +945,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
   w.dZh = take(sizeof(cfloat) * (p.z1_total + (p.s0_off >= 0 ? p.Lf : 0)));
   w.dXh = take(sizeof(cfloat) * p.N_pad);
   w.grad = take(sizeof(float) * p.N);
+  w.dv = take(sizeof(cfloat) * std::max<int64_t>(p.u2_total, 1));
   w.bwd_end = o;
   return JTFS_OK;
 }

@@ -25,6 +25,8 @@ struct Filt {
 struct Grp {
   int32_t n2, j2, K;
   int64_t L2;
+  int32_t n_t = 0, t_lo = 0;   // output times of the group's paths and the first one (L2 grid
+                               // without time averaging, the frame grid with it)
 };
 
 // Stages of the time-axis pipeline (see kernels_time.hip for what each computes).
@@ -47,9 +49,9 @@ struct Launch {
 // Byte offsets of workspace regions for one signal (relative to the signal's segment).
 // part and dYpart are one region (never live at the same time).
 struct WsLayout {
-  size_t Xh, Z1, U1h, S1, Y2, part, psum, scr, S, dS, o1;   // forward (+ loss scratch)
+  size_t Xh, Z1, U1h, S1, Y2, part, psum, scr, S, dS, o1, u2;   // forward (+ loss scratch)
   size_t fwd_end;
-  size_t dP, dYpart, dYh, dS1p, dU1, dZh, dXh, grad;
+  size_t dP, dYpart, dYh, dS1p, dU1, dZh, dXh, grad, dv;
   size_t bwd_end;
 };
 
@@ -123,6 +125,12 @@ struct SigPlan {
   int64_t s0_off = -1;
   int32_t s0_band = -1;
   float w0 = 0.f;
+  bool u0 = false;               // the zeroth order is U0 = x (averaging not local)
+  // the listings' average_local / average_local_fr switched off: second-order paths keep
+  // |Y_fr| at their own time resolution (no phi_T), band-pass paths their own
+  // log-frequency stride 2^j_fr (no phi_F)
+  bool no_avg_local = false, no_avg_fr = false;
+  int64_t u2_total = 0;          // R_pad x sum of the groups' kept times
   // forward frequential work, in complex multiply-adds (contraction) and real ones (pooling)
   double mac_dense = 0, mac_banded = 0, mac_exec = 0, mac_pool = 0;
   int32_t max_fwd_tiles = 0;

@@ -78,7 +78,10 @@ struct FreqGroup {
   int32_t halo;             // phi_T support: |phi_T[d]| <= 1e-9 max beyond circular distance halo
   int32_t fw;               // > 0: each forward chunk pools into a window of fw frames (see plan)
   int32_t nsub;             // row-tile-loop forward: sub-chunks of TC / nsub times per workgroup
-  int32_t pad_;
+  int32_t n_t;              // unaveraged second order: kept times on the L2 grid
+  int64_t u2;               // unaveraged second order: offset of |V| (R_pad x n_t floats) and
+                            // of dV (R_pad x n_t complex) in their regions
+  int32_t t_lo, pad2_;      // unaveraged second order: first kept time on the L2 grid
 };
 
 // Forward frequential work item: rows [rb*64, rb*64+64) x columns [tc*TC, (tc+1)*TC).

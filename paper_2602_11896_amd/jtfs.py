@@ -26,13 +26,16 @@ class Params:
     log2_T: int
     F: float
     periodic: bool = False
-    zeroth: bool = False          # output the zeroth-order block S0 first (JTFS_ZEROTH)
+    zeroth: bool = False          # output the zeroth-order block first (JTFS_ZEROTH)
     zeroth_weight: float = 0.0    # its weight in the metamer loss
+    average_local: bool = True    # False: JTFS_NO_AVERAGE_LOCAL (U0, no phi_T on order 2)
+    average_local_fr: bool = True  # False: JTFS_NO_AVERAGE_LOCAL_FR (k_fr = j_fr, no phi_F)
 
     def c(self) -> L.jtfs_params:
+        flags = ((L.JTFS_ZEROTH if self.zeroth else 0) | (0 if self.average_local else L.JTFS_NO_AVERAGE_LOCAL) |
+                 (0 if self.average_local_fr else L.JTFS_NO_AVERAGE_LOCAL_FR))
         return L.jtfs_params(self.n, self.J, self.Q1, self.Q2, self.J_fr, self.Q_fr, self.log2_T, float(self.F),
-                             1 if self.periodic else 0, L.JTFS_ZEROTH if self.zeroth else 0,
-                             float(self.zeroth_weight))
+                             1 if self.periodic else 0, flags, float(self.zeroth_weight))
 
 
 def _stream(device: torch.device) -> ctypes.c_void_p:

@@ -86,3 +86,33 @@ def test_zeroth_order_weight_in_the_metamer_loss():
     w = descent.block_weights(op, w0)
     assert abs(float(host(lr_)[0]) - E_ref / float(np.dot(w * S_x, S_x))) <= 1e-4 * E_ref / float(np.dot(w * S_x, S_x))
     assert rel(host(dS), 2.0 * w * (S_y - S_x) / float(np.dot(w * S_x, S_x))) <= 1e-5
+
+
+UNAVG = [dict(average_local=False), dict(average_local_fr=False),
+         dict(zeroth=True, average_local=False, average_local_fr=False), dict(zeroth=True, average_local=False)]
+
+
+@pytest.mark.parametrize("args", [TINY, (384, 4, 3, 2, 2, 2, 4, 3), CFG1])
+@pytest.mark.parametrize("flags", UNAVG)
+def test_unaveraged_variants_forward_backward(args, flags):
+    # the average_local / average_local_fr switches of the listings: every block and the
+    # gradient against the oracle
+    print(f"[variants] {flags} {args}", flush=True)
+    op = make_plan(*args, **flags)
+    x = ji.config1_signal(0, n=op.N)
+    y = ji.white_noise_like(x, 1)
+    S_x = fftroute.forward(op, x)
+    S_y, cache = fftroute.forward(op, y, return_cache=True)
+    plan = J.Plan(J.Params(*args, **flags))
+    assert plan.n_coeff == op.n_coeff
+    ws = plan.workspace()
+    yd = dev(y)
+    S = host(plan.forward(yd, ws=ws))
+    for blk in op.blocks:
+        sl = slice(blk.offset, blk.offset + blk.n_lambda * blk.n_frames)
+        assert rel(S[sl], S_y[sl]) <= 1e-4, (blk.order, blk.n2, blk.n_fr, rel(S[sl], S_y[sl]))
+    assert rel(S, S_y) <= 1e-5
+    dS = 2.0 * (S_y - S_x)
+    g_ref = fftroute.backward(op, y, dS, cache=cache)
+    g = host(plan.backward(yd, dev(dS), ws=ws, reuse_forward=True))
+    assert rel(g, g_ref) <= 1e-4

@@ -75,19 +75,28 @@ def test_zeroth_order_layout_matches_oracle(name):
             (b.order, b.n2, b.n_fr, b.n_lambda, b.n_frames, b.offset)
 
 
-def test_unaveraged_variants_and_bad_weights_are_rejected():
-    from paper_2602_11896_amd import _lib as L
-    base = CONFIGS["tiny"]
+@pytest.mark.parametrize("flags", [dict(average_local=False), dict(average_local_fr=False),
+                                   dict(zeroth=True, average_local=False, average_local_fr=False)])
+def test_unaveraged_layout_matches_oracle(flags):
+    args = CONFIGS["tiny"]
+    op = make_plan(*args[:8], periodic=args[8], **flags)
+    p = J.Plan(J.Params(*args, **flags))
+    assert p.n_coeff == op.n_coeff
+    for r, b in zip(p.meta(), op.blocks):
+        assert (r["order"], r["n2"], r["n_fr"], r["n_lambda"], r["n_frames"], r["offset"]) == \
+            (b.order, b.n2, b.n_fr, b.n_lambda, b.n_frames, b.offset)
+    _, _, j, k = p.filters(0, 2)
+    assert k == [b.k for b in op.fr]
+
+
+def test_bad_flags_and_weights_are_rejected():
     lib = L.lib()
-    for flags, want in ((L.JTFS_NO_AVERAGE_LOCAL, L.JTFS_ERR_UNSUPPORTED),
-                        (L.JTFS_ZEROTH | L.JTFS_NO_AVERAGE_LOCAL_FR, L.JTFS_ERR_UNSUPPORTED), (8, L.JTFS_ERR_ARG)):
-        prm = J.Params(*base).c()
-        prm.flags = flags
-        h = ctypes.c_void_p()
-        assert lib.jtfs_plan(ctypes.byref(prm), 1, ctypes.byref(h)) == want
+    prm = J.Params(*CONFIGS["tiny"]).c()
+    prm.flags = 8
+    h = ctypes.c_void_p()
+    assert lib.jtfs_plan(ctypes.byref(prm), 1, ctypes.byref(h)) == L.JTFS_ERR_ARG
     for w in (-1.0, float("nan"), float("inf")):
-        prm = J.Params(*base, zeroth=True, zeroth_weight=w).c()
-        h = ctypes.c_void_p()
+        prm = J.Params(*CONFIGS["tiny"], zeroth=True, zeroth_weight=w).c()
         assert lib.jtfs_plan(ctypes.byref(prm), 1, ctypes.byref(h)) == L.JTFS_ERR_ARG
 
 
