@@ -288,6 +288,24 @@ def hbm_traffic(kernel: str, tuning: dict):
     return round(sum(hits) * 1e6) if hits else None
 
 
+def time_axis_traffic(tuning: dict):
+    """HBM bytes per step of the time-axis kernels (FETCH_SIZE and WRITE_SIZE scaled by a
+    copy, summed over the stage's launches) from the committed counter record, or None
+    when their source changed since or the plan splits long rows at another point."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic.json")))
+        ta = rec["time_axis"]
+        src = open(os.path.join(ROOT, ta["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha1(src).hexdigest()[: len(ta["sha1_prefix"])] != ta["sha1_prefix"]:
+        return None
+    if rec.get("tuning", {}).get("split_bias") != tuning.get("split_bias"):
+        return None
+    return round(sum(ta["hbm_MB_per_step"].values()) * 1e6)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -403,10 +421,11 @@ def main() -> int:
                 "algorithmic_flop_per_launch": flops, "avg_launch_ms": round(t_ms, 4), "launches": n}
 
     t_axis_ms = sum(breakdown.get(k, (0.0, 0))[0] for k in TIME_AXIS_STAGES) / n_brk
+    t_axis_traffic = time_axis_traffic(eff_tuning)
     ta_gbs = TIME_AXIS_ALGO_BYTES_CFG2 / (t_axis_ms * 1e-3) / 1e9
     roofline_time_axis = {"kernels": "time-axis FFT and pointwise stages (" + ", ".join(TIME_AXIS_STAGES) + ")",
                           "bound": "hbm", "achieved": round(ta_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                          "frac": round(ta_gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                          "frac": round(ta_gbs / PEAK_HBM_GBS, 4), "traffic": t_axis_traffic,
                           "algorithmic_bytes_per_step": TIME_AXIS_ALGO_BYTES_CFG2, "ms_per_step": round(t_axis_ms, 4)}
 
     out = {
