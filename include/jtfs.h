@@ -423,6 +423,16 @@ jtfs_status jtfs_dec_backward(jtfs_dec_t dec, const float* params, int32_t batch
 jtfs_status jtfs_dec_adam_step(jtfs_dec_t dec, float* params, const float* grad, float* m, float* v, int64_t step,
                                float lr, float beta1, float beta2, float eps, jtfs_stream_t stream);
 
+/*
+ * jtfs_dec_ws_region - where a hidden layer's state lies in the workspace after
+ * jtfs_dec_forward (which = 0: the activation a_l) or jtfs_dec_backward (which = 1: the
+ * gradient of its pre-activation z_l), for inspection. Both are bfloat16, time-major
+ * [max_batch][t_out][128] (channel fastest), t_out the layer's output length; entries of
+ * signals b >= the call's batch are stale. layer < n_layers - 1 (the output layer has
+ * neither); offset and bytes in bytes from the workspace's start. JTFS_ERR_ARG otherwise.
+ */
+jtfs_status jtfs_dec_ws_region(jtfs_dec_t dec, int32_t layer, int32_t which, size_t* offset, size_t* bytes);
+
 /* Release a decoder description. NULL is ignored. */
 void jtfs_dec_destroy(jtfs_dec_t dec);
 

@@ -142,19 +142,33 @@ def forward(cfg: DecoderConfig, theta: np.ndarray, S: np.ndarray, quantize: bool
     return y, (acts, Ws)
 
 
-def backward(cfg: DecoderConfig, theta: np.ndarray, cache, dy: np.ndarray, quantize: bool = True):
-    """Gradient of <dy, y> with respect to the flat parameter vector."""
+def backward(cfg: DecoderConfig, theta: np.ndarray, cache, dy: np.ndarray, quantize: bool = True,
+             branches=None, dz_out=None):
+    """Gradient of <dy, y> with respect to the flat parameter vector.
+
+    ``branches`` (optional) gives, per hidden layer h < n_layers - 1, a boolean array of
+    that layer's activation shape: True where the derivative of the leaky ReLU is taken
+    as 1, False where it is the leak. By default it is the sign of the activation; a
+    caller comparing with another implementation may pass that implementation's
+    decisions for entries within rounding of zero. ``dz_out`` (optional list) receives
+    the gradient of each hidden layer's pre-activation, index h.
+    """
     q = bf16_round if quantize else (lambda v: np.asarray(v, dtype=np.float64))
     acts, Ws = cache
     grads = [None] * cfg.n_layers
+    if dz_out is not None:
+        dz_out[:] = [None] * (cfg.n_layers - 1)
     dz = np.asarray(dy, dtype=np.float64)[None, :]
     for l in range(cfg.n_layers - 1, -1, -1):
         dW, db, da = upconv_adjoint(dz, acts[l], Ws[l], cfg.strides[l])
         grads[l] = (dW, db)
         if l > 0:
-            # a_{l} = lrelu(z_l): its derivative is 1 where a_l > 0 and leak elsewhere
-            # (a and z share their sign because leak > 0)
-            dz = q(np.where(acts[l] > 0, da, cfg.leak * da))
+            # acts[l] = lrelu(z) of hidden layer l - 1: its derivative is 1 where the
+            # activation is positive and leak elsewhere (a and z share their sign, leak > 0)
+            up = acts[l] > 0 if branches is None else np.asarray(branches[l - 1], dtype=bool)
+            dz = q(np.where(up, da, cfg.leak * da))
+            if dz_out is not None:
+                dz_out[l - 1] = dz
     return np.concatenate([np.concatenate([dW.ravel(), db]) for dW, db in grads])
 
 

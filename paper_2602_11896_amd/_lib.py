@@ -111,6 +111,7 @@ SIGNATURES = [
     ("jtfs_dec_backward", c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("jtfs_dec_adam_step", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_float, ctypes.c_float, c_void_p]),
+    ("jtfs_dec_ws_region", c_int32, [c_void_p, c_int32, c_int32, POINTER(c_size_t), POINTER(c_size_t)]),
     ("jtfs_dec_destroy", None, [c_void_p]),
     ("jtfs_status_str", c_char_p, [c_int32]),
     ("jtfs_last_error", c_char_p, []),

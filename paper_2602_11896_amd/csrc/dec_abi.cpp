@@ -228,6 +228,16 @@ jtfs_status jtfs_dec_adam_step(jtfs_dec_t dec, float* params, const float* grad,
   return JTFS_OK;
 }
 
+jtfs_status jtfs_dec_ws_region(jtfs_dec_t dec, int32_t layer, int32_t which, size_t* offset, size_t* bytes) {
+  if (!dec || !offset || !bytes) return jtfs::report(JTFS_ERR_ARG, "NULL argument");
+  if (layer < 0 || layer >= dec->cfg.n_layers - 1) return jtfs::report(JTFS_ERR_ARG, "not a hidden layer");
+  const Layer& ly = dec->layers[layer];
+  if (which != 0 && which != 1) return jtfs::report(JTFS_ERR_ARG, "which must be 0 (activation) or 1 (its gradient)");
+  *offset = which == 0 ? ly.out_tc : ly.dz_tc;
+  *bytes = size_t(dec->max_batch) * ly.t_out * jtfs::kDecC * 2;
+  return JTFS_OK;
+}
+
 void jtfs_dec_destroy(jtfs_dec_t dec) { delete dec; }
 
 }  // extern "C"

@@ -97,6 +97,15 @@ class Decoder:
                                           _stream(dy.device)), "jtfs_dec_backward")
         return grad
 
+    def ws_region(self, ws: torch.Tensor, layer: int, which: int) -> torch.Tensor:
+        """bfloat16 view [max_batch, t_out, 128] of hidden layer `layer`'s activation
+        (which = 0) or pre-activation gradient (which = 1) in ws (see jtfs_dec_ws_region)."""
+        off, nb = ctypes.c_size_t(), ctypes.c_size_t()
+        L.check(L.lib().jtfs_dec_ws_region(self._h, layer, which, ctypes.byref(off), ctypes.byref(nb)),
+                "jtfs_dec_ws_region")
+        v = ws[off.value: off.value + nb.value].view(torch.bfloat16)
+        return v.view(self.max_batch, -1, 128)
+
     def adam_step(self, params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int,
                   lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
         for t, name in ((params, "params"), (grad, "grad"), (m, "m"), (v, "v")):

@@ -4,8 +4,9 @@ Both sides use the same bfloat16 weights and inputs and round activations and ac
 gradients to bfloat16 at the same points; they differ by FP32 versus FP64 accumulation
 (relative 1e-6 per sum), log1pf versus log1p, and the rare activation whose FP32 and
 FP64 values round to neighbouring bfloat16 numbers (2^-8 relative on that entry).
-Tolerances: relative L2 <= 3e-3 on the waveform, <= 1e-2 on every parameter block of
-the gradient, 1e-6 on Adam and the loss.
+Tolerances: relative L2 <= 2e-3 on the waveform (measured up to 1.3e-3 at full size),
+<= 1e-2 on every parameter block of the gradient and on every hidden pre-activation
+gradient, 1e-6 on Adam and the loss.
 """
 import sys
 
@@ -21,7 +22,7 @@ pytestmark = pytest.mark.gpu
 J = pytest.importorskip("paper_2602_11896_amd.jtfs")
 from paper_2602_11896_amd.decoder import Decoder, DecoderConfig  # noqa: E402
 
-TOL_Y = 3e-3
+TOL_Y = 2e-3
 TOL_G = 1e-2
 
 
@@ -114,7 +115,8 @@ def test_decoder_config4_full_size():
     Waveforms must match; of the gradient only the output layer is compared here: the
     earlier layers pass through leaky-ReLU masks, and an activation within a rounding
     flip of zero can take the other branch on the two sides, changing that entry of the
-    gradient tenfold. The linear variant below checks every layer's gradient.
+    gradient tenfold. The next test checks every layer at leak 0.1 with the branch
+    decisions of those entries matched, and the linear variant every layer at leak 1.
     """
     say("decoder config-4 shape, leak 0.1, batch 2")
     cfg, ocfg = configs([1, 4, 4, 4, 2, 2, 2, 1], 266, 128)
@@ -150,6 +152,58 @@ def test_decoder_config4_full_size():
     e = rel(g_h[-(n_out_w + 1):], g_ref)
     say(f"  output layer gradient rel {e:.2e}")
     assert e <= TOL_G
+
+
+def test_decoder_config4_hidden_gradients_leak():
+    """Full-size decoder with leak 0.1, batch 1: every layer's parameter gradient and
+    every hidden pre-activation gradient against the oracle.
+
+    Both sides round the same values to bfloat16, but an activation whose FP32 and FP64
+    values straddle a rounding boundary differs by one bfloat16 step, and such steps
+    compound with depth; an activation closer to zero than that difference can take the
+    other leaky-ReLU branch. So, per hidden layer: the two-side difference d is measured
+    on the entries whose signs agree, every sign disagreement must lie at an entry with
+    |a| <= d (within the rounding difference of zero), there may be at most 1e-4 of them,
+    and d itself must stay below 2^-4 of the layer's rms (a few bfloat16 steps). The
+    oracle then takes the device's branch on the disagreeing entries only."""
+    say("decoder config-4 shape, leak 0.1, batch 1, all gradients")
+    cfg, ocfg = configs([1, 4, 4, 4, 2, 2, 2, 1], 266, 128)
+    rng = np.random.default_rng(46)
+    theta = params_for(cfg, 7)
+    S = coeffs(rng, 266 * 128)
+    dec = Decoder(cfg, max_batch=1)
+    ws = dec.workspace()
+    p = dev(theta)
+    y = dec.forward(p, dev(S), 1, ws=ws)
+    a_dev = [host(dec.ws_region(ws, h, 0)[0].float()).T for h in range(ocfg.n_layers - 1)]
+    dy = rng.normal(size=65536)
+    g = dec.backward(p, dev(dy), 1, ws)
+    yr, cache = OD.forward(ocfg, theta, S, quantize=True)
+    e = rel(host(y), yr)
+    say(f"  y rel {e:.2e}")
+    assert e <= TOL_Y
+    branches = []
+    for h in range(ocfg.n_layers - 1):
+        a_ref = cache[0][h + 1]
+        assert a_dev[h].shape == a_ref.shape
+        rms = np.sqrt(np.mean(a_ref * a_ref))
+        flip = (a_dev[h] > 0) != (a_ref > 0)
+        d = float(np.max(np.abs(a_dev[h] - a_ref)[~flip]))
+        worst = float(np.max(np.abs(a_ref[flip]))) if flip.any() else 0.0
+        say(f"  layer {h}: rms {rms:.3e}, two-side difference {d / rms:.2e} rms, {int(flip.sum())} sign "
+            f"disagreements, largest |a| among them {worst / rms:.2e} rms")
+        assert d <= 2.0 ** -4 * rms
+        assert flip.sum() <= 1e-4 * flip.size
+        assert worst <= d, f"layer {h}: sign disagreement beyond the rounding difference"
+        branches.append(np.where(flip, a_dev[h] > 0, a_ref > 0))
+    dz_ref = []
+    g_ref = OD.backward(ocfg, theta, cache, dy, quantize=True, branches=branches, dz_out=dz_ref)
+    check_layers(ocfg, host(g), g_ref, TOL_G)
+    for h in range(ocfg.n_layers - 1):
+        dz_dev = host(dec.ws_region(ws, h, 1)[0].float()).T
+        e = rel(dz_dev, dz_ref[h])
+        say(f"  layer {h} dz: rel {e:.2e}")
+        assert e <= TOL_G
 
 
 def test_decoder_config4_linear_gradient():

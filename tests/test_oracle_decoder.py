@@ -143,3 +143,52 @@ def test_config4_decoder_shapes():
     assert cfg.out_len == 65536
     assert [t for _, _, t, _ in cfg.shapes()] == [128, 128, 512, 2048, 8192, 16384, 32768, 65536]
     assert 1.1e6 < D.n_params(cfg) < 1.3e6
+
+
+def test_backward_branches_and_preactivation_gradients():
+    """dz_out holds the gradient of every hidden pre-activation (PyTorch reverse mode);
+    branches equal to the activations' signs change nothing; flipping one entry's branch
+    scales that entry's dz by 1/leak (or leak) and leaves the rest of its layer alone."""
+    cfg = _small_cfg()
+    theta = _theta(cfg, seed=7)
+    rng = np.random.default_rng(8)
+    S = rng.uniform(0.0, 0.1, size=cfg.c_in * cfg.n_frames)
+    dy = rng.normal(size=cfg.out_len)
+    _, cache = D.forward(cfg, theta, S, quantize=False)
+    dz = []
+    g = D.backward(cfg, theta, cache, dy, quantize=False, dz_out=dz)
+    acts = cache[0]
+    same = D.backward(cfg, theta, cache, dy, quantize=False, branches=[a > 0 for a in acts[1:]])
+    np.testing.assert_array_equal(same, g)
+
+    th = torch.tensor(theta, requires_grad=True)
+    a = torch.log1p(torch.tensor(S).reshape(cfg.c_in, cfg.n_frames) / cfg.eps)
+    zs, o = [], 0
+    for l, ((co, ci, _, _), s) in enumerate(zip(cfg.shapes(), cfg.strides)):
+        W = th[o:o + co * ci * 9].reshape(co, ci, 9)
+        o += co * ci * 9
+        b = th[o:o + co]
+        o += co
+        z = torch.nn.functional.conv_transpose1d(a[None], W.flip(2).transpose(0, 1), b, stride=s,
+                                                 padding=4, output_padding=s - 1)[0]
+        if l < cfg.n_layers - 1:
+            z.retain_grad()
+            zs.append(z)
+            a = torch.nn.functional.leaky_relu(z, cfg.leak)
+        else:
+            a = z
+    (a[0] * torch.tensor(dy)).sum().backward()
+    assert len(dz) == cfg.n_layers - 1
+    for h, z in enumerate(zs):
+        np.testing.assert_allclose(dz[h], z.grad.numpy(), rtol=1e-10, atol=1e-12)
+
+    h = 1
+    br = [a > 0 for a in acts[1:]]
+    c, t = np.argwhere(~br[h])[0]
+    br[h][c, t] = True
+    dz2 = []
+    D.backward(cfg, theta, cache, dy, quantize=False, branches=br, dz_out=dz2)
+    np.testing.assert_allclose(dz2[h][c, t], dz[h][c, t] / cfg.leak, rtol=1e-12)
+    keep = np.ones(dz[h].shape, dtype=bool)
+    keep[c, t] = False
+    np.testing.assert_array_equal(dz2[h][keep], dz[h][keep])
