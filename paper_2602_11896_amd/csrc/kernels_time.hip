@@ -256,9 +256,10 @@ __device__ __forceinline__ int tile_row(int e) {
   return row;
 }
 
+// The job's band travels inside the job record (zeros for a row without one).
 template <int ST>
-__device__ __forceinline__ Band job_band(const DevSig& s, const RowJob& j) {
-  return j.band >= 0 ? s.bands[j.band] : Band{0, 0, 0, 0, 0};
+__device__ __forceinline__ Band job_band(const DevSig&, const RowJob& j) {
+  return j.b;
 }
 
 // Single-pass task: `count` rows of 2^LOG2N points in one tile. All sixteen element loads
@@ -324,7 +325,7 @@ template <int ST, int LOG2B>
 __device__ __forceinline__ void split1_ct(const DevSig& s, c32* lds, const SplitTask& tk) {
   using O = Ops<ST>;
   const SplitGeom g = split_geom(LOG2B + tk.log2A, tk.log2A);
-  const RowJob job = s.jobs[tk.job];
+  const RowJob& job = tk.j;
   const Band band = job_band<ST>(s, job);
   const int n1_0 = tk.blk << g.log2C1;
   const TileTw<LOG2B> twp = tile_twiddles<O::DIR, LOG2B>(s.tw, s.log2_Npad);
@@ -400,7 +401,7 @@ template <int ST, int LOG2A>
 __device__ __forceinline__ void split2_ct(const DevSig& s, c32* lds, const SplitTask& tk) {
   using O = Ops<ST>;
   const SplitGeom g = split_geom(tk.log2n, LOG2A);
-  const RowJob job = s.jobs[tk.job];
+  const RowJob& job = tk.j;
   const int k2_0 = tk.blk << g.log2C2;
   const c32* scr = s.scr + tk.scr;
   const TileTw<LOG2A> twp = tile_twiddles<O::DIR, LOG2A>(s.tw, s.log2_Npad);
@@ -450,7 +451,7 @@ __global__ __launch_bounds__(256) void k_s1(DevSig s, int job0) {
   const RowJob j = s.jobs[job0 + blockIdx.x];
   const int Lf = j.n;
   const int log2Lf = 31 - __clz(Lf);
-  const Band b = s.bands[j.band];
+  const Band b = j.b;
   for (int q = threadIdx.x; q < Lf; q += 256) F[q] = fold_gather(s.U1h + j.src, b, s.bandvals, Lf, j.shift, q);
   __syncthreads();
   const int tshift = s.log2_Npad - log2Lf;

@@ -773,7 +773,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
         const SplitGeom g = split_geom(log2n, log2A);
         const int32_t nblk = pass == 1 ? (1 << g.log2A) >> g.log2C1 : (1 << g.log2B) >> g.log2C2;
         for (int32_t r = 0; r < l.njobs; ++r, scr += l.n)
-          for (int32_t b = 0; b < nblk; ++b) p.stasks.push_back(SplitTask{l.job0 + r, log2n, b, log2A, scr});
+          for (int32_t b = 0; b < nblk; ++b) p.stasks.push_back(SplitTask{l.job0 + r, log2n, b, log2A, scr, RowJob{}});
       }
       (pass == 1 ? p.split1_n : p.split2_n)[stage] =
           static_cast<int32_t>(p.stasks.size()) - (pass == 1 ? p.split1_0 : p.split2_0)[stage];
@@ -892,6 +892,10 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     int32_t k1 = p.psi1[n1].k;
     p.jobs.push_back(job(p.z1_off[n1], int64_t(n1) * p.nf_pad, 0, p.band_phiT[k1], Np >> k1, p.Lf, p.log2T - k1));
   }
+
+  // Inline copies: each job carries its band, each two-pass task its job.
+  for (RowJob& j : p.jobs) j.b = j.band >= 0 ? p.bands[static_cast<size_t>(j.band)] : Band{0, 0, 0, 0, 0};
+  for (SplitTask& t : p.stasks) t.j = p.jobs[static_cast<size_t>(t.job)];
 
   // The Fourier-subsampling gathers read, per output bin, one or two aliased blocks of a
   // non-empty band (the subsampling rule keeps a filter's band within two periods of the

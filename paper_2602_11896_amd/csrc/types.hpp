@@ -29,6 +29,8 @@ struct RowJob {
   int32_t n;       // transform length (power of two)
   int32_t shift;   // Fourier subsampling exponent: the fold averages 2^shift blocks
   int32_t t0, t1;  // adjoint gathers: first and end segment (built from a term range)
+  Band b;          // copy of bands[band] (zeros without one), so that a row's loads
+                   // wait for one record, not two in a chain
 };
 
 // A workgroup's share of a single-pass transform stage: `count` consecutive rows of
@@ -42,6 +44,7 @@ struct RowTask {
 struct SplitTask {
   int32_t job, log2n, blk, log2A;   // log2A: the split point n = A B of this row
   int64_t scr;
+  RowJob j;                         // copy of jobs[job]
 };
 
 // One term of a multi-term adjoint gather: out[m] += band[m] * src[m mod src_len]
