@@ -385,9 +385,11 @@ __device__ __forceinline__ void split1_body(const DevSig& s, c32* lds, int task)
 }
 
 // First launch of a stage: the short-row tasks (whole rows in one tile), then pass 1 of
-// every long row; the two sets are independent, so they share one launch.
+// every long row; the two sets are independent, so they share one launch. Three waves per
+// SIMD, except for stage BZH, whose two loads per element would spill registers under
+// that bound (a kernel with scratch also pays for its set-up at every launch).
 template <int ST>
-__global__ __launch_bounds__(256, 3) void k_fft_stage1(DevSig s, int task0, int ntask, int split0) {
+__global__ __launch_bounds__(256, ST == ST_BZH ? 2 : 3) void k_fft_stage1(DevSig s, int task0, int ntask, int split0) {
   __shared__ c32 lds[4096];
   if (static_cast<int>(blockIdx.x) < ntask)
     rows_body<ST>(s, lds, task0 + blockIdx.x);
