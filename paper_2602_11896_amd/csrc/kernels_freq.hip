@@ -718,19 +718,20 @@ __device__ inline int next_live_tile(const DevSig& s, int rt, int rt_hi, int Kal
   return rt;
 }
 
-// H: the pooled-gradient rows of each row tile travel with its W tile through LDS and the
-// Phi_T fragments are loaded once (at most 16 frames, MAXS <= 16); a separate
-// instantiation, so that the other paths' global loads do not make the compiler wait for
-// the W prefetch before the pooling products.
-template <int MAXS, int MAXNT, bool H>
+// HF > 0: the pooled-gradient rows of each row tile travel with its W tile through LDS and
+// the Phi_T fragments are loaded once (at most HF = 16 or 32 frames, MAXS <= 32); a
+// separate instantiation, so that the other paths' global loads do not make the compiler
+// wait for the W prefetch before the pooling products. HF = 0: the pooled gradients are
+// read from global memory inside the row loop (more frames, windowed groups).
+template <int MAXS, int MAXNT, int HF>
 __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
   constexpr int WS = 4 * MAXS;               // W tile columns
   // LDS row pitch (see the forward); the widest variant stays unpadded within 64 KiB
   constexpr int WSP = MAXS >= 64 ? WS : WS + 2;
   constexpr int PER = (16 * WS + 255) / 256;  // W elements staged per thread
-  static_assert(!H || MAXS <= 32, "hoisted pooled gradients need MAXS <= 32");
-  // per buffer: the W tile, then (H) 256 floats of pooled-gradient rows
-  __shared__ c32 wt[2][16 * WSP + (H ? 128 : 0)];
+  static_assert(HF == 0 || (MAXS <= 32 && (HF == 16 || HF == 32)), "hoisting needs MAXS <= 32, HF 16 or 32");
+  // per buffer: the W tile, then (HF > 0) 16 HF floats of pooled-gradient rows
+  __shared__ c32 wt[2][16 * WSP + 8 * HF];
   const BwdItem it = s.bwd_items[item0 + blockIdx.x];
   const FreqGroup fg = s.fgroups[it.grp];
   const int wave = wave_id();
@@ -789,23 +790,27 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
   // times are loaded once, and each row tile's pooled gradients travel with its W tile
   // through LDS instead of being loaded inside the loop.
   auto dpt = [&](int b) { return reinterpret_cast<float*>(wt[b] + 16 * WSP); };
-  constexpr bool hoist = H;
+  constexpr bool hoist = HF > 0;
+  constexpr int NQ = HF > 0 ? HF / 4 : 1;   // 4-frame k-steps of the hoisted pooling adjoint
   const float* dPg = s.dP + fg.dP;
-  float bph[4];
+  float bph[NQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     const int f = 4 * q + lk;
     bph[q] = (hoist && active && f < nF) ? phi[(((s.f_lo + f) << fg.s_t) - (t0 + li)) & (L2 - 1)] : 0.f;
   }
   // complete these loads here: left pending into the loop, they make every pooling
   // product wait for all outstanding loads, the next W tile's prefetch included
 #pragma unroll
-  for (int q = 0; q < 4; ++q) materialize(bph[q]);
+  for (int q = 0; q < NQ; ++q) materialize(bph[q]);
+  // staged pooled-gradient floats (16 rows of nF frames): threadIdx.x and, with 32 frames,
+  // threadIdx.x + 256
   const bool dp_thread = hoist && static_cast<int>(threadIdx.x) < 16 * nF;
+  const bool dp_thread2 = HF > 16 && static_cast<int>(threadIdx.x) + 256 < 16 * nF;
   // frame slots within the phi_T support of this wave's 16 times
   const int sl0 = -floor_div(fg.halo - t0, 1 << fg.s_t);
   const int nsl = floor_div(t0 + 15 + fg.halo, 1 << fg.s_t) - sl0 + 1;
-  float dreg = 0.f;
+  float dreg = 0.f, dreg2 = 0.f;
 
   // stage the first live tile
   int rt = next_live_tile(s, rt_lo, rt_hi, Kal);
@@ -818,6 +823,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
       wt[0][rr * WSP + n] = n < ncols ? s.W[static_cast<int64_t>(rt * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
     }
     if (dp_thread) dpt(0)[threadIdx.x] = dPg[static_cast<int64_t>(rt) * 16 * nF + threadIdx.x];
+    if (dp_thread2) dpt(0)[threadIdx.x + 256] = dPg[static_cast<int64_t>(rt) * 16 * nF + threadIdx.x + 256];
   }
   __syncthreads();
   int buf = 0;
@@ -831,6 +837,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
         wreg[i] = n < ncols ? s.W[static_cast<int64_t>(nxt * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
       }
       if (dp_thread) dreg = dPg[static_cast<int64_t>(nxt) * 16 * nF + threadIdx.x];
+      if (dp_thread2) dreg2 = dPg[static_cast<int64_t>(nxt) * 16 * nF + threadIdx.x + 256];
     }
     const int nlo = load_table(s.rt_nrange, 2 * rt);
     const int nhi = min(load_table(s.rt_nrange, 2 * rt + 1), Kal);
@@ -883,19 +890,19 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
       }
       f4 du = {0.f, 0.f, 0.f, 0.f};
       if constexpr (hoist) {
-        // li nF + f <= 15 * 16 + 15 stays inside the staged rows: read all four operands
+        // li nF + f <= 15 HF + HF - 1 stays inside the staged rows: read all NQ operands
         // at once, then drop the frames beyond nF
         const float* dp = dpt(buf) + li * nF;
-        float dv[4];
+        float dv[NQ];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dv[q] = dp[4 * q + lk];
+        for (int q = 0; q < NQ; ++q) dv[q] = dp[4 * q + lk];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) materialize(dv[q]);
+        for (int q = 0; q < NQ; ++q) materialize(dv[q]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NQ; ++q) {
           if (q < nFq) du = mfma(4 * q + lk < nF ? dv[q] : 0.f, bph[q], du);
         }
-      } else if (nsl < nF) {   // (not H)
+      } else if (nsl < nF) {   // (HF = 0)
         // only the frames whose centres lie within the phi_T support of the wave's times
         const float* dPr = dPg + static_cast<int64_t>(r0 + li) * nF;
         const int nslot = L2 >> fg.s_t;
@@ -978,6 +985,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
         wt[buf ^ 1][rr * WSP + n] = wreg[i];
       }
       if (dp_thread) dpt(buf ^ 1)[threadIdx.x] = dreg;
+      if (dp_thread2) dpt(buf ^ 1)[threadIdx.x + 256] = dreg2;
     }
     __syncthreads();
     buf ^= 1;
@@ -1113,28 +1121,27 @@ hipError_t run_freq_dP(const DevSig& s, const SigPlan& p, hipStream_t st) {
 }
 
 hipError_t run_freq_bwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
-  const bool few_frames = p.n_frames <= 16;
+  // pooled gradients hoisted through LDS for up to 16 or 32 frames, read in the loop beyond
+  const int hf = p.n_frames <= 16 ? 16 : p.n_frames <= 32 ? 32 : 0;
   for (const SigPlan::BwdLaunch& l : p.bwd_launches) {
     const dim3 grid(l.nitems);
+#define JTFS_BWD(S_, NT_)                                                                            \
+  do {                                                                                             \
+    if (hf == 16) hipLaunchKernelGGL((k_freq_bwd<S_, NT_, 16>), grid, dim3(256), 0, st, s, l.item0); \
+    else if (hf == 32) hipLaunchKernelGGL((k_freq_bwd<S_, NT_, 32>), grid, dim3(256), 0, st, s, l.item0); \
+    else hipLaunchKernelGGL((k_freq_bwd<S_, NT_, 0>), grid, dim3(256), 0, st, s, l.item0);          \
+  } while (0)
     switch (l.S) {
-      case 4:
-        if (few_frames) hipLaunchKernelGGL((k_freq_bwd<4, 1, true>), grid, dim3(256), 0, st, s, l.item0);
-        else hipLaunchKernelGGL((k_freq_bwd<4, 1, false>), grid, dim3(256), 0, st, s, l.item0);
+      case 4: JTFS_BWD(4, 1); break;
+      case 8: JTFS_BWD(8, 2); break;
+      case 16: JTFS_BWD(16, 4); break;
+      case 32:   // (32 hoisted frames would spill at this width)
+        if (hf == 16) hipLaunchKernelGGL((k_freq_bwd<32, 8, 16>), grid, dim3(256), 0, st, s, l.item0);
+        else hipLaunchKernelGGL((k_freq_bwd<32, 8, 0>), grid, dim3(256), 0, st, s, l.item0);
         break;
-      case 8:
-        if (few_frames) hipLaunchKernelGGL((k_freq_bwd<8, 2, true>), grid, dim3(256), 0, st, s, l.item0);
-        else hipLaunchKernelGGL((k_freq_bwd<8, 2, false>), grid, dim3(256), 0, st, s, l.item0);
-        break;
-      case 16:
-        if (few_frames) hipLaunchKernelGGL((k_freq_bwd<16, 4, true>), grid, dim3(256), 0, st, s, l.item0);
-        else hipLaunchKernelGGL((k_freq_bwd<16, 4, false>), grid, dim3(256), 0, st, s, l.item0);
-        break;
-      case 32:
-        if (few_frames) hipLaunchKernelGGL((k_freq_bwd<32, 8, true>), grid, dim3(256), 0, st, s, l.item0);
-        else hipLaunchKernelGGL((k_freq_bwd<32, 8, false>), grid, dim3(256), 0, st, s, l.item0);
-        break;
-      default: hipLaunchKernelGGL((k_freq_bwd<64, 16, false>), grid, dim3(256), 0, st, s, l.item0); break;
+      default: hipLaunchKernelGGL((k_freq_bwd<64, 16, 0>), grid, dim3(256), 0, st, s, l.item0); break;
     }
+#undef JTFS_BWD
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -428,3 +428,29 @@ def test_config4_many_frames_parity():
     err = rel(host(dx), g_ref)
     say(f"[parity] config 4 backward: rel L2 {err:.3e}")
     assert err <= TOL_GRAD
+
+
+@pytest.mark.parametrize("args", [(5000, 8, 8, 2, 3, 2, 8, 8.0), (3000, 7, 12, 2, 3, 2, 7, 6.0),
+                                  (2048, 6, 8, 2, 3, 2, 6, 4.0), (2100, 6, 8, 2, 3, 2, 6, 4.0)])
+def test_pooled_gradients_17_to_33_frames(args):
+    """19, 23, 32 and 33 kept frames: up to 32 frames the backward stages each row tile's
+    pooled gradients through LDS (32-frame instantiation, k-step buckets 4 to 16; the
+    32-k-step bucket reads them in the loop), at 33 it reads them in the row loop."""
+    say(f"[parity] frames test {args}")
+    op = make_plan(*args)
+    rng = np.random.default_rng(args[0])
+    x = rng.standard_normal(args[0])
+    y = rng.standard_normal(args[0])
+    S_x = fftroute.forward(op, x)
+    S_y, cache = fftroute.forward(op, y, return_cache=True)
+    plan = J.Plan(J.Params(*args))
+    ws = plan.workspace()
+    yd = dev(y)
+    S = plan.forward(yd, ws=ws)
+    assert_blocks(op, host(S), S_y, f"{op.n_frames} frames forward")
+    dS = 2.0 * (S_y - S_x)
+    g_ref = fftroute.backward(op, y, dS, cache=cache)
+    dx = plan.backward(yd, dev(dS), ws=ws, reuse_forward=True)
+    err = rel(host(dx), g_ref)
+    say(f"[parity] {op.n_frames} frames backward: rel L2 {err:.3e}")
+    assert err <= TOL_GRAD
