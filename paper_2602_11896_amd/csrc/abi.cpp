@@ -46,6 +46,7 @@ struct SigTables {
   const int64_t* s_off;
   const int32_t* band_psi1;   // per first-order filter: its band (level 0, N_pad grid)
   const int32_t* gchunks;
+  const int32_t* live_rt;
 };
 
 struct DeviceArena {
@@ -139,6 +140,7 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     append_bytes(buf, o, sp.stasks);
     append_bytes(buf, o, sp.band_psi1);
     append_bytes(buf, o, sp.gchunks);
+    append_bytes(buf, o, sp.live_rt);
   }
   DeviceArena a;
   if (hipMalloc(&a.base, buf.size() + 256) != hipSuccess) return fail(JTFS_ERR_NOMEM, "hipMalloc of plan tables failed");
@@ -168,6 +170,7 @@ jtfs_status device_tables(jtfs_plan_t p, const DeviceArena** out) {
     t.stasks = reinterpret_cast<const jtfs::SplitTask*>(b + o[15]);
     t.band_psi1 = reinterpret_cast<const int32_t*>(b + o[16]);
     t.gchunks = reinterpret_cast<const int32_t*>(b + o[17]);
+    t.live_rt = reinterpret_cast<const int32_t*>(b + o[18]);
     a.sig.push_back(t);
   }
   if (p->sig.size() > 1) {
@@ -246,6 +249,7 @@ jtfs::DevSig make_devsig(const jtfs_plan_t p, size_t s, const SigTables& t, void
   d.tables = t.tables;
   d.W = t.W;
   d.rt_nrange = t.rt_nrange;
+  d.live_rt = t.live_rt;
   d.frf = t.frf;
   d.fgroups = t.fgroups;
   d.fwd_items = t.fwd_items;

@@ -15,6 +15,7 @@ struct DevSig {
   const float* tables;      // time-domain phi_T / phi_F
   const c32* W;             // R_pad x NW frequential rows
   const int32_t* rt_nrange; // per 16-row tile: n_lo, n_hi
+  const int32_t* live_rt;   // per group (FreqGroup::lt0, nlt): the row tiles whose band meets [0, K)
   const FrFilter* frf;
   const FreqGroup* fgroups;
   const FwdItem* fwd_items;

@@ -46,6 +46,13 @@ __device__ inline int load_table(const int* p, int i) {
   return ((ConstInt*)p)[i];
 }
 
+// Whether row tile rt has non-negligible taps within the first K columns (its rows then
+// meet the group's K stacked rows); the plan lists exactly these tiles per group, the
+// forward and backward visit only them, and the others' pooled rows are zero.
+__device__ __forceinline__ bool tile_live(const DevSig& s, int rt, int K) {
+  return min(load_table(s.rt_nrange, 2 * rt + 1), (K + 3) & ~3) > load_table(s.rt_nrange, 2 * rt);
+}
+
 // Keeps a value live in a register at this point: the reads that produce it are issued
 // (and waited for) here, not sunk into the conditional blocks that use it.
 __device__ inline void materialize(float& x) { asm volatile("" : "+v"(x)); }
@@ -274,9 +281,10 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
   const int nslot = L2 >> fg.s_t;   // frame slots on the padded time axis
   const int slot0 = fg.fw > 0 ? window_start(fg, it.tc) : s.f_lo;
   const int pst = fg.fw > 0 ? fg.fw : nF;   // partial row stride
-  const int nrt = s.R_pad >> 4;
-  const int rt_lo = it.rb * fg.rt_fwd;
-  const int rt_hi = min(nrt, rt_lo + fg.rt_fwd);
+  // this item's share of the group's live row tiles
+  const int32_t* live = s.live_rt + fg.lt0;
+  const int i_lo = it.rb * fg.rt_fwd;
+  const int i_hi = min(fg.nlt, i_lo + fg.rt_fwd);
   const int ncols = min(WS, s.NW);
   float* part = s.part + fg.part + static_cast<int64_t>(it.tc) * s.R_pad * pst;
 
@@ -314,25 +322,27 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
   }
 
   c32 wreg[PER];
+  int rt = i_lo < i_hi ? load_table(live, i_lo) : 0;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int e = threadIdx.x + 256 * i;
     if (e < 16 * WS) {
       const int rr = e / WS, n = e - rr * WS;
-      wt[0][rr * WSP + n] = n < ncols ? s.W[static_cast<int64_t>(rt_lo * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
+      wt[0][rr * WSP + n] = n < ncols ? s.W[static_cast<int64_t>(rt * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
     }
   }
   __syncthreads();
   int buf = 0;
-  for (int rt = rt_lo; rt < rt_hi; ++rt) {
-    const bool next = rt + 1 < rt_hi;
+  for (int il = i_lo; il < i_hi; ++il) {
+    const bool next = il + 1 < i_hi;
+    const int rt_next = next ? load_table(live, il + 1) : 0;
     if (next) {
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const int e = threadIdx.x + 256 * i;
         if (e < 16 * WS) {
           const int rr = e / WS, n = e - rr * WS;
-          wreg[i] = n < ncols ? s.W[static_cast<int64_t>((rt + 1) * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
+          wreg[i] = n < ncols ? s.W[static_cast<int64_t>(rt_next * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
         }
       }
     }
@@ -419,6 +429,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_fwd2(DevSig s, int item0) {
       }
     }
     buf ^= 1;
+    rt = rt_next;
   }
   __syncthreads();   // the next pass restages wt[0] and rewrites red
   }
@@ -433,6 +444,10 @@ __global__ __launch_bounds__(256) void k_freq_psum(DevSig s) {
   const int64_t cells = static_cast<int64_t>(s.R_pad) * s.nF;
   const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (e >= cells) return;
+  if (!tile_live(s, static_cast<int>(e / s.nF) >> 4, fg.K)) {   // not written by the forward
+    s.psum[fg.psum + e] = 0.f;
+    return;
+  }
   const float* src = s.part + fg.part + e;
   float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   int tc = 0;
@@ -473,7 +488,9 @@ __global__ __launch_bounds__(256) void k_freq_pool(DevSig s) {
     for (int e = threadIdx.x; e < Mrows * fc; e += 256) {
       const int r = e / fc, fl = e - r * fc;
       float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      if (fg.fw > 0) {
+      if (fg.fw > 0 && !tile_live(s, (ff.row0 + r) >> 4, fg.K)) {
+        // a row the forward did not visit: zero
+      } else if (fg.fw > 0) {
         // windowed partials: chunk tc holds frame slot f_lo + f at window offset o < fw. The
         // window of chunk t starts at ceil((t TC - halo) / 2^s_t), so only the chunks t with
         // (slot - fw) 2^s_t + halo < t TC <= slot 2^s_t + halo hold the slot (t taken
@@ -712,11 +729,8 @@ __global__ __launch_bounds__(256) void k_freq_dP(DevSig s) {
 // adjoint), dV = dU V / |V|, then dY2 (n x t) += W^H dV; Y2 operands and dY2
 // accumulators stay in registers over the row loop. W tiles are staged in LDS, double
 // buffered: the next live tile's global loads are in flight while the current one is
-// used, and one barrier per tile separates the buffers.
-__device__ inline int next_live_tile(const DevSig& s, int rt, int rt_hi, int Kal) {
-  while (rt < rt_hi && min(load_table(s.rt_nrange, 2 * rt + 1), Kal) <= load_table(s.rt_nrange, 2 * rt)) ++rt;
-  return rt;
-}
+// used, and one barrier per tile separates the buffers. Only the group's live row tiles
+// (the plan's list) are visited.
 
 // HF > 0: the pooled-gradient rows of each row tile travel with its W tile through LDS and
 // the Phi_T fragments are loaded once (at most HF = 16 or 32 frames, MAXS <= 32); a
@@ -780,9 +794,10 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
     dk2[q] = f4{0.f, 0.f, 0.f, 0.f};
     if constexpr (G3) dk3[q] = f4{0.f, 0.f, 0.f, 0.f};
   }
-  const int nrt = s.R_pad >> 4;
-  const int rt_lo = it.rs * fg.rt_per_split;
-  const int rt_hi = min(nrt, rt_lo + fg.rt_per_split);
+  // this item's share of the group's live row tiles
+  const int32_t* live = s.live_rt + fg.lt0;
+  const int i_lo = it.rs * fg.rt_per_split;
+  const int i_hi = min(fg.nlt, i_lo + fg.rt_per_split);
   const float* phi = s.tables + fg.phiT;
   const int nF = s.nF;
   const int nFq = (nF + 3) >> 2;
@@ -813,9 +828,10 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
   float dreg = 0.f, dreg2 = 0.f;
 
   // stage the first live tile
-  int rt = next_live_tile(s, rt_lo, rt_hi, Kal);
+  int il = i_lo;
+  int rt = il < i_hi ? load_table(live, il) : 0;
   c32 wreg[PER];
-  if (rt < rt_hi) {
+  if (il < i_hi) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = threadIdx.x + 256 * i;
@@ -827,9 +843,10 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
   }
   __syncthreads();
   int buf = 0;
-  while (rt < rt_hi) {
-    const int nxt = next_live_tile(s, rt + 1, rt_hi, Kal);
-    if (nxt < rt_hi) {
+  while (il < i_hi) {
+    const bool more = il + 1 < i_hi;
+    const int nxt = more ? load_table(live, il + 1) : 0;
+    if (more) {
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const int e = threadIdx.x + 256 * i;
@@ -977,7 +994,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
         }
       }
     }
-    if (nxt < rt_hi) {
+    if (more) {
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const int e = threadIdx.x + 256 * i;
@@ -990,6 +1007,7 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
     __syncthreads();
     buf ^= 1;
     rt = nxt;
+    ++il;
   }
   if (!active) return;
   c32* dst = s.dYpart + fg.dYpart + static_cast<int64_t>(it.rs) * K * L2;

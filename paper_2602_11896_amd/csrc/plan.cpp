@@ -609,6 +609,14 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     // adds a partial row to sum (measured on MI355X at N = 2^16 with 8 and 128 frames).
     const int64_t max_chunks = nF <= 16 ? 128 : 64;
     const int32_t S = bucket_of(grp.K);
+    // Live row tiles: those whose band of non-negligible taps meets the group's K rows
+    // (the others contribute nothing to V; their pooled rows are zero). Work is split
+    // over these only.
+    fg.lt0 = static_cast<int32_t>(p.live_rt.size());
+    for (int32_t t = 0; t < n_rt; ++t)
+      if (std::min<int32_t>(p.rt_nrange[2 * t + 1], (grp.K + 3) & ~3) > p.rt_nrange[2 * t]) p.live_rt.push_back(t);
+    if (static_cast<int32_t>(p.live_rt.size()) == fg.lt0) p.live_rt.push_back(0);   // (a dead tile: zeros)
+    fg.nlt = static_cast<int32_t>(p.live_rt.size()) - fg.lt0;
     const int32_t wnsub = window_nsub(S, fg);
     fg.fw = wnsub > 0 ? kWindow : 0;
     fg.nsub = std::max(1, wnsub);
@@ -620,8 +628,8 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
       // about 256 workgroups per group: more row splits re-load the same Y2 operands
       // (measured on MI355X, config 2: targets 16..4096 swept, 256 fastest)
       const int32_t want = (tu.fwd_rows_k[bucket_index(S)] + fg.n_tc - 1) / fg.n_tc;
-      const int32_t rs = std::max(1, std::min(want, n_rt / 4));
-      fg.rt_fwd = (n_rt + rs - 1) / rs;
+      const int32_t rs = std::max(1, std::min(want, fg.nlt / 4));
+      fg.rt_fwd = (fg.nlt + rs - 1) / rs;
     } else {
       fg.TC = static_cast<int32_t>(std::max<int64_t>(std::min<int64_t>(grp.L2, 256), grp.L2 / max_chunks));
       fg.n_tc = static_cast<int32_t>(grp.L2 / fg.TC);
@@ -635,9 +643,9 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
     p.dP_total += static_cast<int64_t>(p.R_pad) * nF;
     fg.n_tb = static_cast<int32_t>((grp.L2 + 63) / 64);
     int32_t want = (tu.bwd_rows_k[bucket_index(S)] + fg.n_tb - 1) / fg.n_tb;
-    fg.RS = std::max(1, std::min(want, n_rt / 4));
-    fg.rt_per_split = (n_rt + fg.RS - 1) / fg.RS;
-    fg.RS = (n_rt + fg.rt_per_split - 1) / fg.rt_per_split;
+    fg.RS = std::max(1, std::min(want, fg.nlt / 4));
+    fg.rt_per_split = (fg.nlt + fg.RS - 1) / fg.RS;
+    fg.RS = (fg.nlt + fg.rt_per_split - 1) / fg.rt_per_split;
     fg.dYpart = p.dYpart_total;
     p.dYpart_total += static_cast<int64_t>(fg.RS) * grp.K * grp.L2;
     p.y2_total += static_cast<int64_t>(grp.K) * grp.L2;
@@ -672,7 +680,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
         for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
           const FreqGroup& fg = p.fgroups[gi];
           if (bucket_of(fg.K) != S || fg.fw == 0) continue;
-          const int32_t nrs = (n_rt + fg.rt_fwd - 1) / fg.rt_fwd;
+          const int32_t nrs = (fg.nlt + fg.rt_fwd - 1) / fg.rt_fwd;
           for (int32_t tc = 0; tc < fg.n_tc; ++tc)
             for (int32_t rs = 0; rs < nrs; ++rs) p.fwd_items.push_back(FwdItem{gi, rs, tc, 0});
         }
@@ -685,7 +693,7 @@ jtfs_status build_signal_plan(const jtfs_params& prm, SigPlan& p, std::string& e
         for (int32_t gi = 0; gi < static_cast<int32_t>(p.fgroups.size()); ++gi) {
           const FreqGroup& fg = p.fgroups[gi];
           if (bucket_of(fg.K) != S) continue;
-          const int32_t nrs = (n_rt + fg.rt_fwd - 1) / fg.rt_fwd;
+          const int32_t nrs = (fg.nlt + fg.rt_fwd - 1) / fg.rt_fwd;
           for (int32_t tc = 0; tc < fg.n_tc; ++tc)
             for (int32_t rs = 0; rs < nrs; ++rs) p.fwd_items.push_back(FwdItem{gi, rs, tc, 0});
         }

@@ -111,6 +111,7 @@ struct SigPlan {
   // pass-2 launch, each row with its own scratch (tasks of stage st: [split0, split0 + nsplit)
   // for pass 1, then the same count shifted by nsplit1 for pass 2).
   std::vector<SplitTask> stasks;
+  std::vector<int32_t> live_rt;                // per group: its live 16-row tiles, ascending
   // Bin-parallel adjoint gathers (stages BU and BX): chunks of up to 256 output bins of
   // one row, pairs (job, first bin); the chunks of stage st are [gch0[st], gch0[st] + gchn[st]).
   std::vector<int32_t> gchunks;

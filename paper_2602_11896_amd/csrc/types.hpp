@@ -85,6 +85,7 @@ struct FreqGroup {
   int64_t u2;               // unaveraged second order: offset of |V| (R_pad x n_t floats) and
                             // of dV (R_pad x n_t complex) in their regions
   int32_t t_lo, pad2_;      // unaveraged second order: first kept time on the L2 grid
+  int32_t lt0, nlt;         // live row tiles (rows meeting [0, K)): live_rt[lt0 .. lt0 + nlt)
 };
 
 // Forward frequential work item: rows [rb*64, rb*64+64) x columns [tc*TC, (tc+1)*TC).
