@@ -698,6 +698,7 @@ __global__ __launch_bounds__(256) void k_freq_dP(DevSig s) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= s.R_pad * nF) return;
   const int row = e / nF, f = e - (e / nF) * nF;
+  if (!tile_live(s, row >> 4, fg.K)) return;   // (the backward reads live row tiles only)
   int g = -1;
   for (int q = 0; q < s.n_g; ++q) {
     const FrFilter c = s.frf[q];
