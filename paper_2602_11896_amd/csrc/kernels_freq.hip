@@ -738,13 +738,17 @@ __global__ __launch_bounds__(256) void k_freq_dP(DevSig s) {
 // separate instantiation, so that the other paths' global loads do not make the compiler
 // wait for the W prefetch before the pooling products. HF = 0: the pooled gradients are
 // read from global memory inside the row loop (more frames, windowed groups).
-template <int MAXS, int MAXNT, int HF>
+// WIN (with HF = 32, more than 32 frames): the staged frames are the slots within the
+// phi_T support of the workgroup's 64 times (at most 32, checked by the launcher), and
+// each wave pools only its own slots among them.
+template <int MAXS, int MAXNT, int HF, bool WIN = false>
 __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
   constexpr int WS = 4 * MAXS;               // W tile columns
   // LDS row pitch (see the forward); the widest variant stays unpadded within 64 KiB
   constexpr int WSP = MAXS >= 64 ? WS : WS + 2;
   constexpr int PER = (16 * WS + 255) / 256;  // W elements staged per thread
   static_assert(HF == 0 || (MAXS <= 32 && (HF == 16 || HF == 32)), "hoisting needs MAXS <= 32, HF 16 or 32");
+  static_assert(!WIN || HF == 32, "windowed hoisting stages 32 slots");
   // per buffer: the W tile, then (HF > 0) 16 HF floats of pooled-gradient rows
   __shared__ c32 wt[2][16 * WSP + 8 * HF];
   const BwdItem it = s.bwd_items[item0 + blockIdx.x];
@@ -809,23 +813,51 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
   constexpr bool hoist = HF > 0;
   constexpr int NQ = HF > 0 ? HF / 4 : 1;   // 4-frame k-steps of the hoisted pooling adjoint
   const float* dPg = s.dP + fg.dP;
+  // frame slots within the phi_T support of this wave's 16 times
+  const int sl0 = -floor_div(fg.halo - t0, 1 << fg.s_t);
+  const int nsl = floor_div(t0 + 15 + fg.halo, 1 << fg.s_t) - sl0 + 1;
+  const int nslot = L2 >> fg.s_t;
+  // staged window: W frames per row (all kept frames, or the workgroup's WIN slots from sw0);
+  // this wave's slots start at offset ow in it
+  int W = nF, sw0 = s.f_lo, ow = 0;
+  if constexpr (WIN) {
+    const int tw0 = it.tb * 64;
+    sw0 = -floor_div(fg.halo - tw0, 1 << fg.s_t);
+    W = floor_div(tw0 + 63 + fg.halo, 1 << fg.s_t) - sw0 + 1;
+    ow = sl0 - sw0;
+  }
   float bph[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int f = 4 * q + lk;
-    bph[q] = (hoist && active && f < nF) ? phi[(((s.f_lo + f) << fg.s_t) - (t0 + li)) & (L2 - 1)] : 0.f;
+    if constexpr (WIN) {
+      const int sl = ((sl0 + f) % nslot + nslot) % nslot;
+      const int fk = sl - s.f_lo;
+      bph[q] = (active && f < nsl && fk >= 0 && fk < nF) ? phi[((sl << fg.s_t) - (t0 + li)) & (L2 - 1)] : 0.f;
+    } else {
+      bph[q] = (hoist && active && f < nF) ? phi[(((s.f_lo + f) << fg.s_t) - (t0 + li)) & (L2 - 1)] : 0.f;
+    }
   }
   // complete these loads here: left pending into the loop, they make every pooling
   // product wait for all outstanding loads, the next W tile's prefetch included
 #pragma unroll
   for (int q = 0; q < NQ; ++q) materialize(bph[q]);
-  // staged pooled-gradient floats (16 rows of nF frames): threadIdx.x and, with 32 frames,
-  // threadIdx.x + 256
-  const bool dp_thread = hoist && static_cast<int>(threadIdx.x) < 16 * nF;
-  const bool dp_thread2 = HF > 16 && static_cast<int>(threadIdx.x) + 256 < 16 * nF;
-  // frame slots within the phi_T support of this wave's 16 times
-  const int sl0 = -floor_div(fg.halo - t0, 1 << fg.s_t);
-  const int nsl = floor_div(t0 + 15 + fg.halo, 1 << fg.s_t) - sl0 + 1;
+  // staged pooled-gradient floats (16 rows of W frames): element threadIdx.x and, with 32
+  // frames, threadIdx.x + 256; doff = its offset in a row tile's dP rows (-1: a slot
+  // outside the kept frames, staged as zero)
+  const bool dp_thread = hoist && static_cast<int>(threadIdx.x) < 16 * W;
+  const bool dp_thread2 = HF > 16 && static_cast<int>(threadIdx.x) + 256 < 16 * W;
+  int doff = threadIdx.x, doff2 = threadIdx.x + 256;
+  if constexpr (WIN) {
+    auto off = [&](int e) {
+      const int rr = e / W, k = e - rr * W;
+      const int fk = ((sw0 + k) % nslot + nslot) % nslot - s.f_lo;
+      return (fk >= 0 && fk < nF) ? rr * nF + fk : -1;
+    };
+    doff = dp_thread ? off(threadIdx.x) : -1;
+    doff2 = dp_thread2 ? off(threadIdx.x + 256) : -1;
+  }
+  auto dp_at = [&](int t, int o) { return o >= 0 ? dPg[static_cast<int64_t>(t) * 16 * nF + o] : 0.f; };
   float dreg = 0.f, dreg2 = 0.f;
 
   // stage the first live tile
@@ -839,8 +871,8 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
       const int rr = e / WS, n = e - rr * WS;
       wt[0][rr * WSP + n] = n < ncols ? s.W[static_cast<int64_t>(rt * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
     }
-    if (dp_thread) dpt(0)[threadIdx.x] = dPg[static_cast<int64_t>(rt) * 16 * nF + threadIdx.x];
-    if (dp_thread2) dpt(0)[threadIdx.x + 256] = dPg[static_cast<int64_t>(rt) * 16 * nF + threadIdx.x + 256];
+    if (dp_thread) dpt(0)[threadIdx.x] = dp_at(rt, doff);
+    if (dp_thread2) dpt(0)[threadIdx.x + 256] = dp_at(rt, doff2);
   }
   __syncthreads();
   int buf = 0;
@@ -854,8 +886,8 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
         const int rr = e / WS, n = e - rr * WS;
         wreg[i] = n < ncols ? s.W[static_cast<int64_t>(nxt * 16 + rr) * s.NW + n] : c32{0.f, 0.f};
       }
-      if (dp_thread) dreg = dPg[static_cast<int64_t>(nxt) * 16 * nF + threadIdx.x];
-      if (dp_thread2) dreg2 = dPg[static_cast<int64_t>(nxt) * 16 * nF + threadIdx.x + 256];
+      if (dp_thread) dreg = dp_at(nxt, doff);
+      if (dp_thread2) dreg2 = dp_at(nxt, doff2);
     }
     const int nlo = load_table(s.rt_nrange, 2 * rt);
     const int nhi = min(load_table(s.rt_nrange, 2 * rt + 1), Kal);
@@ -907,7 +939,21 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
         vi[v] = G3 ? k1[v] + k2[v] : k2[v];
       }
       f4 du = {0.f, 0.f, 0.f, 0.f};
-      if constexpr (hoist) {
+      if constexpr (WIN) {
+        // this wave's nsl slots start at ow in the staged window: read all NQ operands at
+        // once (indices clamped into the row), then drop the slots beyond nsl
+        const float* dp = dpt(buf) + li * W;
+        float dv[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) dv[q] = dp[min(ow + 4 * q + lk, W - 1)];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) materialize(dv[q]);
+        const int nq = (nsl + 3) >> 2;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          if (q < nq) du = mfma(4 * q + lk < nsl ? dv[q] : 0.f, bph[q], du);
+        }
+      } else if constexpr (hoist) {
         // li nF + f <= 15 HF + HF - 1 stays inside the staged rows: read all NQ operands
         // at once, then drop the frames beyond nF
         const float* dp = dpt(buf) + li * nF;
@@ -923,7 +969,6 @@ __global__ __launch_bounds__(256, 2) void k_freq_bwd(DevSig s, int item0) {
       } else if (nsl < nF) {   // (HF = 0)
         // only the frames whose centres lie within the phi_T support of the wave's times
         const float* dPr = dPg + static_cast<int64_t>(r0 + li) * nF;
-        const int nslot = L2 >> fg.s_t;
         for (int q = 0; q < (nsl + 3) >> 2; ++q) {
           const int k = 4 * q + lk;
           const int sl = ((sl0 + k) % nslot + nslot) % nslot;
@@ -1140,14 +1185,28 @@ hipError_t run_freq_dP(const DevSig& s, const SigPlan& p, hipStream_t st) {
 }
 
 hipError_t run_freq_bwd(const DevSig& s, const SigPlan& p, hipStream_t st) {
-  // pooled gradients hoisted through LDS for up to 16 or 32 frames, read in the loop beyond
-  const int hf = p.n_frames <= 16 ? 16 : p.n_frames <= 32 ? 32 : 0;
+  // pooled gradients hoisted through LDS for up to 16 or 32 frames; beyond, the slots of
+  // each workgroup's phi_T window when every group of the launch keeps that within 32
+  // (k-step buckets up to 16), else read in the loop
+  const int hf0 = p.n_frames <= 16 ? 16 : p.n_frames <= 32 ? 32 : 0;
   for (const SigPlan::BwdLaunch& l : p.bwd_launches) {
     const dim3 grid(l.nitems);
+    int hf = hf0;
+    if (hf == 0 && l.S <= 16) {
+      bool fits = true;
+      for (const FreqGroup& fg : p.fgroups) {
+        const int need = (fg.K + 3) / 4;
+        const int bucket = need <= 4 ? 4 : need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 64;
+        // widest window of a 64-time block: floor((63 + 2 halo) / 2^s_t) + 2 slots
+        if (bucket == l.S && (63 + 2 * fg.halo) / (1 << fg.s_t) + 2 > 32) fits = false;
+      }
+      if (fits) hf = -1;
+    }
 #define JTFS_BWD(S_, NT_)                                                                            \
   do {                                                                                             \
     if (hf == 16) hipLaunchKernelGGL((k_freq_bwd<S_, NT_, 16>), grid, dim3(256), 0, st, s, l.item0); \
     else if (hf == 32) hipLaunchKernelGGL((k_freq_bwd<S_, NT_, 32>), grid, dim3(256), 0, st, s, l.item0); \
+    else if (hf == -1) hipLaunchKernelGGL((k_freq_bwd<S_, NT_, 32, true>), grid, dim3(256), 0, st, s, l.item0); \
     else hipLaunchKernelGGL((k_freq_bwd<S_, NT_, 0>), grid, dim3(256), 0, st, s, l.item0);          \
   } while (0)
     switch (l.S) {

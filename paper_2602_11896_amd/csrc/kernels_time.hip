@@ -446,22 +446,30 @@ __global__ __launch_bounds__(256) void k_fft_split2(DevSig s, int task0) {
   }
 }
 
+// The Lf twiddles exp(-2 pi i q / Lf), q < Lf <= 1024, into LDS (the direct DFTs below
+// read each of them Lf times).
+__device__ __forceinline__ void stage_twiddles(const DevSig& s, c32* Tw, int Lf, int log2Lf) {
+  const int tshift = s.log2_Npad - log2Lf;
+  for (int q = threadIdx.x; q < Lf; q += 256) Tw[q] = s.tw[q << tshift];
+}
+
 // First-order averaging (Eq. 3 before phi_F): S1 = Re IDFT_Lf(fold(U1hat . phi_T^(k1))),
 // one workgroup per first-order row; the Lf-point inverse DFT is computed directly.
 __global__ __launch_bounds__(256) void k_s1(DevSig s, int job0) {
   __shared__ c32 F[1024];
+  __shared__ c32 Tw[1024];
   const RowJob j = s.jobs[job0 + blockIdx.x];
   const int Lf = j.n;
   const int log2Lf = 31 - __clz(Lf);
   const Band b = j.b;
   for (int q = threadIdx.x; q < Lf; q += 256) F[q] = fold_gather(s.U1h + j.src, b, s.bandvals, Lf, j.shift, q);
+  stage_twiddles(s, Tw, Lf, log2Lf);
   __syncthreads();
-  const int tshift = s.log2_Npad - log2Lf;
   for (int f = threadIdx.x; f < Lf; f += 256) {
     float acc = 0.f;
     for (int q = 0; q < Lf; ++q) {
-      const c32 w = s.tw[((q * f) & (Lf - 1)) << tshift];   // exp(-2 pi i q f / Lf)
-      acc += F[q].x * w.x + F[q].y * w.y;                    // Re(F exp(+2 pi i q f / Lf))
+      const c32 w = Tw[(q * f) & (Lf - 1)];   // exp(-2 pi i q f / Lf)
+      acc += F[q].x * w.x + F[q].y * w.y;     // Re(F exp(+2 pi i q f / Lf))
     }
     s.S1[j.dst + f] = acc / Lf;
   }
@@ -471,18 +479,19 @@ __global__ __launch_bounds__(256) void k_s1(DevSig s, int job0) {
 // frames, one workgroup; the Lf-point inverse DFT is computed directly.
 __global__ __launch_bounds__(256) void k_s0(DevSig s) {
   __shared__ c32 F[1024];
+  __shared__ c32 Tw[1024];
   const int Lf = s.Lf;
   const int log2Lf = 31 - __clz(Lf);
   const Band b = s.bands[s.s0_band];
   for (int q = threadIdx.x; q < Lf; q += 256) F[q] = fold_gather(s.Xh, b, s.bandvals, Lf, s.log2T, q);
+  stage_twiddles(s, Tw, Lf, log2Lf);
   __syncthreads();
-  const int tshift = s.log2_Npad - log2Lf;
   for (int i = threadIdx.x; i < s.nF; i += 256) {
     const int f = s.f_lo + i;
     float acc = 0.f;
     for (int q = 0; q < Lf; ++q) {
-      const c32 w = s.tw[((q * f) & (Lf - 1)) << tshift];   // exp(-2 pi i q f / Lf)
-      acc += F[q].x * w.x + F[q].y * w.y;                    // Re(F exp(+2 pi i q f / Lf))
+      const c32 w = Tw[(q * f) & (Lf - 1)];   // exp(-2 pi i q f / Lf)
+      acc += F[q].x * w.x + F[q].y * w.y;     // Re(F exp(+2 pi i q f / Lf))
     }
     s.S[s.s0_off + i] = acc / Lf;
   }
@@ -494,6 +503,7 @@ __global__ __launch_bounds__(256) void k_s0(DevSig s) {
 // (the signal-spectrum gather of stage BX reads it with phi_T).
 __global__ __launch_bounds__(256) void k_ds1h(DevSig s) {
   __shared__ float d[1024];
+  __shared__ c32 Tw[1024];
   const int n1 = blockIdx.x;
   const int Lf = s.nf_pad;
   const int log2Lf = 31 - __clz(Lf);
@@ -508,12 +518,12 @@ __global__ __launch_bounds__(256) void k_ds1h(DevSig s) {
     }
     d[f] = acc;
   }
+  stage_twiddles(s, Tw, Lf, log2Lf);
   __syncthreads();
-  const int tshift = s.log2_Npad - log2Lf;
   for (int m = threadIdx.x; m < Lf; m += 256) {
     c32 acc{0.f, 0.f};
     for (int f = 0; f < Lf; ++f) {
-      const c32 w = s.tw[((m * f) & (Lf - 1)) << tshift];
+      const c32 w = Tw[(m * f) & (Lf - 1)];
       acc.x += d[f] * w.x;
       acc.y += d[f] * w.y;
     }
