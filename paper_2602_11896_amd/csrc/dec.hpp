@@ -28,6 +28,20 @@ inline int64_t dec_out_chunks(int batch, int t) { return int64_t(batch) * ((t + 
 // Weight copies of one layer from the FP32 master [c_out][c_in][9].
 hipError_t run_dec_cast(const float* W, int c_in, int cip, int c_out, uint16_t* wf, uint16_t* wd, float* wout,
                         hipStream_t st);
+// The weight copies of every layer in one launch: layer l's master W[l] ([c_out][c_in][9]),
+// its forward copy wf[l] and data-gradient copy wd[l] (either may be null) or, for the
+// one-channel output layer, its rounded FP32 copy wout (non-null only there).
+constexpr int kDecMaxLayers = 8;
+struct DecCastSet {
+  const float* W[kDecMaxLayers];
+  uint16_t* wf[kDecMaxLayers];
+  uint16_t* wd[kDecMaxLayers];
+  int c_in[kDecMaxLayers], cip[kDecMaxLayers], c_out[kDecMaxLayers];
+  int64_t end[kDecMaxLayers];   // running end of layer l's elements (wf, then wd, then wout)
+  float* wout;
+  int n;
+};
+hipError_t run_dec_cast_all(const DecCastSet& set, hipStream_t st);
 // a_0 = bf16(log1p(S / eps)) in TC [B][F][cip] and CT layouts; S is [B][c_in][F] FP32.
 hipError_t run_dec_input(const float* S, int batch, int c_in, int F, int cip, float eps, uint16_t* x_tc,
                          uint16_t* x_ct, hipStream_t st);

@@ -163,14 +163,28 @@ jtfs_status jtfs_dec_forward(jtfs_dec_t dec, const float* params, const float* S
   const jtfs_dec_config& c = dec->cfg;
   const auto& Ls = dec->layers;
   const int L = c.n_layers;
+  // every layer's bfloat16 weight copies (and the output layer's rounded FP32 copy) in one launch
+  jtfs::DecCastSet cs{};
+  cs.n = L;
+  cs.wout = at<float>(ws, dec->wout);
+  int64_t run = 0;
   for (int l = 0; l < L; ++l) {
     const Layer& ly = Ls[l];
-    if (l < L - 1)
-      DEC_HIP(jtfs::run_dec_cast(params + ly.w_off, ly.c_in, ly.cip, ly.c_out, at<uint16_t>(ws, ly.wf),
-                                 l > 0 ? at<uint16_t>(ws, ly.wd) : nullptr, nullptr, st));
-    else
-      DEC_HIP(jtfs::run_dec_cast(params + ly.w_off, ly.c_in, ly.c_in, 1, nullptr, nullptr, at<float>(ws, dec->wout), st));
+    cs.W[l] = params + ly.w_off;
+    cs.c_in[l] = ly.c_in;
+    cs.c_out[l] = ly.c_out;
+    if (l < L - 1) {
+      cs.cip[l] = ly.cip;
+      cs.wf[l] = at<uint16_t>(ws, ly.wf);
+      cs.wd[l] = l > 0 ? at<uint16_t>(ws, ly.wd) : nullptr;
+      run += int64_t(ly.c_out) * jtfs::kDecK * ly.cip + (l > 0 ? int64_t(ly.c_in) * jtfs::kDecK * ly.c_out : 0);
+    } else {
+      cs.cip[l] = ly.c_in;
+      run += int64_t(ly.c_out) * ly.c_in * jtfs::kDecK;
+    }
+    cs.end[l] = run;
   }
+  DEC_HIP(jtfs::run_dec_cast_all(cs, st));
   DEC_HIP(jtfs::run_dec_input(S, batch, c.c_in, c.n_frames, dec->cip0, c.eps, at<uint16_t>(ws, dec->x_tc),
                               at<uint16_t>(ws, dec->x_ct), st));
   for (int l = 0; l < L - 1; ++l) {

@@ -23,6 +23,15 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kRowB = kDecC + 8;   // LDS row pitch of a bf16 tile (272 bytes)
 constexpr int kRowF = kDecC + 4;   // LDS row pitch of an FP32 tile
 constexpr int fwd_pitch(int s) { return s == 4 ? kDecC : kRowB; }
+// input rows per workgroup of the LDS-staged forward (stride 2 or 4)
+constexpr int fwd_lds_rows(int s) { return s == 2 ? 96 : 64; }
+// its LDS bytes: the staged inputs and one tap's weights, or the output tile
+constexpr size_t fwd_lds_bytes(int s) {
+  return ((fwd_lds_rows(s) + 2 * (kDecH / s) + kDecC) * kRowB > s * fwd_lds_rows(s) * fwd_pitch(s)
+              ? size_t(fwd_lds_rows(s) + 2 * (kDecH / s) + kDecC) * kRowB
+              : size_t(s) * fwd_lds_rows(s) * fwd_pitch(s)) * sizeof(uint16_t);
+}
+static_assert(fwd_lds_bytes(2) <= 65536 && fwd_lds_bytes(4) <= 65536, "LDS-staged forward exceeds 64 KiB");
 
 __device__ inline f32x4 mma(uint4 a, uint4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
@@ -79,6 +88,38 @@ __global__ void k_cast_wd(const float* __restrict__ W, int c_in, int c_out, uint
   const int k = static_cast<int>((i / c_out) % kDecK);
   const int ci = static_cast<int>(i / (int64_t(c_out) * kDecK));
   wd[i] = f2bf(W[(int64_t(co) * c_in + ci) * kDecK + k]);
+}
+
+// Every layer's copies in one launch: element i belongs to the layer whose running end
+// passes it; inside the layer, first the forward copy, then the data-gradient copy (or the
+// output layer's rounded FP32 copy). Same element maps as the kernels above.
+__global__ void k_cast_all(DecCastSet set) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  int l = 0;
+  while (l < set.n && i >= set.end[l]) ++l;
+  if (l >= set.n) return;
+  int64_t e = i - (l > 0 ? set.end[l - 1] : 0);
+  const float* W = set.W[l];
+  const int c_in = set.c_in[l], cip = set.cip[l], c_out = set.c_out[l];
+  if (set.wf[l]) {
+    const int64_t n = int64_t(c_out) * kDecK * cip;
+    if (e < n) {
+      const int ci = static_cast<int>(e % cip);
+      const int k = static_cast<int>((e / cip) % kDecK);
+      const int co = static_cast<int>(e / (int64_t(cip) * kDecK));
+      set.wf[l][e] = ci < c_in ? f2bf(W[(int64_t(co) * c_in + ci) * kDecK + k]) : uint16_t(0);
+      return;
+    }
+    e -= n;
+  }
+  if (set.wd[l]) {
+    const int co = static_cast<int>(e % c_out);
+    const int k = static_cast<int>((e / c_out) % kDecK);
+    const int ci = static_cast<int>(e / (int64_t(c_out) * kDecK));
+    set.wd[l][e] = f2bf(W[(int64_t(co) * c_in + ci) * kDecK + k]);
+    return;
+  }
+  set.wout[e] = bf2f(f2bf(W[e]));
 }
 
 __global__ void k_cast_out(const float* __restrict__ W, int n, float* __restrict__ wo) {
@@ -188,6 +229,134 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
 #pragma unroll
     for (int e = 0; e < 4; ++e)
       o[e] = uint32_t(tile[(8 * ch + 2 * e) * P + co]) | (uint32_t(tile[(8 * ch + 2 * e + 1) * P + co]) << 16);
+    st16(out_ct + (int64_t(b) * kDecC + co) * ct_len + kDecPad + t, uint4{o[0], o[1], o[2], o[3]});
+  }
+  if (blockIdx.x == 0)
+    for (int co = threadIdx.x; co < kDecC; co += 256) st16(out_ct + (int64_t(b) * kDecC + co) * ct_len, uint4{0, 0, 0, 0});
+  if (blockIdx.x == gridDim.x - 1)
+    for (int co = threadIdx.x; co < kDecC; co += 256)
+      st16(out_ct + (int64_t(b) * kDecC + co) * ct_len + kDecPad + t_out, uint4{0, 0, 0, 0});
+}
+
+// ---------------------------------------------------------------------------------------
+// Hidden layer forward, LDS-staged (strides 2 and 4, 128 input channels). Workgroup: batch
+// item blockIdx.y, input rows m in [MR bx, MR bx + MR) (MR = 96 at stride 2, 64 at stride 4,
+// so that every staged tile fits in 64 KiB of LDS), all 128 output channels. The input rows (with the taps' halo of 4 / S rows on each side)
+// are staged in LDS once; the weights of one tap at a time ([128 co][128 ci], 32 KiB) are
+// staged in LDS and read by all four waves, so each weight is fetched from L2 once per
+// workgroup and tap instead of once per wave and row block. Wave w: rows (w & 1) MR / 2 ..
+// + MR / 2, channels 64 (w >> 1) .. + 64, all S phases (32 accumulator tiles).
+template <int S>
+__global__ __launch_bounds__(256, 2) void k_conv_fwd_lds(const uint16_t* __restrict__ x, int t_in,
+                                                         const uint16_t* __restrict__ wf, const float* __restrict__ bias,
+                                                         float leak, uint16_t* __restrict__ out_tc,
+                                                         uint16_t* __restrict__ out_ct) {
+  static_assert(S == 2 || S == 4, "LDS-staged forward: strides 2 and 4");
+  constexpr int MR = fwd_lds_rows(S);  // input rows per workgroup
+  constexpr int H = kDecH / S;         // halo rows: d = (r + k - 4) / S lies in [-H, H]
+  constexpr int NRI = MR + 2 * H;      // staged input rows
+  constexpr int RT = MR / 32;          // 16-row tiles per wave
+  constexpr int P = kRowB;             // LDS pitch (bf16) of the input and weight tiles
+  constexpr int PO = fwd_pitch(S);     // LDS pitch of the output tile
+  extern __shared__ uint16_t lds[];
+  uint16_t* xin = lds;                 // [NRI][P]
+  uint16_t* wk = lds + NRI * P;        // [128][P]
+  uint16_t* tile = lds;                // epilogue: [S MR][PO] (after the last product)
+  const int b = blockIdx.y, m0 = blockIdx.x * MR;
+  const int w = wave_index();
+  const int lane = threadIdx.x & 63, g = lane >> 4, li = lane & 15;
+  const int rw = (w & 1) * (MR / 2), cw = 64 * (w >> 1);
+  const int t_out = S * t_in;
+  const uint16_t* xb = x + int64_t(b) * t_in * kDecC;
+  const uint4 zero{0u, 0u, 0u, 0u};
+
+  for (int e = threadIdx.x; e < NRI * 16; e += 256) {
+    const int row = e >> 4, c8 = (e & 15) * 8;
+    const int u = m0 - H + row;
+    st16(xin + row * P + c8, (u >= 0 && u < t_in) ? ld16(xb + int64_t(u) * kDecC + c8) : zero);
+  }
+  f32x4 acc[S][RT][4];
+#pragma unroll
+  for (int r = 0; r < S; ++r)
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[r][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // a tap's weights: eight 16-byte pieces per thread, loaded one tap ahead (in flight during
+  // the previous tap's products)
+  uint4 wpre[8];
+  auto load_tap = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int co = e >> 4, c8 = (e & 15) * 8;
+      wpre[q] = ld16(wf + (int64_t(co) * kDecK + k) * kDecC + c8);
+    }
+  };
+  load_tap(0);
+#pragma unroll
+  for (int k = 0; k < kDecK; ++k) {
+    __syncthreads();   // the previous tap's weights are consumed (and, first, the input staged)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      st16(wk + (e >> 4) * P + (e & 15) * 8, wpre[q]);
+    }
+    if (k + 1 < kDecK) load_tap(k + 1);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      if ((r + k - kDecH + 4 * S) % S != 0) continue;
+      const int d = (r + k - kDecH) / S;   // exact division
+#pragma unroll
+      for (int c0 = 0; c0 < kDecC; c0 += 32) {
+        uint4 A[RT], Bv[4];
+#pragma unroll
+        for (int i = 0; i < RT; ++i) A[i] = ld16(xin + (rw + 16 * i + li + d + H) * P + c0 + 8 * g);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Bv[j] = ld16(wk + (cw + 16 * j + li) * P + c0 + 8 * g);
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[r][i][j] = mma(A[i], Bv[j], acc[r][i][j]);
+      }
+    }
+  }
+  __syncthreads();   // every wave is done with the staged inputs and weights
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int co = cw + 16 * j + li;
+    const float bo = bias[co];
+#pragma unroll
+    for (int r = 0; r < S; ++r)
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ml = rw + 16 * i + 4 * g + v;
+          const float z = acc[r][i][j][v] + bo;
+          tile[(ml * S + r) * PO + co] = f2bf(z > 0.f ? z : leak * z);
+        }
+  }
+  __syncthreads();
+  const int t0 = m0 * S;
+  // TC rows
+  for (int i = threadIdx.x; i < S * MR * 16; i += 256) {
+    const int row = i >> 4, c8 = (i & 15) * 8;
+    if (t0 + row < t_out) st16(out_tc + (int64_t(b) * t_out + t0 + row) * kDecC + c8, ld16(tile + row * PO + c8));
+  }
+  // CT rows: 8 consecutive samples of one channel per thread (neighbouring threads take
+  // neighbouring channels)
+  const int64_t ct_len = t_out + 2 * kDecPad;
+  for (int i = threadIdx.x; i < kDecC * (S * MR / 8); i += 256) {
+    const int co = i % kDecC, ch = i / kDecC;
+    const int t = t0 + 8 * ch;
+    if (t >= t_out) continue;
+    uint32_t o[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      o[e] = uint32_t(tile[(8 * ch + 2 * e) * PO + co]) | (uint32_t(tile[(8 * ch + 2 * e + 1) * PO + co]) << 16);
     st16(out_ct + (int64_t(b) * kDecC + co) * ct_len + kDecPad + t, uint4{o[0], o[1], o[2], o[3]});
   }
   if (blockIdx.x == 0)
@@ -639,6 +808,13 @@ inline int blocks_for(int64_t n, int per) { return static_cast<int>((n + per - 1
 template <int S>
 hipError_t launch_fwd(const uint16_t* x_tc, int cip, int t_in, int batch, const uint16_t* wf, const float* bias,
                       float leak, uint16_t* out_tc, uint16_t* out_ct, hipStream_t st) {
+  if constexpr (S == 2 || S == 4) {
+    if (cip == kDecC) {
+      hipLaunchKernelGGL(k_conv_fwd_lds<S>, dim3(blocks_for(t_in, fwd_lds_rows(S)), batch), dim3(256),
+                         fwd_lds_bytes(S), st, x_tc, t_in, wf, bias, leak, out_tc, out_ct);
+      return hipGetLastError();
+    }
+  }
   const size_t lds = size_t(kDecTile) * S * fwd_pitch(S) * sizeof(uint16_t);
   hipLaunchKernelGGL(k_conv_fwd<S>, dim3(blocks_for(t_in, kDecTile), batch), dim3(256), lds, st, x_tc, cip, t_in, wf,
                      bias, leak, out_tc, out_ct);
@@ -681,6 +857,12 @@ hipError_t run_dec_cast(const float* W, int c_in, int cip, int c_out, uint16_t* 
   if (e != hipSuccess || !wd) return e;
   hipLaunchKernelGGL(k_cast_wd, dim3(blocks_for(int64_t(c_in) * kDecK * c_out, 256)), dim3(256), 0, st, W, c_in, c_out,
                      wd);
+  return hipGetLastError();
+}
+
+hipError_t run_dec_cast_all(const DecCastSet& set, hipStream_t st) {
+  if (set.n < 1 || set.n > kDecMaxLayers) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cast_all, dim3(blocks_for(set.end[set.n - 1], 256)), dim3(256), 0, st, set);
   return hipGetLastError();
 }
 
