@@ -421,63 +421,92 @@ __device__ void mask_store_tc(const float* ftile, uint16_t* btile, int b, int u0
 
 // Hidden layer data gradient. Rows u of the layer input, channels ci:
 //   da[u, ci] = sum_k sum_co W[co, ci, k] dz[s u - k + 4, co]
-// Workgroup: batch item blockIdx.y, rows [64 bx, 64 bx + 64); wave w: 32 rows x 64 channels.
+// Workgroup: batch item blockIdx.y, rows [128 bx, 128 bx + 128),
+// wave w: 64 rows (w & 1) x 64 channels (w >> 1); one tap's weights ([128 ci][128 co])
+// at a time, loaded a tap ahead and shared by the four waves. The epilogue runs in two
+// 64-row halves through the shared helpers.
+constexpr int kDgradRows = 128;
+constexpr size_t kDgradLdsBig = size_t(kDecTile) * kRowF * sizeof(float) + size_t(kDecTile) * kRowB * sizeof(uint16_t);
+static_assert(size_t(kDecC) * kRowB * sizeof(uint16_t) <= kDgradLdsBig, "weight tile larger than the epilogue tiles");
+
 template <int S, int S2>
-__global__ __launch_bounds__(256) void k_conv_dgrad(const uint16_t* __restrict__ dz, int t_out,
-                                                    const uint16_t* __restrict__ wd, int t_in,
-                                                    const uint16_t* __restrict__ a_prev, float leak,
-                                                    uint16_t* __restrict__ dz_prev, uint16_t* __restrict__ dzp_prev) {
+__global__ __launch_bounds__(256, 2) void k_conv_dgrad_lds(const uint16_t* __restrict__ dz, int t_out,
+                                                           const uint16_t* __restrict__ wd, int t_in,
+                                                           const uint16_t* __restrict__ a_prev, float leak,
+                                                           uint16_t* __restrict__ dz_prev,
+                                                           uint16_t* __restrict__ dzp_prev) {
   extern __shared__ float smem[];
-  float* ftile = smem;                                                     // [64][kRowF]
-  uint16_t* btile = reinterpret_cast<uint16_t*>(smem + kDecTile * kRowF);  // [64][kRowB]
-  const int b = blockIdx.y, u0 = blockIdx.x * kDecTile;
+  uint16_t* wk = reinterpret_cast<uint16_t*>(smem);                        // [128][kRowB]
+  float* ftile = smem;                                                     // epilogue: [64][kRowF]
+  uint16_t* btile = reinterpret_cast<uint16_t*>(smem + kDecTile * kRowF);  // epilogue: [64][kRowB]
+  const int b = blockIdx.y, u0 = blockIdx.x * kDgradRows;
   const int w = wave_index();
   const int lane = threadIdx.x & 63, g = lane >> 4, li = lane & 15;
-  const int uw = u0 + 32 * (w & 1), cw = 64 * (w >> 1);
+  const int rw = 64 * (w & 1), cw = 64 * (w >> 1);
   const uint16_t* db = dz + int64_t(b) * t_out * kDecC;
   const uint4 zero{0u, 0u, 0u, 0u};
-  f32x4 acc[2][4];
+  f32x4 acc[4][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k = 0; k < kDecK; ++k) {
-    const uint16_t* arow[2];
-    bool aok[2];
+  uint4 wpre[8];
+  auto load_tap = [&](int k) {
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-      const int u = uw + 16 * mb + li;
-      const int t = S * u - k + kDecH;
-      aok[mb] = u < t_in && t >= 0 && t < t_out;
-      arow[mb] = db + int64_t(aok[mb] ? t : 0) * kDecC + 8 * g;
+    for (int q = 0; q < 8; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      wpre[q] = ld16(wd + (int64_t(e >> 4) * kDecK + k) * kDecC + (e & 15) * 8);
     }
-    const uint16_t* brow[4];
+  };
+  load_tap(0);
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) brow[cb] = wd + (int64_t(cw + 16 * cb + li) * kDecK + k) * kDecC + 8 * g;
+  for (int k = 0; k < kDecK; ++k) {
+    __syncthreads();   // the previous tap's weights are consumed
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      st16(wk + (e >> 4) * kRowB + (e & 15) * 8, wpre[q]);
+    }
+    if (k + 1 < kDecK) load_tap(k + 1);
+    __syncthreads();
+    const uint16_t* arow[4];
+    bool aok[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int u = u0 + rw + 16 * i + li;
+      const int t = S * u - k + kDecH;
+      aok[i] = u < t_in && t >= 0 && t < t_out;
+      arow[i] = db + int64_t(aok[i] ? t : 0) * kDecC + 8 * g;
+    }
 #pragma unroll
     for (int c0 = 0; c0 < kDecC; c0 += 32) {
-      uint4 A[2], Bv[4];
+      uint4 A[4], Bv[4];
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb) A[mb] = aok[mb] ? ld16(arow[mb] + c0) : zero;
+      for (int i = 0; i < 4; ++i) A[i] = aok[i] ? ld16(arow[i] + c0) : zero;
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) Bv[cb] = ld16(brow[cb] + c0);
+      for (int j = 0; j < 4; ++j) Bv[j] = ld16(wk + (cw + 16 * j + li) * kRowB + c0 + 8 * g);
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) acc[mb][cb] = mma(A[mb], Bv[cb], acc[mb][cb]);
+        for (int j = 0; j < 4; ++j) acc[i][j] = mma(A[i], Bv[j], acc[i][j]);
     }
   }
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();   // the weights (h = 0) or the previous half's tiles (h = 1) are consumed
+    if ((w & 1) == h) {
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        ftile[(32 * (w & 1) + 16 * mb + 4 * g + v) * kRowF + cw + 16 * cb + li] = acc[mb][cb][v];
-  __syncthreads();
-  mask_store_tc(ftile, btile, b, u0, t_in, a_prev, leak, dz_prev);
-  __syncthreads();
-  store_polyphase<S2>(btile, b, u0, t_in, dzp_prev);
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ftile[(16 * i + 4 * g + v) * kRowF + cw + 16 * j + li] = acc[i][j][v];
+    }
+    __syncthreads();
+    mask_store_tc(ftile, btile, b, u0 + kDecTile * h, t_in, a_prev, leak, dz_prev);
+    __syncthreads();
+    store_polyphase<S2>(btile, b, u0 + kDecTile * h, t_in, dzp_prev);
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -821,13 +850,13 @@ hipError_t launch_fwd(const uint16_t* x_tc, int cip, int t_in, int batch, const 
   return hipGetLastError();
 }
 
-constexpr size_t kDgradLds = size_t(kDecTile) * kRowF * sizeof(float) + size_t(kDecTile) * kRowB * sizeof(uint16_t);
+constexpr size_t kDgradLds = kDgradLdsBig;
 
 template <int S, int S2>
 hipError_t launch_dgrad(const uint16_t* dz, int t_out, const uint16_t* wd, int t_in, int batch, const uint16_t* a_prev,
                         float leak, uint16_t* dz_prev, uint16_t* dzp_prev, hipStream_t st) {
-  hipLaunchKernelGGL((k_conv_dgrad<S, S2>), dim3(blocks_for(t_in, kDecTile), batch), dim3(256), kDgradLds, st, dz,
-                     t_out, wd, t_in, a_prev, leak, dz_prev, dzp_prev);
+  hipLaunchKernelGGL((k_conv_dgrad_lds<S, S2>), dim3(blocks_for(t_in, kDgradRows), batch), dim3(256), kDgradLdsBig,
+                     st, dz, t_out, wd, t_in, a_prev, leak, dz_prev, dzp_prev);
   return hipGetLastError();
 }
 
