@@ -19,10 +19,19 @@ constexpr int kDecK = 9;          // taps per filter
 constexpr int kDecH = 4;          // (taps - 1) / 2
 constexpr int kDecPad = 8;        // zero samples at each end of a CT / P row
 constexpr int kDecTile = 64;      // time rows per workgroup tile
-constexpr int kDecChunk = 4096;   // time samples per weight-gradient partial
+constexpr int kDecChunk = 4096;   // longest run of time samples per weight-gradient partial
 constexpr int kDecOutChunk = 2048;
 
-inline int64_t dec_chunks(int batch, int t) { return int64_t(batch) * ((t + kDecChunk - 1) / kDecChunk); }
+// Time samples per weight-gradient partial of a hidden layer with t input samples: 4096,
+// halved (down to 512) while the launch, batch * ceil(t / chunk) * (cip / 64) workgroups
+// times s polyphase rows (9 taps at stride 1), would give the 256 CUs fewer than two each.
+inline int dec_wgrad_chunk(int batch, int t, int cip, int s) {
+  const int64_t z = int64_t(cip / 64) * (s == 1 ? kDecK : s);
+  int chunk = kDecChunk;
+  while (chunk > 512 && int64_t(batch) * ((t + chunk - 1) / chunk) * z < 512) chunk /= 2;
+  return chunk;
+}
+inline int64_t dec_chunks(int batch, int t, int chunk) { return int64_t(batch) * ((t + chunk - 1) / chunk); }
 inline int64_t dec_out_chunks(int batch, int t) { return int64_t(batch) * ((t + kDecOutChunk - 1) / kDecOutChunk); }
 
 // Weight copies of one layer from the FP32 master [c_out][c_in][9].

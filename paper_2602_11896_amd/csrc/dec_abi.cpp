@@ -74,9 +74,15 @@ jtfs_status build(jtfs_dec_s& d) {
       ly.out_ct = take(size_t(B) * jtfs::kDecC * (ly.t_out + 2 * jtfs::kDecPad) * 2);
       ly.dz_tc = take(size_t(B) * ly.t_out * jtfs::kDecC * 2);
       ly.dzp = take(size_t(B) * jtfs::kDecC * ly.stride * (ly.t_in + 2 * jtfs::kDecPad) * 2);
-      // weight partials, then B * 128 bias partials
-      part_bytes = std::max(part_bytes, (size_t(jtfs::dec_chunks(static_cast<int>(B), ly.t_in)) * jtfs::kDecK *
-                                             jtfs::kDecC * ly.cip + size_t(B) * jtfs::kDecC) * sizeof(float));
+      // weight partials, then the bias partials: 128 per chunk and polyphase row (strides 2 and 4)
+      // or per batch item (stride 1); the chunk length depends on the batch, so take the largest
+      // size over batches up to B
+      for (int64_t b = 1; b <= B; ++b) {
+        const int64_t n = jtfs::dec_chunks(static_cast<int>(b), ly.t_in,
+                                           jtfs::dec_wgrad_chunk(static_cast<int>(b), ly.t_in, ly.cip, ly.stride));
+        part_bytes = std::max(part_bytes, (size_t(n) * jtfs::kDecK * jtfs::kDecC * ly.cip +
+                                           size_t(std::max<int64_t>(n * ly.stride, b)) * jtfs::kDecC) * sizeof(float));
+      }
     } else {
       // weight partials, then one bias partial per 8192 samples of dy
       part_bytes = std::max(part_bytes, (size_t(jtfs::dec_out_chunks(static_cast<int>(B), ly.t_out)) * jtfs::kDecC *

@@ -573,13 +573,13 @@ __device__ void wgrad_tap(const uint16_t* __restrict__ dzp, const uint16_t* __re
 
 template <int S>
 __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__ dzp, const uint16_t* __restrict__ xct,
-                                                    int M, int cip, int chunks_per_b, float* __restrict__ part) {
-  const int chunk = blockIdx.x;
-  const int b = chunk / chunks_per_b, mc = chunk % chunks_per_b;
-  const int m_begin = mc * kDecChunk;
-  const int m_end = min(M, m_begin + kDecChunk);
+                                                    int M, int cip, int chunk, int chunks_per_b,
+                                                    float* __restrict__ part) {
+  const int b = blockIdx.x / chunks_per_b, mc = blockIdx.x % chunks_per_b;
+  const int m_begin = mc * chunk;
+  const int m_end = min(M, m_begin + chunk);
   const int ci0 = 64 * blockIdx.y;
-  float* p = part + int64_t(chunk) * kDecK * kDecC * cip;
+  float* p = part + int64_t(blockIdx.x) * kDecK * kDecC * cip;
   switch (blockIdx.z) {
     case 0: wgrad_tap<S, 0>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p); break;
     case 1: wgrad_tap<S, 1>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p); break;
@@ -590,6 +590,117 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__
     case 6: wgrad_tap<S, 6>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p); break;
     case 7: wgrad_tap<S, 7>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p); break;
     default: wgrad_tap<S, 8>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p); break;
+  }
+}
+
+// Weight gradient of every tap of one polyphase row R at once (strides 2 and 4): the taps
+// with 4 - KT = S q + R all read dz_P row R and the layer input at a shift of -q samples
+// (|q| <= 2), so one workgroup loads, per 32 samples, the dz rows once and three aligned
+// 16-byte pieces of each input row, and forms every tap's operand by realigning them in
+// registers. Workgroup: chunk (blockIdx.x), 64 input channels (blockIdx.y), row R
+// (blockIdx.z); wave w owns output channels [32 w, 32 w + 32) and all 64 input channels.
+// Partials as for one tap: part[chunk][KT][128][cip]. The workgroups of the first channel
+// block also sum their dz rows for the bias gradient: bpart[chunk][R][128].
+template <int S, int R>
+__device__ void wgrad_row(const uint16_t* __restrict__ dzp, const uint16_t* __restrict__ xct, int M, int cip, int b,
+                          int m_begin, int m_end, int ci0, float* __restrict__ part, float* __restrict__ bpart) {
+  const int w = wave_index();
+  const int lane = threadIdx.x & 63, g = lane >> 4, li = lane & 15;
+  const int64_t row_len = M + 2 * kDecPad;
+  const uint4 zero{0u, 0u, 0u, 0u};
+  const uint16_t* arow[2];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+    arow[mb] = dzp + ((int64_t(b) * kDecC + 32 * w + 16 * mb + li) * S + R) * row_len + kDecPad;
+  const uint16_t* xrow[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) xrow[nb] = xct + (int64_t(b) * cip + ci0 + 16 * nb + li) * row_len + kDecPad;
+  f32x4 acc[kDecK][2][4];
+#pragma unroll
+  for (int kt = 0; kt < kDecK; ++kt)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[kt][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bool with_bias = bpart != nullptr;
+  float bsum[2] = {0.f, 0.f};
+  for (int m = m_begin; m < m_end; m += 32) {
+    const int mm = m + 8 * g;
+    const bool ok = mm < m_end;   // (then mm <= M - 8: the pieces at mm - 8 and mm + 8 lie in the padded row)
+    uint4 A[2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) A[mb] = ok ? ld16(arow[mb] + mm) : zero;
+    if (with_bias) {
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const uint32_t u[4] = {A[mb].x, A[mb].y, A[mb].z, A[mb].w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bsum[mb] += __uint_as_float(u[i] << 16) + __uint_as_float(u[i] & 0xffff0000u);
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      const uint4 cm = ok ? ld16(xrow[nb] + mm - 8) : zero;
+      const uint4 c0 = ok ? ld16(xrow[nb] + mm) : zero;
+      const uint4 c8 = ok ? ld16(xrow[nb] + mm + 8) : zero;
+#pragma unroll
+      for (int kt = 0; kt < kDecK; ++kt) {
+        if constexpr (true) {
+          if (((kDecH - kt) % S + S) % S != R) continue;
+          const int sh = -((kDecH - kt - R) / S);   // the input is read at m + sh
+          uint4 Bv;
+          switch (sh) {   // (a compile-time constant once unrolled)
+            case -2: Bv = realign<6>(cm, c0); break;
+            case -1: Bv = realign<7>(cm, c0); break;
+            case 0: Bv = c0; break;
+            case 1: Bv = realign<1>(c0, c8); break;
+            default: Bv = realign<2>(c0, c8); break;
+          }
+#pragma unroll
+          for (int mb = 0; mb < 2; ++mb) acc[kt][mb][nb] = mma(A[mb], Bv, acc[kt][mb][nb]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int kt = 0; kt < kDecK; ++kt) {
+    if (((kDecH - kt) % S + S) % S != R) continue;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          part[(int64_t(kt) * kDecC + 32 * w + 16 * mb + 4 * g + v) * cip + ci0 + 16 * nb + li] = acc[kt][mb][nb][v];
+  }
+  if (with_bias) {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      float t = bsum[mb];
+      t += __shfl_xor(t, 16);   // the four lane groups hold disjoint times of one channel
+      t += __shfl_xor(t, 32);
+      if (g == 0) bpart[(int64_t(blockIdx.x) * S + R) * kDecC + 32 * w + 16 * mb + li] = t;
+    }
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(256, 2) void k_conv_wgrad_rows(const uint16_t* __restrict__ dzp,
+                                                            const uint16_t* __restrict__ xct, int M, int cip,
+                                                            int chunk, int chunks_per_b, float* __restrict__ part,
+                                                            float* __restrict__ bpart) {
+  static_assert(S == 2 || S == 4, "shifts of at most two samples");
+  const int b = blockIdx.x / chunks_per_b, mc = blockIdx.x % chunks_per_b;
+  const int m_begin = mc * chunk;
+  const int m_end = min(M, m_begin + chunk);
+  const int ci0 = 64 * blockIdx.y;
+  float* p = part + int64_t(blockIdx.x) * kDecK * kDecC * cip;
+  float* bp = blockIdx.y == 0 ? bpart : nullptr;
+  switch (blockIdx.z) {
+    case 0: wgrad_row<S, 0>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p, bp); break;
+    case 1: wgrad_row<S, 1>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p, bp); break;
+    case 2: if constexpr (S > 2) wgrad_row<S, 2>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p, bp); break;
+    default: if constexpr (S > 2) wgrad_row<S, 3>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p, bp); break;
   }
 }
 
@@ -960,13 +1071,25 @@ hipError_t run_dec_dgrad(int s, int s2, const uint16_t* dz_tc, int t_out, const 
 
 hipError_t run_dec_wgrad(int s, const uint16_t* dzp, const uint16_t* x_ct, int t_in, int cip, int c_in, int batch,
                          float* part, float* grad_w, float* grad_b, hipStream_t st) {
-  const int cpb = blocks_for(t_in, kDecChunk);
+  const int chunk = dec_wgrad_chunk(batch, t_in, cip, s);
+  const int cpb = blocks_for(t_in, chunk);
   const int n_chunks = cpb * batch;
-  const dim3 grid(n_chunks, cip / 64, kDecK);
+  // bias partials follow the weight partials in `part`: [chunk][row][128] from the stride-2/4
+  // kernels, [batch item][128] row sums at stride 1
+  float* bpart = part + int64_t(n_chunks) * kDecK * kDecC * cip;
   switch (s) {
-    case 1: hipLaunchKernelGGL(k_conv_wgrad<1>, grid, dim3(256), 0, st, dzp, x_ct, t_in, cip, cpb, part); break;
-    case 2: hipLaunchKernelGGL(k_conv_wgrad<2>, grid, dim3(256), 0, st, dzp, x_ct, t_in, cip, cpb, part); break;
-    case 4: hipLaunchKernelGGL(k_conv_wgrad<4>, grid, dim3(256), 0, st, dzp, x_ct, t_in, cip, cpb, part); break;
+    case 1:
+      hipLaunchKernelGGL(k_conv_wgrad<1>, dim3(n_chunks, cip / 64, kDecK), dim3(256), 0, st, dzp, x_ct, t_in, cip,
+                         chunk, cpb, part);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_conv_wgrad_rows<2>, dim3(n_chunks, cip / 64, 2), dim3(256), 0, st, dzp, x_ct, t_in, cip,
+                         chunk, cpb, part, bpart);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_conv_wgrad_rows<4>, dim3(n_chunks, cip / 64, 4), dim3(256), 0, st, dzp, x_ct, t_in, cip,
+                         chunk, cpb, part, bpart);
+      break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
@@ -974,12 +1097,13 @@ hipError_t run_dec_wgrad(int s, const uint16_t* dzp, const uint16_t* x_ct, int t
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(int64_t(kDecK) * kDecC * cip, 256)), dim3(256), 0, st, part,
                      n_chunks, cip, c_in, grad_w);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // bias: per-(batch item, channel) sums after the weight partials in `part`, then over the batch
-  float* bpart = part + int64_t(n_chunks) * kDecK * kDecC * cip;
-  hipLaunchKernelGGL(k_rowsum_bf16, dim3(batch * kDecC), dim3(256), 0, st, dzp, int64_t(s) * (t_in + 2 * kDecPad),
-                     bpart);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kDecC), 0, st, bpart, batch, kDecC, grad_b);
+  int brows = n_chunks * s;
+  if (s == 1) {
+    hipLaunchKernelGGL(k_rowsum_bf16, dim3(batch * kDecC), dim3(256), 0, st, dzp, int64_t(t_in + 2 * kDecPad), bpart);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    brows = batch;
+  }
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kDecC), 0, st, bpart, brows, kDecC, grad_b);
   return hipGetLastError();
 }
 

@@ -85,6 +85,7 @@ def check_layers(ocfg, g_dev, g_ref, tol):
     ([2, 1], 1, 8, 1),
     ([4, 4, 1], 70, 8, 2),
     ([1, 1, 1], 130, 24, 2),
+    ([2, 4, 1], 4, 600, 2),   # weight-gradient partials of 512 samples with ragged last chunks
 ])
 def test_decoder_forward_backward_small(strides, c_in, F, batch):
     say(f"decoder fwd/bwd strides={strides} c_in={c_in} F={F} batch={batch}")
