@@ -595,69 +595,86 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t* __restrict__
 
 // Weight gradient of every tap of one polyphase row R at once (strides 2 and 4): the taps
 // with 4 - KT = S q + R all read dz_P row R and the layer input at a shift of -q samples
-// (|q| <= 2), so one workgroup loads, per 32 samples, the dz rows once and three aligned
-// 16-byte pieces of each input row, and forms every tap's operand by realigning them in
-// registers. Workgroup: chunk (blockIdx.x), 64 input channels (blockIdx.y), row R
-// (blockIdx.z); wave w owns output channels [32 w, 32 w + 32) and all 64 input channels.
-// Partials as for one tap: part[chunk][KT][128][cip]. The workgroups of the first channel
-// block also sum their dz rows for the bias gradient: bpart[chunk][R][128].
+// (|q| <= 2). Workgroup: chunk (blockIdx.x), 64 input channels (blockIdx.y), row R
+// (blockIdx.z). The dz rows of all 128 output channels, shared by the four waves, go
+// through LDS 64 samples at a time (the next 64 are loaded into registers while the
+// current ones are used); wave w owns input channels ci0 + [16 w, 16 w + 16) and reads
+// three aligned 16-byte pieces of each input row per 32 samples, from which every tap's
+// operand is formed by realigning in registers. Partials as for one tap:
+// part[chunk][KT][128][cip]. The workgroups of the first channel block also sum the dz
+// rows for the bias gradient: bpart[chunk][R][128].
+constexpr int kWgTile = 64;                 // samples per LDS stage
+constexpr int kWgPitch = kWgTile + 8;       // 144 bytes: rows 16 bytes apart modulo the 128-byte bank cycle
+constexpr int kWgPieces = kDecC * kWgTile / 8 / 256;   // 16-byte pieces per thread per stage
+
 template <int S, int R>
 __device__ void wgrad_row(const uint16_t* __restrict__ dzp, const uint16_t* __restrict__ xct, int M, int cip, int b,
-                          int m_begin, int m_end, int ci0, float* __restrict__ part, float* __restrict__ bpart) {
+                          int m_begin, int m_end, int ci0, float* __restrict__ part, float* __restrict__ bpart,
+                          uint16_t* __restrict__ atile) {
   const int w = wave_index();
   const int lane = threadIdx.x & 63, g = lane >> 4, li = lane & 15;
   const int64_t row_len = M + 2 * kDecPad;
   const uint4 zero{0u, 0u, 0u, 0u};
-  const uint16_t* arow[2];
-#pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
-    arow[mb] = dzp + ((int64_t(b) * kDecC + 32 * w + 16 * mb + li) * S + R) * row_len + kDecPad;
-  const uint16_t* xrow[4];
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) xrow[nb] = xct + (int64_t(b) * cip + ci0 + 16 * nb + li) * row_len + kDecPad;
-  f32x4 acc[kDecK][2][4];
+  // staging: thread t moves piece (t & 7) of rows (t >> 3) + 32 j
+  const int sp = threadIdx.x & 7, sr = threadIdx.x >> 3;
+  const uint16_t* srow = dzp + ((int64_t(b) * kDecC + sr) * S + R) * row_len + kDecPad + 8 * sp;
+  const int64_t srow_step = int64_t(32) * S * row_len;
+  const uint16_t* xrow = xct + (int64_t(b) * cip + ci0 + 16 * w + li) * row_len + kDecPad;
+  f32x4 acc[kDecK][8];
 #pragma unroll
   for (int kt = 0; kt < kDecK; ++kt)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[kt][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < 8; ++i) acc[kt][i] = f32x4{0.f, 0.f, 0.f, 0.f};
   const bool with_bias = bpart != nullptr;
-  float bsum[2] = {0.f, 0.f};
-  for (int m = m_begin; m < m_end; m += 32) {
-    const int mm = m + 8 * g;
-    const bool ok = mm < m_end;   // (then mm <= M - 8: the pieces at mm - 8 and mm + 8 lie in the padded row)
-    uint4 A[2];
+  float bsum[kWgPieces];
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb) A[mb] = ok ? ld16(arow[mb] + mm) : zero;
-    if (with_bias) {
+  for (int j = 0; j < kWgPieces; ++j) bsum[j] = 0.f;
+  uint4 P[kWgPieces];
+  auto fetch = [&](int m0) {
+    const bool in = m0 + 8 * sp < m_end;   // pieces past the chunk's end read as zero
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb) {
-        const uint32_t u[4] = {A[mb].x, A[mb].y, A[mb].z, A[mb].w};
+    for (int j = 0; j < kWgPieces; ++j) P[j] = in ? ld16(srow + j * srow_step + m0) : zero;
+  };
+  fetch(m_begin);
+  for (int m0 = m_begin; m0 < m_end; m0 += kWgTile) {
+    __syncthreads();   // every wave is done with the previous stage
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bsum[mb] += __uint_as_float(u[i] << 16) + __uint_as_float(u[i] & 0xffff0000u);
+    for (int j = 0; j < kWgPieces; ++j) {
+      st16(atile + (sr + 32 * j) * kWgPitch + 8 * sp, P[j]);
+      if (with_bias) {
+        const uint32_t u[4] = {P[j].x, P[j].y, P[j].z, P[j].w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bsum[j] += __uint_as_float(u[i] << 16) + __uint_as_float(u[i] & 0xffff0000u);
       }
     }
+    __syncthreads();
+    if (m0 + kWgTile < m_end) fetch(m0 + kWgTile);
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-      const uint4 cm = ok ? ld16(xrow[nb] + mm - 8) : zero;
-      const uint4 c0 = ok ? ld16(xrow[nb] + mm) : zero;
-      const uint4 c8 = ok ? ld16(xrow[nb] + mm + 8) : zero;
+    for (int step = 0; step < kWgTile / 32; ++step) {
+      const int mm = m0 + 32 * step + 8 * g;
+      const bool ok = mm < m_end;   // (then mm <= M - 8: the pieces at mm - 8 and mm + 8 lie in the padded row)
+      const uint4 cm = ok ? ld16(xrow + mm - 8) : zero;
+      const uint4 c0 = ok ? ld16(xrow + mm) : zero;
+      const uint4 c8 = ok ? ld16(xrow + mm + 8) : zero;
+      uint4 Bt[kDecK];
 #pragma unroll
       for (int kt = 0; kt < kDecK; ++kt) {
-        if constexpr (true) {
-          if (((kDecH - kt) % S + S) % S != R) continue;
-          const int sh = -((kDecH - kt - R) / S);   // the input is read at m + sh
-          uint4 Bv;
-          switch (sh) {   // (a compile-time constant once unrolled)
-            case -2: Bv = realign<6>(cm, c0); break;
-            case -1: Bv = realign<7>(cm, c0); break;
-            case 0: Bv = c0; break;
-            case 1: Bv = realign<1>(c0, c8); break;
-            default: Bv = realign<2>(c0, c8); break;
-          }
+        if (((kDecH - kt) % S + S) % S != R) continue;
+        switch (-((kDecH - kt - R) / S)) {   // the input is read at m + shift (a compile-time constant)
+          case -2: Bt[kt] = realign<6>(cm, c0); break;
+          case -1: Bt[kt] = realign<7>(cm, c0); break;
+          case 0: Bt[kt] = c0; break;
+          case 1: Bt[kt] = realign<1>(c0, c8); break;
+          default: Bt[kt] = realign<2>(c0, c8); break;
+        }
+      }
 #pragma unroll
-          for (int mb = 0; mb < 2; ++mb) acc[kt][mb][nb] = mma(A[mb], Bv, acc[kt][mb][nb]);
+      for (int mb = 0; mb < 8; ++mb) {
+        const uint4 A = ld16(atile + (16 * mb + li) * kWgPitch + 32 * step + 8 * g);
+#pragma unroll
+        for (int kt = 0; kt < kDecK; ++kt) {
+          if (((kDecH - kt) % S + S) % S != R) continue;
+          acc[kt][mb] = mma(A, Bt[kt], acc[kt][mb]);
         }
       }
     }
@@ -666,20 +683,19 @@ __device__ void wgrad_row(const uint16_t* __restrict__ dzp, const uint16_t* __re
   for (int kt = 0; kt < kDecK; ++kt) {
     if (((kDecH - kt) % S + S) % S != R) continue;
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < 8; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          part[(int64_t(kt) * kDecC + 32 * w + 16 * mb + 4 * g + v) * cip + ci0 + 16 * nb + li] = acc[kt][mb][nb][v];
+      for (int v = 0; v < 4; ++v)
+        part[(int64_t(kt) * kDecC + 16 * mb + 4 * g + v) * cip + ci0 + 16 * w + li] = acc[kt][mb][v];
   }
   if (with_bias) {
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-      float t = bsum[mb];
-      t += __shfl_xor(t, 16);   // the four lane groups hold disjoint times of one channel
-      t += __shfl_xor(t, 32);
-      if (g == 0) bpart[(int64_t(blockIdx.x) * S + R) * kDecC + 32 * w + 16 * mb + li] = t;
+    for (int j = 0; j < kWgPieces; ++j) {
+      float t = bsum[j];
+      t += __shfl_xor(t, 1);   // the eight threads of a row hold its eight pieces
+      t += __shfl_xor(t, 2);
+      t += __shfl_xor(t, 4);
+      if (sp == 0) bpart[(int64_t(blockIdx.x) * S + R) * kDecC + sr + 32 * j] = t;
     }
   }
 }
@@ -690,17 +706,19 @@ __global__ __launch_bounds__(256, 2) void k_conv_wgrad_rows(const uint16_t* __re
                                                             int chunk, int chunks_per_b, float* __restrict__ part,
                                                             float* __restrict__ bpart) {
   static_assert(S == 2 || S == 4, "shifts of at most two samples");
+  static_assert(kWgPieces * 256 * 8 == kDecC * kWgTile, "staging covers the tile");
   const int b = blockIdx.x / chunks_per_b, mc = blockIdx.x % chunks_per_b;
   const int m_begin = mc * chunk;
   const int m_end = min(M, m_begin + chunk);
   const int ci0 = 64 * blockIdx.y;
   float* p = part + int64_t(blockIdx.x) * kDecK * kDecC * cip;
   float* bp = blockIdx.y == 0 ? bpart : nullptr;
+  __shared__ uint16_t atile[kDecC * kWgPitch];
   switch (blockIdx.z) {
-    case 0: wgrad_row<S, 0>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p, bp); break;
-    case 1: wgrad_row<S, 1>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p, bp); break;
-    case 2: if constexpr (S > 2) wgrad_row<S, 2>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p, bp); break;
-    default: if constexpr (S > 2) wgrad_row<S, 3>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p, bp); break;
+    case 0: wgrad_row<S, 0>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p, bp, atile); break;
+    case 1: wgrad_row<S, 1>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p, bp, atile); break;
+    case 2: if constexpr (S > 2) wgrad_row<S, 2>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p, bp, atile); break;
+    default: if constexpr (S > 2) wgrad_row<S, 3>(dzp, xct, M, cip, b, m_begin, m_end, ci0, p, bp, atile); break;
   }
 }
 
@@ -737,13 +755,23 @@ __global__ __launch_bounds__(256) void k_rowsum_bf16(const uint16_t* __restrict_
   if (threadIdx.x == 0) out[blockIdx.x] = static_cast<float>(red[0]);
 }
 
-// out[c] = sum_{r < rows} x[r * cols + c], fixed order.
-__global__ void k_colsum(const float* __restrict__ x, int rows, int cols, float* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// out[c] = sum_{r < rows} x[r * cols + c] in a fixed order: block (64, 16) owns 64 columns;
+// thread (c, j) sums rows j, j + 16, ..., and the 16 slices are added in order.
+__global__ __launch_bounds__(1024) void k_colsum(const float* __restrict__ x, int rows, int cols,
+                                                 float* __restrict__ out) {
+  __shared__ float red[16][64];
+  const int c = blockIdx.x * 64 + threadIdx.x;
   float acc = 0.f;
-  for (int r = 0; r < rows; ++r) acc += x[int64_t(r) * cols + c];
-  out[c] = acc;
+  if (c < cols)
+    for (int r = threadIdx.y; r < rows; r += 16) acc += x[int64_t(r) * cols + c];
+  red[threadIdx.y][threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.y == 0 && c < cols) {
+    float t = 0.f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) t += red[j][threadIdx.x];
+    out[c] = t;
+  }
 }
 
 // Sum of each contiguous FP32 row of row_len values (the last row may be shorter).
@@ -765,11 +793,12 @@ __global__ __launch_bounds__(256) void k_rowsum_f32(const float* __restrict__ x,
 // ---------------------------------------------------------------------------------------
 // Output layer (one channel, stride 1), FP32 arithmetic on bf16 activations.
 
-// 24 samples x[t0 - 8 .. t0 + 16) of a CT row (padded index t0 .. t0 + 24).
-__device__ inline void load24(const uint16_t* row, int t0, float v[24]) {
+// 32 samples x[t0 - 8 .. t0 + 24) of a CT row (padded index t0 .. t0 + 32); the last piece is
+// read only when `more` (t0 + 8 < T: the 16 outputs reach past the first 8).
+__device__ inline void load32(const uint16_t* row, int t0, bool more, float v[32]) {
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const uint4 u = ld16(row + t0 + 8 * q);
+  for (int q = 0; q < 4; ++q) {
+    const uint4 u = (q < 3 || more) ? ld16(row + t0 + 8 * q) : uint4{0u, 0u, 0u, 0u};
     const uint32_t wv[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -779,38 +808,44 @@ __device__ inline void load24(const uint16_t* row, int t0, float v[24]) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_out_fwd(const uint16_t* __restrict__ xct, int T, const float* __restrict__ wo,
+__global__ __launch_bounds__(512) void k_out_fwd(const uint16_t* __restrict__ xct, int T, const float* __restrict__ wo,
                                                  const float* __restrict__ bias, float* __restrict__ y) {
-  // 64 threads x 8 samples per block; the four waves take 32 channels each and their sums
+  // 64 threads x 16 samples per block; the eight waves take 16 channels each and their sums
   // are combined through LDS in a fixed order
-  __shared__ float red[4][64 * 8];
+  __shared__ float red[8][64 * 16];
   const int b = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int t0 = 8 * (blockIdx.x * 64 + lane);
+  const int t0 = 16 * (blockIdx.x * 64 + lane);
+  const bool more = t0 + 8 < T;   // (T is a multiple of 8)
   const int64_t row_len = T + 2 * kDecPad;
-  float acc[8];
+  float acc[16];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) acc[i] = 0.f;
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
   if (t0 < T) {
-    for (int ci = wave * (kDecC / 4); ci < (wave + 1) * (kDecC / 4); ++ci) {
-      float v[24];
-      load24(xct + (int64_t(b) * kDecC + ci) * row_len, t0, v);
+#pragma unroll 2
+    for (int ci = wave * (kDecC / 8); ci < (wave + 1) * (kDecC / 8); ++ci) {
+      float v[32];
+      load32(xct + (int64_t(b) * kDecC + ci) * row_len, t0, more, v);
 #pragma unroll
       for (int k = 0; k < kDecK; ++k) {
         const float wk = wo[ci * kDecK + k];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] += wk * v[i + k + 4];
+        for (int i = 0; i < 16; ++i) acc[i] += wk * v[i + k + 4];
       }
     }
   }
 #pragma unroll
-  for (int i = 0; i < 8; ++i) red[wave][lane * 8 + i] = acc[i];
+  for (int i = 0; i < 16; ++i) red[wave][lane * 16 + i] = acc[i];
   __syncthreads();
   if (wave == 0 && t0 < T) {
     float* yo = y + int64_t(b) * T + t0;
+    const int n = more ? 16 : 8;
+    for (int i = 0; i < n; ++i) {
+      float t = 0.f;
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-      yo[i] = bias[0] + ((red[0][lane * 8 + i] + red[1][lane * 8 + i]) + (red[2][lane * 8 + i] + red[3][lane * 8 + i]));
+      for (int w = 0; w < 8; ++w) t += red[w][lane * 16 + i];
+      yo[i] = bias[0] + t;
+    }
   }
 }
 
@@ -859,16 +894,21 @@ __global__ __launch_bounds__(256) void k_out_wgrad(const float* __restrict__ dy,
   float acc[kDecK];
 #pragma unroll
   for (int k = 0; k < kDecK; ++k) acc[k] = 0.f;
-  for (int t0 = t_begin + 8 * sub; t0 < t_end; t0 += 128) {
-    float v[24];
-    load24(row, t0, v);
-    const float4 d0 = *reinterpret_cast<const float4*>(dy + int64_t(b) * T + t0);
-    const float4 d1 = *reinterpret_cast<const float4*>(dy + int64_t(b) * T + t0 + 4);
-    const float d[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+  for (int t0 = t_begin + 16 * sub; t0 < t_end; t0 += 256) {
+    const bool more = t0 + 8 < t_end;   // (chunk ends are multiples of 8)
+    float v[32];
+    load32(row, t0, more, v);
+    const float* dyp = dy + int64_t(b) * T + t0;
+    const float4 d0 = *reinterpret_cast<const float4*>(dyp);
+    const float4 d1 = *reinterpret_cast<const float4*>(dyp + 4);
+    const float4 d2 = more ? *reinterpret_cast<const float4*>(dyp + 8) : float4{0.f, 0.f, 0.f, 0.f};
+    const float4 d3 = more ? *reinterpret_cast<const float4*>(dyp + 12) : float4{0.f, 0.f, 0.f, 0.f};
+    const float d[16] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w,
+                         d2.x, d2.y, d2.z, d2.w, d3.x, d3.y, d3.z, d3.w};
 #pragma unroll
     for (int k = 0; k < kDecK; ++k)
 #pragma unroll
-      for (int i = 0; i < 8; ++i) acc[k] += d[i] * v[i + k + 4];
+      for (int i = 0; i < 16; ++i) acc[k] += d[i] * v[i + k + 4];
   }
 #pragma unroll
   for (int k = 0; k < kDecK; ++k) {
@@ -1025,7 +1065,7 @@ hipError_t run_dec_conv_fwd(int s, const uint16_t* x_tc, int cip, int t_in, int 
 
 hipError_t run_dec_out_fwd(const uint16_t* x_ct, int T, int batch, const float* wout, const float* bias, float* y,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_out_fwd, dim3(blocks_for(T / 8, 64), batch), dim3(256), 0, st, x_ct, T, wout, bias, y);
+  hipLaunchKernelGGL(k_out_fwd, dim3(blocks_for(T, 1024), batch), dim3(512), 0, st, x_ct, T, wout, bias, y);
   return hipGetLastError();
 }
 
@@ -1054,7 +1094,7 @@ hipError_t run_dec_out_bwd(const float* dy, int T, int batch, const float* wout,
   float* bpart = part + int64_t(n_chunks) * kDecC * kDecK;
   hipLaunchKernelGGL(k_rowsum_f32, dim3(nrow), dim3(256), 0, st, dy, n, int64_t(8192), bpart);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, st, bpart, nrow, 1, grad_b);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64, 16), 0, st, bpart, nrow, 1, grad_b);
   return hipGetLastError();
 }
 
@@ -1103,7 +1143,7 @@ hipError_t run_dec_wgrad(int s, const uint16_t* dzp, const uint16_t* x_ct, int t
     if ((e = hipGetLastError()) != hipSuccess) return e;
     brows = batch;
   }
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kDecC), 0, st, bpart, brows, kDecC, grad_b);
+  hipLaunchKernelGGL(k_colsum, dim3(kDecC / 64), dim3(64, 16), 0, st, bpart, brows, kDecC, grad_b);
   return hipGetLastError();
 }
 
