@@ -482,7 +482,10 @@ __global__ __launch_bounds__(256, 2) void k_conv_dgrad_lds(const uint16_t* __res
     for (int c0 = 0; c0 < kDecC; c0 += 32) {
       uint4 A[4], Bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) A[i] = aok[i] ? ld16(arow[i] + c0) : zero;
+      for (int i = 0; i < 4; ++i) {
+        const uint4 v = ld16(arow[i] + c0);   // (unconditional: arow is clamped to a valid row)
+        A[i] = aok[i] ? v : zero;
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) Bv[j] = ld16(wk + (cw + 16 * j + li) * kRowB + c0 + 8 * g);
 #pragma unroll
@@ -629,13 +632,28 @@ __device__ void wgrad_row(const uint16_t* __restrict__ dzp, const uint16_t* __re
   float bsum[kWgPieces];
 #pragma unroll
   for (int j = 0; j < kWgPieces; ++j) bsum[j] = 0.f;
+  // Loads are unconditional (addresses clamped into the chunk) so that they issue ahead of
+  // their use; staged pieces past the chunk's end are then replaced by zeros, which also
+  // cancels the clamped input pieces that meet them.
   uint4 P[kWgPieces];
   auto fetch = [&](int m0) {
-    const bool in = m0 + 8 * sp < m_end;   // pieces past the chunk's end read as zero
+    const bool in = m0 + 8 * sp < m_end;
+    const int off = in ? m0 + 8 * sp : m_begin;
 #pragma unroll
-    for (int j = 0; j < kWgPieces; ++j) P[j] = in ? ld16(srow + j * srow_step + m0) : zero;
+    for (int j = 0; j < kWgPieces; ++j) {
+      const uint4 v = ld16(srow + j * srow_step + off - 8 * sp);
+      P[j] = in ? v : zero;
+    }
+  };
+  uint4 nm, n0, n8;   // input pieces of the next 32 samples
+  auto fetch_x = [&](int m) {
+    const int mm = min(m + 8 * g, m_end - 8);   // (mm <= M - 8: the pieces at mm - 8 and mm + 8 lie in the padded row)
+    nm = ld16(xrow + mm - 8);
+    n0 = ld16(xrow + mm);
+    n8 = ld16(xrow + mm + 8);
   };
   fetch(m_begin);
+  fetch_x(m_begin);
   for (int m0 = m_begin; m0 < m_end; m0 += kWgTile) {
     __syncthreads();   // every wave is done with the previous stage
 #pragma unroll
@@ -651,11 +669,8 @@ __device__ void wgrad_row(const uint16_t* __restrict__ dzp, const uint16_t* __re
     if (m0 + kWgTile < m_end) fetch(m0 + kWgTile);
 #pragma unroll
     for (int step = 0; step < kWgTile / 32; ++step) {
-      const int mm = m0 + 32 * step + 8 * g;
-      const bool ok = mm < m_end;   // (then mm <= M - 8: the pieces at mm - 8 and mm + 8 lie in the padded row)
-      const uint4 cm = ok ? ld16(xrow + mm - 8) : zero;
-      const uint4 c0 = ok ? ld16(xrow + mm) : zero;
-      const uint4 c8 = ok ? ld16(xrow + mm + 8) : zero;
+      const uint4 cm = nm, c0 = n0, c8 = n8;
+      if (m0 + 32 * step + 32 < m_end) fetch_x(m0 + 32 * step + 32);
       uint4 Bt[kDecK];
 #pragma unroll
       for (int kt = 0; kt < kDecK; ++kt) {
@@ -835,7 +850,7 @@ __global__ __launch_bounds__(512) void k_out_fwd(const uint16_t* __restrict__ xc
     }
   }
 #pragma unroll
-  for (int i = 0; i < 16; ++i) red[wave][lane * 16 + i] = acc[i];
+  for (int i = 0; i < 16; ++i) red[wave][i * 64 + lane] = acc[i];
   __syncthreads();
   if (wave == 0 && t0 < T) {
     float* yo = y + int64_t(b) * T + t0;
@@ -843,7 +858,7 @@ __global__ __launch_bounds__(512) void k_out_fwd(const uint16_t* __restrict__ xc
     for (int i = 0; i < n; ++i) {
       float t = 0.f;
 #pragma unroll
-      for (int w = 0; w < 8; ++w) t += red[w][lane * 16 + i];
+      for (int w = 0; w < 8; ++w) t += red[w][i * 64 + lane];
       yo[i] = bias[0] + t;
     }
   }
