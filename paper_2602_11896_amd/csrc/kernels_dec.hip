@@ -421,13 +421,35 @@ __device__ void mask_store_tc(const float* ftile, uint16_t* btile, int b, int u0
 
 // Hidden layer data gradient. Rows u of the layer input, channels ci:
 //   da[u, ci] = sum_k sum_co W[co, ci, k] dz[s u - k + 4, co]
-// Workgroup: batch item blockIdx.y, rows [128 bx, 128 bx + 128),
-// wave w: 64 rows (w & 1) x 64 channels (w >> 1); one tap's weights ([128 ci][128 co])
-// at a time, loaded a tap ahead and shared by the four waves. The epilogue runs in two
-// 64-row halves through the shared helpers.
+// Workgroup: batch item blockIdx.y, rows [128 bx, 128 bx + 128), wave w: 64 rows (w & 1) x
+// 64 channels (w >> 1). The taps with 4 - k = s q + p read only the dz rows t = s v + p
+// (v = u + q), so the workgroup stages those rows of one parity p in LDS once, for half of
+// the output channels at a time, and runs the parity's taps on them; each tap's weights
+// for that half ([128 ci][64 co]) are staged too, loaded a tap ahead. The epilogue runs in
+// two 64-row halves through the shared helpers.
 constexpr int kDgradRows = 128;
+constexpr int kDgradPitch = 64 + 8;   // 144 bytes: rows 16 bytes apart modulo the 128-byte bank cycle
 constexpr size_t kDgradLdsBig = size_t(kDecTile) * kRowF * sizeof(float) + size_t(kDecTile) * kRowB * sizeof(uint16_t);
-static_assert(size_t(kDecC) * kRowB * sizeof(uint16_t) <= kDgradLdsBig, "weight tile larger than the epilogue tiles");
+static_assert(size_t(kDgradRows + 2 * kDecH + kDecC) * kDgradPitch * sizeof(uint16_t) <= kDgradLdsBig,
+              "staged rows and weights larger than the epilogue tiles");
+
+// The order of a workgroup's products: parity p, then channel half h, then the taps of p.
+template <int S>
+struct DgradSeq {
+  int p[2 * kDecK], h[2 * kDecK], k[2 * kDecK];
+  constexpr DgradSeq() : p(), h(), k() {
+    int n = 0;
+    for (int pp = 0; pp < S; ++pp)
+      for (int hh = 0; hh < 2; ++hh)
+        for (int kk = 0; kk < kDecK; ++kk)
+          if (((kDecH - kk - pp) % S + S) % S == 0) {
+            p[n] = pp;
+            h[n] = hh;
+            k[n] = kk;
+            ++n;
+          }
+  }
+};
 
 template <int S, int S2>
 __global__ __launch_bounds__(256, 2) void k_conv_dgrad_lds(const uint16_t* __restrict__ dz, int t_out,
@@ -435,8 +457,14 @@ __global__ __launch_bounds__(256, 2) void k_conv_dgrad_lds(const uint16_t* __res
                                                            const uint16_t* __restrict__ a_prev, float leak,
                                                            uint16_t* __restrict__ dz_prev,
                                                            uint16_t* __restrict__ dzp_prev) {
+  constexpr int H = kDecH / S;                 // |q| <= H
+  constexpr int NR = kDgradRows + 2 * H;       // staged rows v = u0 - H ..
+  constexpr int PA = kDgradPitch;
+  constexpr int NA = (NR * 8 + 255) / 256;     // staged 16-byte pieces per thread
+  constexpr DgradSeq<S> seq{};
   extern __shared__ float smem[];
-  uint16_t* wk = reinterpret_cast<uint16_t*>(smem);                        // [128][kRowB]
+  uint16_t* at = reinterpret_cast<uint16_t*>(smem);                        // [NR][PA]
+  uint16_t* wk = at + NR * PA;                                             // [128][PA]
   float* ftile = smem;                                                     // epilogue: [64][kRowF]
   uint16_t* btile = reinterpret_cast<uint16_t*>(smem + kDecTile * kRowF);  // epilogue: [64][kRowB]
   const int b = blockIdx.y, u0 = blockIdx.x * kDgradRows;
@@ -450,44 +478,58 @@ __global__ __launch_bounds__(256, 2) void k_conv_dgrad_lds(const uint16_t* __res
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  uint4 wpre[8];
-  auto load_tap = [&](int k) {
+  // weights of tap k, channel half h: 4 pieces per thread (ci = e >> 3, co = 64 h + 8 (e & 7))
+  uint4 wpre[4];
+  auto load_w = [&](int k, int h) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 4; ++q) {
       const int e = threadIdx.x + 256 * q;
-      wpre[q] = ld16(wd + (int64_t(e >> 4) * kDecK + k) * kDecC + (e & 15) * 8);
+      wpre[q] = ld16(wd + (int64_t(e >> 3) * kDecK + k) * kDecC + 64 * h + (e & 7) * 8);
     }
   };
-  load_tap(0);
+  // dz rows t = S v + p of channel half h (zero outside [0, t_out)); loads unconditional
+  uint4 apre[NA];
+  auto load_a = [&](int p, int h) {
 #pragma unroll
-  for (int k = 0; k < kDecK; ++k) {
-    __syncthreads();   // the previous tap's weights are consumed
+    for (int q = 0; q < NA; ++q) {
+      const int e = min(int(threadIdx.x) + 256 * q, NR * 8 - 1);
+      const int t = S * (u0 - H + (e >> 3)) + p;
+      const bool ok = t >= 0 && t < t_out;
+      const uint4 v = ld16(db + int64_t(ok ? t : 0) * kDecC + 64 * h + (e & 7) * 8);
+      apre[q] = ok ? v : zero;
+    }
+  };
+  load_w(seq.k[0], seq.h[0]);
+  load_a(seq.p[0], seq.h[0]);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+  for (int n = 0; n < 2 * kDecK; ++n) {
+    const int p = seq.p[n], h = seq.h[n], k = seq.k[n];
+    const bool restage = n == 0 || p != seq.p[n - 1] || h != seq.h[n - 1];
+    const bool next_restage = n + 1 < 2 * kDecK && (p != seq.p[n + 1] || h != seq.h[n + 1]);
+    __syncthreads();   // the previous products are done with the staged rows and weights
+    if (restage) {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        if (e < NR * 8) st16(at + (e >> 3) * PA + (e & 7) * 8, apre[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
       const int e = threadIdx.x + 256 * q;
-      st16(wk + (e >> 4) * kRowB + (e & 15) * 8, wpre[q]);
+      st16(wk + (e >> 3) * PA + (e & 7) * 8, wpre[q]);
     }
-    if (k + 1 < kDecK) load_tap(k + 1);
+    if (n + 1 < 2 * kDecK) load_w(seq.k[n + 1], seq.h[n + 1]);
+    if (next_restage) load_a(seq.p[n + 1], seq.h[n + 1]);
     __syncthreads();
-    const uint16_t* arow[4];
-    bool aok[4];
+    const int qs = (kDecH - k - p) / S + H;   // staged row of u = u0 is qs (exact division)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int u = u0 + rw + 16 * i + li;
-      const int t = S * u - k + kDecH;
-      aok[i] = u < t_in && t >= 0 && t < t_out;
-      arow[i] = db + int64_t(aok[i] ? t : 0) * kDecC + 8 * g;
-    }
-#pragma unroll
-    for (int c0 = 0; c0 < kDecC; c0 += 32) {
+    for (int c0 = 0; c0 < 64; c0 += 32) {
       uint4 A[4], Bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint4 v = ld16(arow[i] + c0);   // (unconditional: arow is clamped to a valid row)
-        A[i] = aok[i] ? v : zero;
-      }
+      for (int i = 0; i < 4; ++i) A[i] = ld16(at + (rw + 16 * i + li + qs) * PA + c0 + 8 * g);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) Bv[j] = ld16(wk + (cw + 16 * j + li) * kRowB + c0 + 8 * g);
+      for (int j = 0; j < 4; ++j) Bv[j] = ld16(wk + (cw + 16 * j + li) * PA + c0 + 8 * g);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
