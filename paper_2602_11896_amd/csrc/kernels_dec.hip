@@ -790,7 +790,8 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int n_chunks, int
   const int co = static_cast<int>((i / cip) % kDecC);
   const int k = static_cast<int>(i / (int64_t(cip) * kDecC));
   float acc = 0.f;
-  for (int c = 0; c < n_chunks; ++c) acc += part[c * per + i];
+#pragma unroll 8
+  for (int c = 0; c < n_chunks; ++c) acc += part[c * per + i];   // (loads issue ahead of the in-order adds)
   grad[(int64_t(co) * c_in + ci) * kDecK + k] = acc;
 }
 
