@@ -270,19 +270,6 @@ __global__ __launch_bounds__(256, 2) void k_conv_fwd_lds(const uint16_t* __restr
   const uint16_t* xb = x + int64_t(b) * t_in * kDecC;
   const uint4 zero{0u, 0u, 0u, 0u};
 
-  for (int e = threadIdx.x; e < NRI * 16; e += 256) {
-    const int row = e >> 4, c8 = (e & 15) * 8;
-    const int u = m0 - H + row;
-    st16(xin + row * P + c8, (u >= 0 && u < t_in) ? ld16(xb + int64_t(u) * kDecC + c8) : zero);
-  }
-  f32x4 acc[S][RT][4];
-#pragma unroll
-  for (int r = 0; r < S; ++r)
-#pragma unroll
-    for (int i = 0; i < RT; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[r][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
   // a tap's weights: eight 16-byte pieces per thread, loaded one tap ahead (in flight during
   // the previous tap's products)
   uint4 wpre[8];
@@ -295,6 +282,33 @@ __global__ __launch_bounds__(256, 2) void k_conv_fwd_lds(const uint16_t* __restr
     }
   };
   load_tap(0);
+  {
+    // input rows: every load issued before the first store (addresses clamped to row 0,
+    // values outside [0, t_in) replaced by zeros)
+    constexpr int NX = (NRI * 16 + 255) / 256;
+    uint4 xv[NX];
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      const int e = min(int(threadIdx.x) + 256 * q, NRI * 16 - 1);
+      const int u = m0 - H + (e >> 4);
+      const bool ok = u >= 0 && u < t_in;
+      const uint4 v = ld16(xb + int64_t(ok ? u : 0) * kDecC + (e & 15) * 8);
+      xv[q] = ok ? v : zero;
+    }
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (e < NRI * 16) st16(xin + (e >> 4) * P + (e & 15) * 8, xv[q]);
+    }
+  }
+  f32x4 acc[S][RT][4];
+#pragma unroll
+  for (int r = 0; r < S; ++r)
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[r][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
 #pragma unroll
   for (int k = 0; k < kDecK; ++k) {
     __syncthreads();   // the previous tap's weights are consumed (and, first, the input staged)
@@ -367,13 +381,13 @@ __global__ __launch_bounds__(256, 2) void k_conv_fwd_lds(const uint16_t* __restr
 }
 
 // ---------------------------------------------------------------------------------------
-// Shared epilogue of the data-gradient kernels: a bf16 tile of dz rows u in [u0, u0 + 64)
+// Shared epilogue of the data-gradient kernels: a bf16 tile of dz rows u in [u0, u0 + ROWS)
 // (LDS, pitch kRowB) goes to the polyphase layout of stride S2.
-template <int S2>
+template <int S2, int ROWS = kDecTile>
 __device__ void store_polyphase(const uint16_t* tile, int b, int u0, int t_rows, uint16_t* __restrict__ dzp) {
   const int M2 = t_rows / S2;
   const int64_t row_len = M2 + 2 * kDecPad;
-  constexpr int n8 = kDecTile / S2 / 8;
+  constexpr int n8 = ROWS / S2 / 8;
   const int m20 = u0 / S2;
   for (int i = threadIdx.x; i < kDecC * S2 * n8; i += 256) {
     const int ci = i / (S2 * n8), rem = i % (S2 * n8), r2 = rem / n8, ch = rem % n8;
@@ -389,7 +403,7 @@ __device__ void store_polyphase(const uint16_t* tile, int b, int u0, int t_rows,
   }
   if (u0 == 0)
     for (int i = threadIdx.x; i < kDecC * S2; i += 256) st16(dzp + (int64_t(b) * kDecC * S2 + i) * row_len, uint4{0, 0, 0, 0});
-  if (u0 + kDecTile >= t_rows)
+  if (u0 + ROWS >= t_rows)
     for (int i = threadIdx.x; i < kDecC * S2; i += 256)
       st16(dzp + (int64_t(b) * kDecC * S2 + i) * row_len + kDecPad + M2, uint4{0, 0, 0, 0});
 }
@@ -908,35 +922,58 @@ __global__ __launch_bounds__(512) void k_out_fwd(const uint16_t* __restrict__ xc
 }
 
 // dz of the last hidden layer: da[u, ci] = sum_k w[ci][k] dy[u - k + 4], masked.
+// Output layer data gradient: dz[u, c] = lrelu'(a[u, c]) * sum_k w[c][k] dy[u - k + 4], written
+// TC and in the polyphase layout of the last hidden layer's stride S2. Workgroup: 128 rows
+// u of one signal; thread: channels 8 (tid & 15) .. + 8 (their 72 weights in registers) of
+// rows (tid >> 4) + 16 j, each row's 8 values packed to bf16 in one 16-byte store.
+constexpr int kOutRows = 128;
 template <int S2>
 __global__ __launch_bounds__(256) void k_out_dgrad(const float* __restrict__ dy, int T, const float* __restrict__ wo,
                                                    const uint16_t* __restrict__ a_tc, float leak,
                                                    uint16_t* __restrict__ dz_tc, uint16_t* __restrict__ dzp) {
-  extern __shared__ float smem[];
-  float* ftile = smem;                                                     // [64][kRowF]
-  uint16_t* btile = reinterpret_cast<uint16_t*>(smem + kDecTile * kRowF);  // [64][kRowB]
-  __shared__ float dys[kDecTile + 8];
-  const int b = blockIdx.y, u0 = blockIdx.x * kDecTile;
-  for (int i = threadIdx.x; i < kDecTile + 8; i += 256) {
+  __shared__ uint16_t btile[kOutRows * kRowB];
+  __shared__ float dys[kOutRows + 2 * kDecH];
+  const int b = blockIdx.y, u0 = blockIdx.x * kOutRows;
+  for (int i = threadIdx.x; i < kOutRows + 2 * kDecH; i += 256) {
     const int t = u0 - kDecH + i;
     dys[i] = (t >= 0 && t < T) ? dy[int64_t(b) * T + t] : 0.f;
   }
+  const int c8 = (threadIdx.x & 15) * 8;
+  float wk[8][kDecK];
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+#pragma unroll
+    for (int k = 0; k < kDecK; ++k) wk[e][k] = wo[(c8 + e) * kDecK + k];
   __syncthreads();
-  // thread: channel ci = tid & 127, rows (tid >> 7) + 2 j
-  const int ci = threadIdx.x & (kDecC - 1);
-  float wk[kDecK];
+#pragma unroll 2
+  for (int row = threadIdx.x >> 4; row < kOutRows; row += 16) {
+    const int u = u0 + row;
+    if (u >= T) break;
+    float d[kDecK];
 #pragma unroll
-  for (int k = 0; k < kDecK; ++k) wk[k] = wo[ci * kDecK + k];
-  for (int row = threadIdx.x >> 7; row < kDecTile; row += 2) {
-    float acc = 0.f;
+    for (int k = 0; k < kDecK; ++k) d[k] = dys[row - k + 2 * kDecH];
+    const int64_t off = (int64_t(b) * T + u) * kDecC + c8;
+    const uint4 a = ld16(a_tc + off);
+    const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
+    uint32_t o[4];
 #pragma unroll
-    for (int k = 0; k < kDecK; ++k) acc += wk[k] * dys[row - k + 2 * kDecH];
-    ftile[row * kRowF + ci] = acc;
+    for (int e = 0; e < 4; ++e) {
+      float d0 = 0.f, d1 = 0.f;
+#pragma unroll
+      for (int k = 0; k < kDecK; ++k) {
+        d0 += wk[2 * e][k] * d[k];
+        d1 += wk[2 * e + 1][k] * d[k];
+      }
+      const float m0 = bf_lo(aw[e]) > 0.f ? d0 : leak * d0;
+      const float m1 = bf_hi(aw[e]) > 0.f ? d1 : leak * d1;
+      o[e] = uint32_t(f2bf(m0)) | (uint32_t(f2bf(m1)) << 16);
+    }
+    const uint4 v{o[0], o[1], o[2], o[3]};
+    st16(dz_tc + off, v);
+    st16(btile + row * kRowB + c8, v);
   }
   __syncthreads();
-  mask_store_tc(ftile, btile, b, u0, T, a_tc, leak, dz_tc);
-  __syncthreads();
-  store_polyphase<S2>(btile, b, u0, T, dzp);
+  store_polyphase<S2, kOutRows>(btile, b, u0, T, dzp);
 }
 
 // Partials of dW_out[ci][k] = sum_t dy[t] x[ci][t + k - 4] over 2048-sample chunks.
@@ -1059,7 +1096,6 @@ hipError_t launch_fwd(const uint16_t* x_tc, int cip, int t_in, int batch, const 
   return hipGetLastError();
 }
 
-constexpr size_t kDgradLds = kDgradLdsBig;
 
 template <int S, int S2>
 hipError_t launch_dgrad(const uint16_t* dz, int t_out, const uint16_t* wd, int t_in, int batch, const uint16_t* a_prev,
@@ -1130,11 +1166,11 @@ hipError_t run_dec_out_fwd(const uint16_t* x_ct, int T, int batch, const float* 
 hipError_t run_dec_out_bwd(const float* dy, int T, int batch, const float* wout, const uint16_t* a_tc,
                            const uint16_t* a_ct, float leak, int s2, uint16_t* dz_tc, uint16_t* dzp, float* part,
                            float* grad_w, float* grad_b, hipStream_t st) {
-  const dim3 grid(blocks_for(T, kDecTile), batch);
+  const dim3 grid(blocks_for(T, kOutRows), batch);
   switch (s2) {
-    case 1: hipLaunchKernelGGL(k_out_dgrad<1>, grid, dim3(256), kDgradLds, st, dy, T, wout, a_tc, leak, dz_tc, dzp); break;
-    case 2: hipLaunchKernelGGL(k_out_dgrad<2>, grid, dim3(256), kDgradLds, st, dy, T, wout, a_tc, leak, dz_tc, dzp); break;
-    case 4: hipLaunchKernelGGL(k_out_dgrad<4>, grid, dim3(256), kDgradLds, st, dy, T, wout, a_tc, leak, dz_tc, dzp); break;
+    case 1: hipLaunchKernelGGL(k_out_dgrad<1>, grid, dim3(256), 0, st, dy, T, wout, a_tc, leak, dz_tc, dzp); break;
+    case 2: hipLaunchKernelGGL(k_out_dgrad<2>, grid, dim3(256), 0, st, dy, T, wout, a_tc, leak, dz_tc, dzp); break;
+    case 4: hipLaunchKernelGGL(k_out_dgrad<4>, grid, dim3(256), 0, st, dy, T, wout, a_tc, leak, dz_tc, dzp); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
