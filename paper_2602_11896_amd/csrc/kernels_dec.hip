@@ -573,6 +573,8 @@ __global__ __launch_bounds__(256, 2) void k_conv_dgrad_lds(const uint16_t* __res
 //   dW[co, ci, KT] = sum_b sum_m dz_P[b, co, r, m] x[b, ci, m - q],  4 - KT = s q + r, 0 <= r < s.
 // Workgroup: one chunk of (b, m) (blockIdx.x), 64 input channels (blockIdx.y); all 128 output
 // channels, wave w owning rows [32 w, 32 w + 32). Partials [chunk][9][128][cip], summed later.
+// Launched at stride 1 (the first layer, whose 266 input channels are padded to 320); strides
+// 2 and 4 use the row-wise kernel below, which shares the dz rows between taps.
 template <int S, int KT>
 __device__ void wgrad_tap(const uint16_t* __restrict__ dzp, const uint16_t* __restrict__ xct, int M, int cip, int b,
                           int m_begin, int m_end, int ci0, float* __restrict__ part) {
