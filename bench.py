@@ -209,6 +209,40 @@ def config4_part(n_signals: int) -> dict:
     return out
 
 
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+
+
+def decoder_bound_ms(layer_shapes, n_frames: int, batch: int) -> float:
+    """Sum over the decoder's kernels of the larger of their compute time at the peak and
+    their HBM time at 8 TB/s, for one forward + backward. Bytes are the tensors each kernel
+    must move in this layout, each read or written once: a hidden layer's forward reads its
+    time-major input and writes its output time-major and channel-major; its data gradient
+    reads dz (time-major) and the previous activation and writes the previous dz
+    time-major and polyphase; its weight gradient reads dz (polyphase) and its
+    channel-major input. The one-channel output layer runs in FP32 vector arithmetic."""
+    t, total = n_frames, 0.0
+    n = len(layer_shapes)
+    for i, (co, ci, s) in enumerate(layer_shapes):
+        t_in, t_out = t, t * s
+        if i < n - 1:
+            flop = 2.0 * 9 * ci * co * t_in * batch
+            parts = [(flop, batch * (2 * t_in * ci + 2 * 2 * t_out * co))]                      # forward
+            if i > 0:
+                parts.append((flop, batch * (2 * t_out * co + 2 * t_in * ci + 2 * 2 * t_in * ci)))  # data gradient
+            parts.append((flop, batch * (2 * t_out * co + 2 * t_in * ci)))                       # weight gradient
+            peak = PEAK_BF16_MFMA_TFLOPS
+        else:
+            flop = 2.0 * 9 * ci * t_in * batch
+            parts = [(flop, batch * (2 * t_in * ci + 4 * t_in)),                 # forward
+                     (flop, batch * (4 * t_in + 2 * t_in * ci + 2 * 2 * t_in * ci)),  # data gradient
+                     (flop, batch * (2 * t_in * ci + 4 * t_in))]                 # weight gradient
+            peak = PEAK_FP32_VECTOR_TFLOPS
+        for f, by in parts:
+            total += max(f / (peak * 1e12), by / (PEAK_HBM_GBS * 1e9))
+        t = t_out
+    return total * 1e3
+
+
 def decoder_part(batch: int = 16, reps: int = 10) -> dict:
     """Decoder forward + backward (weights and data gradients) at the trained shape, batch 16,
     against the dense BF16 MFMA peak. Algorithmic work: per layer 9 C_in C_out MACs per
@@ -248,9 +282,11 @@ def decoder_part(batch: int = 16, reps: int = 10) -> dict:
         T *= s
     flops = 2.0 * macs * batch
     tf = flops / (ms * 1e-3) / 1e12
+    bound = decoder_bound_ms(cfg.layer_shapes(), cfg.n_frames, batch)
     return {"batch": batch, "ms_fwd_bwd": round(ms, 3), "algorithmic_gflop": round(flops / 1e9, 1),
             "achieved": round(tf, 2), "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(tf / PEAK_BF16_MFMA_TFLOPS, 4)}
+            "frac": round(tf / PEAK_BF16_MFMA_TFLOPS, 4),
+            "bound_ms": round(bound, 3), "frac_of_bound": round(bound / ms, 4)}
 
 
 def effective_tuning(t) -> dict:

@@ -69,3 +69,20 @@ def test_default_run_uses_the_recorded_schedules():
     """A default bench run (library schedules) reports counted traffic: the committed record
     was taken with exactly those schedules."""
     assert bench.effective_tuning(None) == _record()["tuning"]
+
+
+def test_decoder_bound_hand_cases():
+    """The decoder's combined bound against sums worked by hand: a 4-channel first layer
+    (every kernel HBM-bound) and a stride-1, 128-channel stack (the MFMA term wins where
+    the kernel moves fewer than 312 bytes per 1e5 flops)."""
+    # hidden 4 -> 128 at stride 2 on 8 frames, output layer on 16 samples, batch 1:
+    # bytes 8256 (forward), 4160 (weight gradient); output 4160, 12352, 4160; all at 8 TB/s
+    got = bench.decoder_bound_ms([(128, 4, 2), (1, 128, 1)], 8, 1)
+    assert abs(got - 33088 / 8e12 * 1e3) < 1e-15
+    # two 128 -> 128 stride-1 layers on 8 frames, batch 2: forward and weight gradient of
+    # both at 4 718 592 flops and 2.5 PFLOP/s (1.8874368 ns each); the second layer's data
+    # gradient moves 16 384 bytes (2.048 ns; the first layer has none); output layer
+    # 0.52 + 1.544 + 0.52 ns
+    got = bench.decoder_bound_ms([(128, 128, 1), (128, 128, 1), (1, 128, 1)], 8, 2)
+    expect = (4 * 1.8874368e-9 + 2.048e-9 + 0.52e-9 + 1.544e-9 + 0.52e-9) * 1e3
+    assert abs(got - expect) < 1e-9 * expect
