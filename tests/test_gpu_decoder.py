@@ -227,6 +227,33 @@ def test_decoder_config4_linear_gradient():
     check_layers(ocfg, host(g), OD.backward(ocfg, theta, cache, dy, quantize=True), TOL_G)
 
 
+def test_decoder_gradient_independent_of_chunking():
+    """Full-size decoder: the weight-gradient chunk length depends on the batch (shorter
+    chunks when the launch would not fill the GPU), so a batch-4 backward and the sum of
+    four batch-1 backwards add the same products in different groupings. The waveforms
+    are the same bits (no sum spans signals); the gradients agree to FP32 summation
+    order (relative 1e-5 per parameter block)."""
+    say("decoder config-4 shape: batch 4 against 4 x batch 1")
+    cfg, ocfg = configs([1, 4, 4, 4, 2, 2, 2, 1], 266, 128)
+    rng = np.random.default_rng(52)
+    theta = params_for(cfg, 9)
+    B = 4
+    S = coeffs(rng, B * 266 * 128)
+    dec = Decoder(cfg, max_batch=B)
+    ws = dec.workspace()
+    p = dev(theta)
+    dy = rng.normal(size=B * dec.out_len)
+    y4 = host(dec.forward(p, dev(S), B, ws=ws))
+    g4 = host(dec.backward(p, dev(dy), B, ws))
+    g1 = np.zeros_like(g4)
+    n_s, n_y = 266 * 128, dec.out_len
+    for b in range(B):
+        y1 = host(dec.forward(p, dev(S[b * n_s:(b + 1) * n_s]), 1, ws=ws))
+        assert np.array_equal(y1, y4[b * n_y:(b + 1) * n_y]), b
+        g1 += host(dec.backward(p, dev(dy[b * n_y:(b + 1) * n_y]), 1, ws))
+    check_layers(ocfg, g4, g1, 1e-5)
+
+
 def test_decoder_adam_matches_oracle():
     cfg, _ = configs([2, 1], 5, 8)
     dec = Decoder(cfg, 1)
